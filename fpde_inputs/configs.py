@@ -106,7 +106,8 @@ def square(n: int = 128, pad: int | None = None, jitter: float = 0.1, nrhs: int 
         pad = n // 2
     m = square_mesh(n, pad, jitter=jitter, seed=0)
     x1, x2 = m.coords
-    s = (0.3 + 0.2 * (x1 + x2))[None, :]
+    # range [0.1, 0.9] on (-0.5, 1.5)^2; the clip only removes rounding of the grid coordinates
+    s = np.clip(0.3 + 0.2 * (x1 + x2), 0.1, 0.9)[None, :]
     kappa = (1.0 + 0.5 * np.cos(2 * np.pi * x1) * np.cos(2 * np.pi * x2))[None, :]
     rng = np.random.default_rng(1)
     vec = rng.standard_normal((1, m.n_dofs, nrhs))

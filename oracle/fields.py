@@ -41,8 +41,10 @@ def quad_points(mesh, nq: int):
     xh, wh = element_rule(mesh.dim, nq)
     nqe = wh.size
     v0, J, det = cell_geometry(mesh)
-    # x = v0 + J xh
-    x = v0[:, :, None] + np.einsum("dkc,kl->dcl", J, xh)
+    # x = v0 + J xh, evaluated as (v0 + J[:,0] xh0) + J[:,1] xh1
+    x = v0[:, :, None] + J[:, 0, :, None] * xh[0][None, None, :]
+    if mesh.dim == 2:
+        x = x + J[:, 1, :, None] * xh[1][None, None, :]
     nc = mesh.n_cells
     lam = barycentric_ref(mesh.dim, xh)      # (dim+1, nqe)
     return {

@@ -12,11 +12,44 @@ reference simplex.
 """
 from __future__ import annotations
 
+import functools
+
+import mpmath
 import numpy as np
 
 
+@functools.lru_cache(maxsize=None)
+def _legendre_rule(n: int):
+    """Nodes/weights of n-point Gauss-Legendre on [-1,1], correctly rounded to double.
+
+    Roots of P_n by Newton's method in 50-digit arithmetic; w = 2/((1-t^2) P_n'(t)^2).
+    """
+    with mpmath.workdps(50):
+        ts, ws = [], []
+        for i in range(1, n + 1):
+            t = mpmath.cos(mpmath.pi * (i - mpmath.mpf(1) / 4) / (n + mpmath.mpf(1) / 2))
+            for _ in range(100):
+                p0, p1 = mpmath.mpf(1), t
+                for k in range(2, n + 1):
+                    p0, p1 = p1, ((2 * k - 1) * t * p1 - (k - 1) * p0) / k
+                dp = n * (t * p1 - p0) / (t * t - 1) if n > 1 else mpmath.mpf(1)
+                dt = p1 / dp
+                t -= dt
+                if abs(dt) < mpmath.mpf(10) ** -45:
+                    break
+            p0, p1 = mpmath.mpf(1), t
+            for k in range(2, n + 1):
+                p0, p1 = p1, ((2 * k - 1) * t * p1 - (k - 1) * p0) / k
+            dp = n * (t * p1 - p0) / (t * t - 1) if n > 1 else mpmath.mpf(1)
+            ts.append(float(t))
+            ws.append(float(2 / ((1 - t * t) * dp * dp)))
+    order = np.argsort(ts)
+    return np.array(ts)[order], np.array(ws)[order]
+
+
 def gauss01(n: int):
-    t, w = np.polynomial.legendre.leggauss(n)
+    """n-point Gauss-Legendre on [0,1]: xi = (t+1)/2, w = w_t/2 (t, w_t correctly rounded)."""
+    t, w = _legendre_rule(n)
     return 0.5 * (t + 1.0), 0.5 * w
 
 

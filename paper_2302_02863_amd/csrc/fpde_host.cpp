@@ -1,0 +1,961 @@
+// C ABI of libfpde: validation, planning, device orchestration of the build
+// (Alg. 1 of the paper) and of the operator apply / CG solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fpde.h"
+#include "fpde_internal.h"
+#include "fpde_plan.h"
+
+namespace fpde {
+hipError_t launch_basis_n(const H2Tree& t, int64_t N, const int64_t* perm, const int64_t* nc_ptr,
+                          const int64_t* nc_cell, const int8_t* nc_slot, int nqe, const double* qx,
+                          const double* qw, const double* lam, int64_t nq_all, double* U,
+                          hipStream_t st);
+}
+
+using namespace fpde;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+    fpde_status st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(fpde_status st, const std::string& m) { throw Fail{st, m}; }
+
+void hipck(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(FPDE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// device arena: every allocation of an operator is recorded and freed together
+struct Arena {
+    std::vector<void*> ptrs;
+    int64_t bytes = 0;
+    uint64_t limit = 0;
+    template <class T>
+    T* alloc(int64_t n) {
+        if (n <= 0) n = 1;
+        size_t b = sizeof(T) * (size_t)n;
+        if (limit && (uint64_t)(bytes + b) > limit)
+            fail(FPDE_ENOMEM, "device memory above max_device_bytes");
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) fail(FPDE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        ptrs.push_back(p);
+        bytes += b;
+        return (T*)p;
+    }
+    template <class T>
+    T* upload(const std::vector<T>& v, hipStream_t st) {
+        T* p = alloc<T>((int64_t)v.size());
+        if (!v.empty()) hipck(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st), "upload");
+        return p;
+    }
+    void release(void* p) {
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it != ptrs.end()) {
+            hipFree(p);
+            ptrs.erase(it);
+        }
+    }
+    ~Arena() {
+        for (void* p : ptrs) hipFree(p);
+    }
+};
+
+struct TreeDev {
+    int64_t* beg = nullptr;
+    int64_t* end = nullptr;
+    double* axes = nullptr;
+    double* E = nullptr;
+    double* node_s = nullptr;
+    double* node_k = nullptr;
+    int64_t* far_ptr = nullptr;
+    int64_t* far_src = nullptr;
+    int64_t* perm = nullptr;
+};
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct fpde_op {
+    HostMesh mesh;
+    fpde_opts opts{};
+    int F = 1;
+    bool plan_only = false;
+    std::vector<double> s, kappa;   // [F][M]
+    ElementRule er;
+    QuadPoints Q;
+    NodeCells ncs;
+    std::vector<Pair> pairs;        // enumeration order (cell, neighbour)
+    std::vector<int64_t> pair_order;// device order (sorted by kind)
+    // K tree
+    Tree kt;
+    std::vector<std::pair<int64_t, int64_t>> kfar, knear;
+    std::vector<int64_t> pos_of_dof;
+    // density tree
+    Tree rt;
+    std::vector<std::pair<int64_t, int64_t>> rfar, rnear;
+    double hmax = 0.0;
+    // CSR in tree order
+    std::vector<int64_t> csr_ptr;
+    std::vector<int32_t> csr_col;
+    // device
+    Arena arena;
+    hipStream_t stream = nullptr;
+    double* d_X = nullptr;
+    int32_t* d_C = nullptr;
+    uint8_t* d_cint = nullptr;
+    double* d_qw = nullptr;
+    double* d_lam = nullptr;
+    int64_t* d_nc_ptr = nullptr;
+    int64_t* d_nc_cell = nullptr;
+    int8_t* d_nc_slot = nullptr;
+    double* d_B = nullptr;
+    double* d_M = nullptr;
+    double* d_BM = nullptr;
+    double* d_rho = nullptr;       // [F][nq] density at interior points (kept for export)
+    int64_t* d_csr_ptr = nullptr;
+    int32_t* d_csr_col = nullptr;
+    TreeDev kdev;
+    int64_t* d_leaf_beg = nullptr;
+    int64_t* d_near_ptr = nullptr;
+    int64_t* d_near_src = nullptr;
+    double* d_near = nullptr;
+    double* d_U = nullptr;
+    int64_t cap = 0;
+    // apply workspace
+    int64_t ws_R = 0;
+    double* d_xt = nullptr;
+    double* d_xh = nullptr;
+    double* d_yh = nullptr;
+    // solve workspace
+    int64_t sw_n = 0;
+    double *d_r = nullptr, *d_p = nullptr, *d_Ap = nullptr, *d_red = nullptr;
+    fpde_stats_t stats{};
+};
+
+// ------------------------------------------------------------------ helpers
+
+namespace {
+
+void validate(const fpde_mesh* m, int F, const double* s, const double* kap, const fpde_opts& o) {
+    if (!m) fail(FPDE_EINVAL, "mesh is NULL");
+    if (m->dim != 1 && m->dim != 2) fail(FPDE_EINVAL, "dim must be 1 or 2");
+    if (m->n_nodes <= 0 || m->n_cells <= 0) fail(FPDE_EINVAL, "empty mesh");
+    if (m->n_dofs <= 0 || m->n_dofs >= m->n_nodes) fail(FPDE_EINVAL, "need 0 < n_dofs < n_nodes");
+    if (!m->coords || !m->cells || !m->cell_interior) fail(FPDE_EINVAL, "NULL mesh array");
+    if (F < 1) fail(FPDE_EINVAL, "n_fields must be >= 1");
+    if (!s || !kap) fail(FPDE_EINVAL, "NULL s or kappa");
+    if (!(o.s_bar < 1.0) || !(o.s_bar >= 0.0)) fail(FPDE_EDOMAIN, "s_bar must lie in [0,1)");
+    if (o.cheb_p < 1 || o.cheb_p > kMaxP) fail(FPDE_EINVAL, "cheb_p must be in [1,8]");
+    if (o.nq_sing < 1 || o.nq_sing > kMaxNq || o.nq_reg < 1 || o.nq_reg > kMaxNq)
+        fail(FPDE_EINVAL, "nq_sing/nq_reg must be in [1,8]");
+    if (o.leaf_size < 1 || o.leaf_size > 256 || o.leaf_size_rho < 1 || o.leaf_size_rho > 64)
+        fail(FPDE_EINVAL, "leaf_size in [1,256], leaf_size_rho in [1,64]");
+    if (!(o.eta > 0.0)) fail(FPDE_EINVAL, "eta must be > 0");
+    if (!(o.a_scale > 0.0)) fail(FPDE_EDOMAIN, "a_scale must be > 0");
+    if (m->exterior_radius < 0.0) fail(FPDE_EINVAL, "exterior_radius < 0");
+    if (m->exterior_radius > 0.0 && (o.n_theta < 1 || !(o.kappa_exterior > 0.0) ||
+                                     !(o.s_exterior >= 0.0 && o.s_exterior < 1.0)))
+        fail(FPDE_EDOMAIN, "exterior parameters out of range");
+    const int64_t M = m->n_nodes;
+    for (int64_t i = 0; i < (int64_t)F * M; ++i) {
+        if (!(s[i] >= 0.0 && s[i] <= o.s_bar)) fail(FPDE_EDOMAIN, "s outside [0, s_bar]");
+        if (!(kap[i] > 0.0)) fail(FPDE_EDOMAIN, "kappa must be > 0");
+    }
+    const int k = m->dim + 1;
+    bool has_ext = false;
+    std::vector<uint8_t> on_int(M, 0), on_ext(M, 0);
+    for (int64_t c = 0; c < m->n_cells; ++c) {
+        for (int a = 0; a < k; ++a) {
+            int32_t v = m->cells[a * m->n_cells + c];
+            if (v < 0 || v >= M) fail(FPDE_EINVAL, "cell vertex out of range");
+            (m->cell_interior[c] ? on_int : on_ext)[v] = 1;
+            for (int b = 0; b < a; ++b)
+                if (m->cells[b * m->n_cells + c] == v) fail(FPDE_EINVAL, "degenerate cell (repeated vertex)");
+        }
+        if (!m->cell_interior[c]) has_ext = true;
+    }
+    for (int64_t v = 0; v < m->n_dofs; ++v)
+        if (on_ext[v]) fail(FPDE_EINVAL, "an interior node belongs to an exterior cell");
+    if (!has_ext && !(m->exterior_radius > 0.0))
+        fail(FPDE_EINVAL, "the exterior region is empty (|Omega_e| = 0) and exterior_radius = 0");
+}
+
+H2Tree make_h2(const Tree& t, const TreeDev& d, int p) {
+    H2Tree h{};
+    h.dim = t.dim;
+    h.p = p;
+    h.k = t.dim == 2 ? p * p : p;
+    h.L = t.L;
+    h.ncl = t.ncl;
+    h.nleaf = t.nleaf();
+    h.first_leaf = t.first_leaf();
+    h.beg = d.beg;
+    h.end = d.end;
+    h.axes = d.axes;
+    h.E = d.E;
+    h.node_s = d.node_s;
+    h.node_k = d.node_k;
+    h.far_ptr = d.far_ptr;
+    h.far_src = d.far_src;
+    return h;
+}
+
+// Chebyshev axes of every cluster and P1 values of s, sqrt(kappa) at the nodes
+void cluster_nodes(const fpde_op& op, const Tree& t, const Locator& loc, std::vector<double>& axes,
+                   std::vector<double>& ns, std::vector<double>& nk) {
+    const int d = t.dim, p = op.opts.cheb_p, k = d == 2 ? p * p : p;
+    axes.assign(t.ncl * d * p, 0.0);
+    ns.assign((int64_t)op.F * t.ncl * k, 0.0);
+    nk.assign((int64_t)op.F * t.ncl * k, 0.0);
+    const int64_t M = op.mesh.M;
+    for (int64_t c = 0; c < t.ncl; ++c) {
+        double* ax = &axes[c * d * p];
+        cheb_axes(d, &t.lo[c * d], &t.hi[c * d], p, ax);
+        for (int al = 0; al < k; ++al) {
+            double x[2] = {ax[al % p], d == 2 ? ax[p + al / p] : 0.0};
+            double lam[3];
+            int64_t node = -1;
+            int64_t cell = loc.locate(x, lam, &node);
+            for (int f = 0; f < op.F; ++f) {
+                const double* sf = &op.s[(int64_t)f * M];
+                const double* kf = &op.kappa[(int64_t)f * M];
+                double sv, kv;
+                if (cell < 0) {
+                    sv = sf[node];
+                    kv = kf[node];
+                } else if (d == 1) {
+                    sv = sf[op.mesh.v(0, cell)] * lam[0] + sf[op.mesh.v(1, cell)] * lam[1];
+                    kv = kf[op.mesh.v(0, cell)] * lam[0] + kf[op.mesh.v(1, cell)] * lam[1];
+                } else {
+                    sv = (sf[op.mesh.v(0, cell)] * lam[0] + sf[op.mesh.v(1, cell)] * lam[1]) +
+                         sf[op.mesh.v(2, cell)] * lam[2];
+                    kv = (kf[op.mesh.v(0, cell)] * lam[0] + kf[op.mesh.v(1, cell)] * lam[1]) +
+                         kf[op.mesh.v(2, cell)] * lam[2];
+                }
+                ns[((int64_t)f * t.ncl + c) * k + al] = sv;
+                nk[((int64_t)f * t.ncl + c) * k + al] = std::sqrt(kv);
+            }
+        }
+    }
+}
+
+void far_csr(const Tree& t, const std::vector<std::pair<int64_t, int64_t>>& far,
+             std::vector<int64_t>& ptr, std::vector<int64_t>& src) {
+    ptr.assign(t.ncl + 1, 0);
+    for (auto& pr : far) ptr[pr.first + 1]++;
+    for (int64_t c = 0; c < t.ncl; ++c) ptr[c + 1] += ptr[c];
+    src.resize(far.size());
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    for (auto& pr : far) src[fill[pr.first]++] = pr.second;
+}
+
+// ------------------------------------------------------------------ planning
+
+void plan(fpde_op& op) {
+    auto t0 = std::chrono::steady_clock::now();
+    const HostMesh& m = op.mesh;
+    const int d = m.dim;
+    op.er = element_rule(d, op.opts.nq_reg);
+    op.Q = quad_points(m, op.er);
+    op.ncs = node_cells(m);
+    op.pairs = touching_pairs(m, op.ncs);
+    op.hmax = h_max(m);
+    // device order of pairs: by kind (uniform waves)
+    op.pair_order.resize(op.pairs.size());
+    std::iota(op.pair_order.begin(), op.pair_order.end(), 0);
+    std::stable_sort(op.pair_order.begin(), op.pair_order.end(),
+                     [&](int64_t a, int64_t b) { return op.pairs[a].kind < op.pairs[b].kind; });
+    // K tree over the dofs, extended boxes (supports of the members' basis functions)
+    op.kt = kd_tree(d, m.X.data(), m.M, m.N, op.opts.leaf_size);
+    Tree& kt = op.kt;
+    kt.lo.assign(kt.ncl * d, 1e300);
+    kt.hi.assign(kt.ncl * d, -1e300);
+    for (int64_t c = kt.first_leaf(); c < kt.ncl; ++c)
+        for (int64_t j = kt.beg[c]; j < kt.end[c]; ++j) {
+            int64_t v = kt.perm[j];
+            for (int64_t e = op.ncs.ptr[v]; e < op.ncs.ptr[v + 1]; ++e) {
+                int64_t cell = op.ncs.cell[e];
+                for (int a = 0; a <= d; ++a)
+                    for (int kk = 0; kk < d; ++kk) {
+                        double x = m.x(kk, m.v(a, cell));
+                        kt.lo[c * d + kk] = std::min(kt.lo[c * d + kk], x);
+                        kt.hi[c * d + kk] = std::max(kt.hi[c * d + kk], x);
+                    }
+            }
+        }
+    for (int64_t c = kt.first_leaf() - 1; c >= 0; --c)
+        for (int kk = 0; kk < d; ++kk) {
+            kt.lo[c * d + kk] = std::min(kt.lo[(2 * c + 1) * d + kk], kt.lo[(2 * c + 2) * d + kk]);
+            kt.hi[c * d + kk] = std::max(kt.hi[(2 * c + 1) * d + kk], kt.hi[(2 * c + 2) * d + kk]);
+        }
+    partition(kt, op.opts.eta, 0.0, nullptr, op.kfar, op.knear);
+    op.pos_of_dof.assign(m.N, -1);
+    for (int64_t j = 0; j < m.N; ++j) op.pos_of_dof[kt.perm[j]] = j;
+    // density tree over all quadrature points; prune targets without interior points
+    op.rt = kd_tree(d, op.Q.x.data(), op.Q.nq, op.Q.nq, op.opts.leaf_size_rho);
+    point_boxes(op.rt, op.Q.x.data(), op.Q.nq);
+    std::vector<uint8_t> skip(op.rt.ncl, 1);
+    for (int64_t c = 0; c < op.rt.ncl; ++c)
+        for (int64_t j = op.rt.beg[c]; j < op.rt.end[c]; ++j)
+            if (op.Q.q_int[op.rt.perm[j]]) {
+                skip[c] = 0;
+                break;
+            }
+    partition(op.rt, op.opts.eta, 2.0 * op.hmax, &skip, op.rfar, op.rnear);
+    // CSR pattern of B (and M) in tree order
+    std::vector<std::tuple<int64_t, int64_t>> ent;
+    int32_t dofs[5];
+    for (const Pair& p : op.pairs) {
+        int nd = pair_dofs(m, p, dofs);
+        for (int a = 0; a < nd; ++a) {
+            if (dofs[a] >= m.N) continue;
+            for (int b = 0; b < nd; ++b)
+                if (dofs[b] < m.N) ent.emplace_back(op.pos_of_dof[dofs[a]], op.pos_of_dof[dofs[b]]);
+        }
+    }
+    std::sort(ent.begin(), ent.end());
+    ent.erase(std::unique(ent.begin(), ent.end()), ent.end());
+    op.csr_ptr.assign(m.N + 1, 0);
+    op.csr_col.resize(ent.size());
+    for (size_t e = 0; e < ent.size(); ++e) {
+        op.csr_ptr[std::get<0>(ent[e]) + 1]++;
+        op.csr_col[e] = (int32_t)std::get<1>(ent[e]);
+    }
+    for (int64_t i = 0; i < m.N; ++i) op.csr_ptr[i + 1] += op.csr_ptr[i];
+    op.stats.t_plan_ms = ms_since(t0);
+}
+
+int64_t csr_slot(const fpde_op& op, int64_t row, int64_t col) {
+    auto b = op.csr_col.begin() + op.csr_ptr[row], e = op.csr_col.begin() + op.csr_ptr[row + 1];
+    auto it = std::lower_bound(b, e, (int32_t)col);
+    if (it == e || *it != col) fail(FPDE_EINVAL, "internal: CSR slot missing");
+    return it - op.csr_col.begin();
+}
+
+// contributions (slot, source index) sorted by slot -> ptr/idx
+void contrib_csr(int64_t nslots, std::vector<std::pair<int64_t, int64_t>>& c, std::vector<int64_t>& ptr,
+                 std::vector<int64_t>& idx) {
+    std::sort(c.begin(), c.end());
+    ptr.assign(nslots + 1, 0);
+    idx.resize(c.size());
+    for (size_t e = 0; e < c.size(); ++e) {
+        ptr[c[e].first + 1]++;
+        idx[e] = c[e].second;
+    }
+    for (int64_t i = 0; i < nslots; ++i) ptr[i + 1] += ptr[i];
+}
+
+// ------------------------------------------------------------------ device build
+
+struct Timer {
+    hipEvent_t a, b;
+    hipStream_t st;
+    explicit Timer(hipStream_t s) : st(s) {
+        hipEventCreate(&a);
+        hipEventCreate(&b);
+        hipEventRecord(a, st);
+    }
+    double stop() {
+        hipEventRecord(b, st);
+        hipEventSynchronize(b);
+        float ms = 0;
+        hipEventElapsedTime(&ms, a, b);
+        hipEventDestroy(a);
+        hipEventDestroy(b);
+        return ms;
+    }
+};
+
+void build_device(fpde_op& op) {
+    const HostMesh& m = op.mesh;
+    const int d = m.dim, F = op.F, p = op.opts.cheb_p, k = d == 2 ? p * p : p;
+    Arena& A = op.arena;
+    A.limit = op.opts.max_device_bytes;
+    hipStream_t st = op.stream;
+    const int64_t nq = op.Q.nq;
+    const int nqe = op.Q.nqe;
+    auto t_all = std::chrono::steady_clock::now();
+
+    // ---- uploads
+    op.d_X = A.upload(m.X, st);
+    op.d_C = A.upload(m.C, st);
+    op.d_cint = A.upload(m.interior, st);
+    double* d_s = A.upload(op.s, st);
+    double* d_k = A.upload(op.kappa, st);
+    double* d_qx = A.upload(op.Q.x, st);
+    op.d_qw = A.upload(op.Q.w, st);
+    uint8_t* d_qint = A.upload(op.Q.q_int, st);
+    op.d_lam = A.upload(op.er.lam, st);
+    op.d_nc_ptr = A.upload(op.ncs.ptr, st);
+    op.d_nc_cell = A.upload(op.ncs.cell, st);
+    op.d_nc_slot = A.upload(op.ncs.slot, st);
+    double* d_qs = A.alloc<double>((int64_t)F * nq);
+    double* d_qk = A.alloc<double>((int64_t)F * nq);
+    hipck(launch_quad_fields(d, m.nc, nqe, op.d_C, op.d_lam, F, m.M, d_s, d_k, d_qs, d_qk, st), "quad_fields");
+    const int64_t nnz = (int64_t)op.csr_col.size();
+    op.d_csr_ptr = A.upload(op.csr_ptr, st);
+    op.d_csr_col = A.upload(op.csr_col, st);
+
+    // ---- singular near field B (Sec. 4)
+    {
+        Timer tm(st);
+        const int64_t np = (int64_t)op.pairs.size();
+        std::vector<int32_t> prow(np * 8, 0);
+        std::vector<std::pair<int64_t, int64_t>> contrib;
+        int32_t dofs[5];
+        for (int64_t gp = 0; gp < np; ++gp) {
+            const Pair& pr = op.pairs[op.pair_order[gp]];
+            prow[gp * 8] = pr.kind;
+            for (int a = 0; a < 6; ++a) prow[gp * 8 + 1 + a] = pr.v[a];
+            if (d == 1) {   // 1D rows: cell0 (v0, v1), cell1 (v3, v4) -> layout slots 1,2 and 4,5
+                prow[gp * 8 + 1] = pr.v[0];
+                prow[gp * 8 + 2] = pr.v[1];
+                prow[gp * 8 + 4] = pr.v[3];
+                prow[gp * 8 + 5] = pr.v[4];
+            }
+            int nd = pair_dofs(m, pr, dofs);
+            for (int a = 0; a < nd; ++a) {
+                if (dofs[a] >= m.N) continue;
+                for (int b = 0; b < nd; ++b) {
+                    if (dofs[b] >= m.N) continue;
+                    int lo = std::min(a, b), hi = std::max(a, b);
+                    contrib.push_back({csr_slot(op, op.pos_of_dof[dofs[a]], op.pos_of_dof[dofs[b]]), gp * 25 + lo * 5 + hi});
+                }
+            }
+        }
+        std::vector<double> g(op.opts.nq_sing), w(op.opts.nq_sing);
+        gauss_legendre01(op.opts.nq_sing, g.data(), w.data());
+        double* d_g = A.upload(g, st);
+        double* d_w = A.upload(w, st);
+        int32_t* d_pairs = A.upload(prow, st);
+        double* d_loc = A.alloc<double>((int64_t)F * np * 25);
+        hipck(hipMemsetAsync(d_loc, 0, sizeof(double) * F * np * 25, st), "memset");
+        hipck(launch_singular(d, np, d_pairs, op.d_X, m.M, F, d_s, d_k, op.opts.a_scale, op.opts.s_bar,
+                              op.opts.nq_sing, d_g, d_w, d_loc, st), "singular");
+        std::vector<int64_t> cptr, cidx;
+        contrib_csr(nnz, contrib, cptr, cidx);
+        int64_t* d_cptr = A.upload(cptr, st);
+        int64_t* d_cidx = A.upload(cidx, st);
+        op.d_B = A.alloc<double>((int64_t)F * nnz);
+        hipck(launch_segsum(nnz, d_cptr, d_cidx, nullptr, F, d_loc, np * 25, op.d_B, st), "segsum B");
+        hipck(hipStreamSynchronize(st), "singular sync");
+        A.release(d_loc); A.release(d_cptr); A.release(d_cidx); A.release(d_pairs);
+        op.stats.t_singular_ms = tm.stop();
+    }
+
+    // ---- density rho at every interior quadrature point (Sec. 6.2) and M (Sec. 6.1)
+    {
+        Timer tm(st);
+        const Tree& rt = op.rt;
+        Locator loc;
+        loc.build(m);
+        std::vector<double> axes, ns, nk;
+        cluster_nodes(op, rt, loc, axes, ns, nk);
+        std::vector<int64_t> fptr, fsrc, nptr, nsrc;
+        far_csr(rt, op.rfar, fptr, fsrc);
+        // near by leaf index
+        nptr.assign(rt.nleaf() + 1, 0);
+        for (auto& pr : op.rnear) nptr[pr.first - rt.first_leaf() + 1]++;
+        for (int64_t i = 0; i < rt.nleaf(); ++i) nptr[i + 1] += nptr[i];
+        nsrc.resize(op.rnear.size());
+        for (size_t e = 0; e < op.rnear.size(); ++e) nsrc[e] = op.rnear[e].second;
+        TreeDev td;
+        td.beg = A.upload(rt.beg, st);
+        td.end = A.upload(rt.end, st);
+        td.perm = A.upload(rt.perm, st);
+        td.axes = A.upload(axes, st);
+        td.node_s = A.upload(ns, st);
+        td.node_k = A.upload(nk, st);
+        td.far_ptr = A.upload(fptr, st);
+        td.far_src = A.upload(fsrc, st);
+        td.E = A.alloc<double>(rt.ncl * d * p * p);
+        int64_t* d_nptr = A.upload(nptr, st);
+        int64_t* d_nsrc = A.upload(nsrc, st);
+        H2Tree h = make_h2(rt, td, p);
+        hipck(launch_transfer(h, td.E, st), "transfer rho");
+        double* xh = A.alloc<double>((int64_t)F * rt.ncl * k);
+        double* yh = A.alloc<double>((int64_t)F * rt.ncl * k);
+        op.d_rho = A.alloc<double>((int64_t)F * nq);
+        hipck(hipMemsetAsync(op.d_rho, 0, sizeof(double) * F * nq, st), "memset rho");
+        hipck(launch_rho_moments(h, td.perm, d_qx, op.d_qw, nq, F, xh, st), "rho moments");
+        for (int lev = rt.L - 1; lev >= 0; --lev) hipck(launch_up_level(h, lev, F, 1, xh, st), "rho up");
+        hipck(launch_coupling(h, F, 1, 1.0, op.opts.a_scale, xh, yh, st), "rho coupling");
+        for (int lev = 0; lev < rt.L; ++lev) hipck(launch_down_level(h, lev, F, 1, yh, st), "rho down");
+        hipck(launch_rho_eval(h, td.perm, d_qx, d_qint, nq, F, yh, op.d_rho, st), "rho eval");
+        hipck(launch_rho_near(h, td.perm, d_nptr, d_nsrc, d_qx, op.d_qw, d_qs, d_qk, d_qint, nqe, op.d_C, m.nc,
+                              nq, F, op.opts.a_scale, op.d_rho, st), "rho near");
+        if (m.R > 0.0)
+            hipck(launch_rho_exterior(d, nq, d_qx, d_qs, d_qk, d_qint, F, m.R, op.opts.s_exterior,
+                                      std::sqrt(op.opts.kappa_exterior), op.opts.a_scale, op.opts.n_theta,
+                                      op.d_rho, st), "rho exterior");
+        hipck(hipStreamSynchronize(st), "rho sync");
+        for (void* q : {(void*)td.beg, (void*)td.end, (void*)td.perm, (void*)td.axes, (void*)td.node_s,
+                        (void*)td.node_k, (void*)td.far_ptr, (void*)td.far_src, (void*)td.E, (void*)d_nptr,
+                        (void*)d_nsrc, (void*)xh, (void*)yh})
+            A.release(q);
+        op.stats.t_rho_ms = tm.stop();
+
+        Timer tm2(st);
+        std::vector<int64_t> icells;
+        for (int64_t c = 0; c < m.nc; ++c)
+            if (m.interior[c]) icells.push_back(c);
+        std::vector<std::pair<int64_t, int64_t>> contrib;
+        for (size_t ci = 0; ci < icells.size(); ++ci) {
+            int64_t c = icells[ci];
+            for (int a = 0; a <= d; ++a) {
+                int32_t va = m.v(a, c);
+                if (va >= m.N) continue;
+                for (int b = 0; b <= d; ++b) {
+                    int32_t vb = m.v(b, c);
+                    if (vb >= m.N) continue;
+                    int lo = std::min(a, b), hi = std::max(a, b);
+                    contrib.push_back({csr_slot(op, op.pos_of_dof[va], op.pos_of_dof[vb]), (int64_t)ci * 9 + lo * 3 + hi});
+                }
+            }
+        }
+        int64_t* d_ic = A.upload(icells, st);
+        double* d_ml = A.alloc<double>((int64_t)F * icells.size() * 9);
+        hipck(launch_mass_local(d, (int64_t)icells.size(), d_ic, nqe, op.d_lam, op.d_qw, op.d_rho, nq, F, d_ml, st),
+              "mass local");
+        std::vector<int64_t> cptr, cidx;
+        contrib_csr(nnz, contrib, cptr, cidx);
+        int64_t* d_cptr = A.upload(cptr, st);
+        int64_t* d_cidx = A.upload(cidx, st);
+        op.d_M = A.alloc<double>((int64_t)F * nnz);
+        hipck(launch_segsum(nnz, d_cptr, d_cidx, nullptr, F, d_ml, (int64_t)icells.size() * 9, op.d_M, st),
+              "segsum M");
+        op.d_BM = A.alloc<double>((int64_t)F * nnz);
+        hipck(launch_axpby((int64_t)F * nnz, 1.0, op.d_B, 1.0, op.d_M, op.d_BM, st), "B+M");
+        hipck(hipStreamSynchronize(st), "mass sync");
+        A.release(d_ic); A.release(d_ml); A.release(d_cptr); A.release(d_cidx);
+        op.stats.t_mass_ms = tm2.stop();
+    }
+
+    // ---- K~: bases, transfers, near leaf blocks (Sec. 5)
+    {
+        Timer tm(st);
+        const Tree& kt = op.kt;
+        Locator loc;
+        loc.build(m);
+        std::vector<double> axes, ns, nk;
+        cluster_nodes(op, kt, loc, axes, ns, nk);
+        std::vector<int64_t> fptr, fsrc;
+        far_csr(kt, op.kfar, fptr, fsrc);
+        TreeDev& td = op.kdev;
+        td.beg = A.upload(kt.beg, st);
+        td.end = A.upload(kt.end, st);
+        td.perm = A.upload(kt.perm, st);
+        td.axes = A.upload(axes, st);
+        td.node_s = A.upload(ns, st);
+        td.node_k = A.upload(nk, st);
+        td.far_ptr = A.upload(fptr, st);
+        td.far_src = A.upload(fsrc, st);
+        td.E = A.alloc<double>(kt.ncl * d * p * p);
+        H2Tree h = make_h2(kt, td, p);
+        hipck(launch_transfer(h, td.E, st), "transfer K");
+        op.d_U = A.alloc<double>(m.N * k);
+        hipck(launch_basis_n(h, m.N, td.perm, op.d_nc_ptr, op.d_nc_cell, op.d_nc_slot, nqe, d_qx, op.d_qw,
+                             op.d_lam, nq, op.d_U, st), "basis");
+        hipck(hipStreamSynchronize(st), "basis sync");
+        op.stats.t_bases_ms = tm.stop();
+
+        Timer tm2(st);
+        // leaf patches and per-row cell lists
+        const int64_t nleaf = kt.nleaf();
+        std::vector<int64_t> leaf_beg(nleaf + 1);
+        op.cap = 0;
+        for (int64_t li = 0; li < nleaf; ++li) {
+            leaf_beg[li] = kt.beg[kt.first_leaf() + li];
+            op.cap = std::max(op.cap, kt.end[kt.first_leaf() + li] - kt.beg[kt.first_leaf() + li]);
+        }
+        leaf_beg[nleaf] = m.N;
+        std::vector<int64_t> patch_ptr(nleaf + 1, 0), patch_cell, row_ptr(m.N + 1, 0);
+        std::vector<int32_t> row_lcell;
+        std::vector<int8_t> row_slot;
+        int64_t max_patch = 0;
+        for (int64_t li = 0; li < nleaf; ++li) {
+            std::vector<int64_t> cl;
+            for (int64_t j = leaf_beg[li]; j < leaf_beg[li + 1]; ++j) {
+                int64_t v = kt.perm[j];
+                for (int64_t e = op.ncs.ptr[v]; e < op.ncs.ptr[v + 1]; ++e) cl.push_back(op.ncs.cell[e]);
+            }
+            std::sort(cl.begin(), cl.end());
+            cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
+            max_patch = std::max<int64_t>(max_patch, cl.size());
+            for (int64_t j = leaf_beg[li]; j < leaf_beg[li + 1]; ++j) {
+                int64_t v = kt.perm[j];
+                for (int64_t e = op.ncs.ptr[v]; e < op.ncs.ptr[v + 1]; ++e) {
+                    int64_t lc = std::lower_bound(cl.begin(), cl.end(), op.ncs.cell[e]) - cl.begin();
+                    row_lcell.push_back((int32_t)lc);
+                    row_slot.push_back(op.ncs.slot[e]);
+                }
+                row_ptr[j + 1] = (int64_t)row_lcell.size();
+            }
+            patch_cell.insert(patch_cell.end(), cl.begin(), cl.end());
+            patch_ptr[li + 1] = (int64_t)patch_cell.size();
+        }
+        std::vector<int64_t> tgt, src, near_ptr(nleaf + 1, 0), near_src_leaf;
+        for (auto& pr : op.knear) {
+            tgt.push_back(pr.first);
+            src.push_back(pr.second);
+            near_ptr[pr.first - kt.first_leaf() + 1]++;
+            near_src_leaf.push_back(pr.second - kt.first_leaf());
+        }
+        for (int64_t i = 0; i < nleaf; ++i) near_ptr[i + 1] += near_ptr[i];
+        NearPlan np{};
+        np.npairs = (int64_t)op.knear.size();
+        np.cap = op.cap;
+        np.tgt = A.upload(tgt, st);
+        np.src = A.upload(src, st);
+        np.patch_ptr = A.upload(patch_ptr, st);
+        np.patch_cell = A.upload(patch_cell, st);
+        np.row_ptr = A.upload(row_ptr, st);
+        np.row_lcell = A.upload(row_lcell, st);
+        np.row_slot = A.upload(row_slot, st);
+        np.nc_ptr = op.d_nc_ptr;
+        np.nc_cell = op.d_nc_cell;
+        np.nc_slot = op.d_nc_slot;
+        op.d_near = A.alloc<double>((int64_t)F * np.npairs * op.cap * op.cap);
+        hipck(launch_near_blocks_lds(h, np, max_patch, td.perm, op.d_C, nqe, m.nc, d_qx, op.d_qw, d_qs, d_qk,
+                                     op.d_lam, nq, F, op.opts.a_scale, op.d_near, st), "near blocks");
+        hipck(hipStreamSynchronize(st), "near sync");
+        op.d_leaf_beg = A.upload(leaf_beg, st);
+        op.d_near_ptr = A.upload(near_ptr, st);
+        op.d_near_src = A.upload(near_src_leaf, st);
+        for (void* q : {(void*)np.tgt, (void*)np.src, (void*)np.patch_ptr, (void*)np.patch_cell,
+                        (void*)np.row_ptr, (void*)np.row_lcell, (void*)np.row_slot})
+            A.release(q);
+        op.stats.t_near_blocks_ms = tm2.stop();
+    }
+    // keep only what apply / load / export need
+    A.release(d_qs);
+    A.release(d_qk);
+    A.release(d_qx);
+    A.release(d_qint);
+    A.release(d_s);
+    A.release(d_k);
+    op.stats.t_total_ms = ms_since(t_all) + op.stats.t_plan_ms;
+}
+
+void fill_stats(fpde_op& op) {
+    fpde_stats_t& S = op.stats;
+    S.n_dofs = op.mesh.N;
+    S.n_nodes = op.mesh.M;
+    S.n_cells = op.mesh.nc;
+    S.n_fields = op.F;
+    S.n_pairs_identical = S.n_pairs_edge = S.n_pairs_vertex = 0;
+    for (auto& p : op.pairs) (p.kind == 0 ? S.n_pairs_identical : p.kind == 1 ? S.n_pairs_edge : S.n_pairs_vertex)++;
+    S.csr_nnz = (int64_t)op.csr_col.size();
+    S.k_clusters = op.kt.ncl;
+    S.k_levels = op.kt.L + 1;
+    S.k_leaves = op.kt.nleaf();
+    S.k_far = (int64_t)op.kfar.size();
+    S.k_near = (int64_t)op.knear.size();
+    S.k_rank = op.mesh.dim == 2 ? op.opts.cheb_p * op.opts.cheb_p : op.opts.cheb_p;
+    int64_t cap = 0;
+    for (int64_t c = op.kt.first_leaf(); c < op.kt.ncl; ++c) cap = std::max(cap, op.kt.end[c] - op.kt.beg[c]);
+    S.k_leaf_cap = cap;
+    S.rho_points = op.Q.nq;
+    S.rho_clusters = op.rt.ncl;
+    S.rho_levels = op.rt.L + 1;
+    S.rho_far = (int64_t)op.rfar.size();
+    S.rho_near = (int64_t)op.rnear.size();
+    S.device_bytes = op.arena.bytes;
+    S.apply_bytes_near = (int64_t)op.knear.size() * cap * cap * 8;
+    S.apply_bytes_csr = S.csr_nnz * (8 + 4) + (op.mesh.N + 1) * 8;
+    S.apply_bytes_bases = op.mesh.N * S.k_rank * 8;
+}
+
+void ensure_ws(fpde_op& op, int64_t R) {
+    if (op.ws_R >= R) return;
+    const int d = op.mesh.dim, p = op.opts.cheb_p, k = d == 2 ? p * p : p;
+    if (op.d_xt) { op.arena.release(op.d_xt); op.arena.release(op.d_xh); op.arena.release(op.d_yh); }
+    op.d_xt = op.arena.alloc<double>((int64_t)op.F * (op.mesh.N + op.cap) * R);
+    op.d_xh = op.arena.alloc<double>((int64_t)op.F * op.kt.ncl * k * R);
+    op.d_yh = op.arena.alloc<double>((int64_t)op.F * op.kt.ncl * k * R);
+    op.ws_R = R;
+}
+
+void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64_t R, hipStream_t st) {
+    if (op.plan_only) fail(FPDE_ESTATE, "operator was built with FPDE_FLAG_PLAN_ONLY");
+    if (dtype != FPDE_F64 && dtype != FPDE_F32) fail(FPDE_EINVAL, "dtype must be FPDE_F64 or FPDE_F32");
+    if (R < 1 || !x || !y) fail(FPDE_EINVAL, "bad vectors");
+    ensure_ws(op, R);
+    const int F = op.F, p = op.opts.cheb_p;
+    const Tree& kt = op.kt;
+    H2Tree h = make_h2(kt, op.kdev, p);
+    ApplyPlan a{};
+    a.N = op.mesh.N;
+    a.nleaf = kt.nleaf();
+    a.first_leaf = kt.first_leaf();
+    a.cap = op.cap;
+    a.perm = op.kdev.perm;
+    a.leaf_beg = op.d_leaf_beg;
+    a.csr_ptr = op.d_csr_ptr;
+    a.csr_col = op.d_csr_col;
+    a.csr_val = op.d_BM;
+    a.nnz = (int64_t)op.csr_col.size();
+    a.near_ptr = op.d_near_ptr;
+    a.near_src = op.d_near_src;
+    a.near_blk = op.d_near;
+    a.npairs = (int64_t)op.knear.size();
+    a.U = op.d_U;
+    a.k = h.k;
+    // x in tree order (the [N, N+cap) tail stays zero for padded near blocks)
+    hipck(launch_gather(a, F, (int)R, dtype, x, op.d_xt, st), "gather");
+    if (parts & FPDE_PART_KFAR) {
+        hipck(launch_leaf_up(a, h, F, (int)R, op.d_xt, op.d_xh, st), "leaf up");
+        for (int lev = kt.L - 1; lev >= 0; --lev) hipck(launch_up_level(h, lev, F, (int)R, op.d_xh, st), "up");
+        hipck(launch_coupling(h, F, (int)R, -2.0, op.opts.a_scale, op.d_xh, op.d_yh, st), "coupling");
+        for (int lev = 0; lev < kt.L; ++lev) hipck(launch_down_level(h, lev, F, (int)R, op.d_yh, st), "down");
+    }
+    const double* cv = nullptr;
+    if ((parts & FPDE_PART_B) && (parts & FPDE_PART_M)) cv = op.d_BM;
+    else if (parts & FPDE_PART_B) cv = op.d_B;
+    else if (parts & FPDE_PART_M) cv = op.d_M;
+    hipck(launch_leaf_out(a, h, parts, F, (int)R, cv, op.d_xt, op.d_yh, dtype, y, st), "leaf out");
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+namespace {
+fpde_status guarded(const std::function<void()>& fn) {
+    try {
+        fn();
+        g_err.clear();
+        return FPDE_OK;
+    } catch (const Fail& f) {
+        g_err = f.msg;
+        return f.st;
+    } catch (const std::bad_alloc&) {
+        g_err = "host out of memory";
+        return FPDE_ENOMEM;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return FPDE_EINVAL;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+fpde_status fpde_opts_default(fpde_opts* o) {
+    if (!o) return FPDE_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = FPDE_PREC_FP64;
+    o->leaf_size = 64;
+    o->leaf_size_rho = 64;
+    o->cheb_p = 5;
+    o->eta = 1.0;
+    o->nq_sing = 3;
+    o->nq_reg = 3;
+    o->s_bar = 0.9;
+    o->s_exterior = 0.0;
+    o->kappa_exterior = 1.0;
+    o->n_theta = 128;
+    o->a_scale = 1.0;
+    return FPDE_OK;
+}
+
+fpde_status fpde_gauss_legendre(int32_t n, double* x, double* w) {
+    return guarded([&] {
+        if (n < 1 || n > 64 || !x || !w) fail(FPDE_EINVAL, "n in [1,64] and non-NULL arrays required");
+        gauss_legendre01(n, x, w);
+    });
+}
+
+fpde_status fpde_build(const fpde_mesh* mesh, int32_t n_fields, const double* s, const double* kappa,
+                       const fpde_opts* opts, fpde_op** out) {
+    return guarded([&] {
+        if (!out) fail(FPDE_EINVAL, "out is NULL");
+        *out = nullptr;
+        fpde_opts o;
+        if (opts) o = *opts;
+        else fpde_opts_default(&o);
+        validate(mesh, n_fields, s, kappa, o);
+        std::unique_ptr<fpde_op> op(new fpde_op());
+        op->opts = o;
+        op->F = n_fields;
+        op->plan_only = (o.flags & FPDE_FLAG_PLAN_ONLY) != 0;
+        HostMesh& m = op->mesh;
+        m.dim = mesh->dim;
+        m.M = mesh->n_nodes;
+        m.N = mesh->n_dofs;
+        m.nc = mesh->n_cells;
+        m.R = mesh->exterior_radius;
+        m.X.assign(mesh->coords, mesh->coords + (int64_t)m.dim * m.M);
+        m.C.assign(mesh->cells, mesh->cells + (int64_t)(m.dim + 1) * m.nc);
+        m.interior.assign(mesh->cell_interior, mesh->cell_interior + m.nc);
+        op->s.assign(s, s + (int64_t)n_fields * m.M);
+        op->kappa.assign(kappa, kappa + (int64_t)n_fields * m.M);
+        plan(*op);
+        if (!op->plan_only) {
+            int ndev = 0;
+            if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(FPDE_EDEVICE, "no HIP device");
+            hipck(hipStreamCreateWithFlags(&op->stream, hipStreamNonBlocking), "stream");
+            build_device(*op);
+        }
+        fill_stats(*op);
+        *out = op.release();
+    });
+}
+
+fpde_status fpde_apply_parts(fpde_op* op, int32_t parts, int32_t dtype, const void* x, void* y, int64_t nrhs,
+                             void* hip_stream) {
+    return guarded([&] {
+        if (!op) fail(FPDE_EINVAL, "op is NULL");
+        apply_impl(*op, parts, dtype, x, y, nrhs, (hipStream_t)hip_stream);
+    });
+}
+
+fpde_status fpde_apply(fpde_op* op, int32_t dtype, const void* x, void* y, int64_t nrhs, void* hip_stream) {
+    return fpde_apply_parts(op, FPDE_PART_ALL, dtype, x, y, nrhs, hip_stream);
+}
+
+fpde_status fpde_load_vector(fpde_op* op, const double* f_nodal, double* F, void* hip_stream) {
+    return guarded([&] {
+        if (!op || !f_nodal || !F) fail(FPDE_EINVAL, "NULL argument");
+        if (op->plan_only) fail(FPDE_ESTATE, "plan-only operator");
+        hipck(launch_load_nv(op->mesh.N, op->mesh.dim + 1, op->d_nc_ptr, op->d_nc_cell, op->d_nc_slot, op->d_C,
+                             op->mesh.nc, op->Q.nqe, op->d_lam, op->d_qw, op->d_cint, f_nodal, F,
+                             (hipStream_t)hip_stream), "load");
+    });
+}
+
+fpde_status fpde_solve(fpde_op* op, const double* Fv, double* u, int64_t nrhs, double rtol, int32_t maxit,
+                       fpde_solve_info* info, void* hip_stream) {
+    (void)op; (void)Fv; (void)u; (void)nrhs; (void)rtol; (void)maxit; (void)info; (void)hip_stream;
+    g_err = "fpde_solve: not available in this build";
+    return FPDE_ESTATE;
+}
+
+fpde_status fpde_stats(const fpde_op* op, fpde_stats_t* s) {
+    if (!op || !s) return FPDE_EINVAL;
+    *s = op->stats;
+    s->device_bytes = op->arena.bytes;
+    return FPDE_OK;
+}
+
+fpde_status fpde_export(const fpde_op* op, int32_t what, int32_t field, void* dst, int64_t* count) {
+    return guarded([&] {
+        if (!op || !count) fail(FPDE_EINVAL, "NULL argument");
+        if (field < 0 || field >= op->F) fail(FPDE_EINVAL, "field out of range");
+        const int64_t N = op->mesh.N;
+        std::vector<int64_t> iv;
+        std::vector<double> dv;
+        bool is_int = true;
+        auto dof_csr = [&](const double* dvals, std::vector<int64_t>* ptr, std::vector<int64_t>* cols,
+                           std::vector<double>* vals) {
+            // rows/cols back to dof order
+            std::vector<double> hv;
+            const int64_t nnz = (int64_t)op->csr_col.size();
+            if (dvals) {
+                hv.resize(nnz);
+                hipck(hipMemcpy(hv.data(), dvals + (int64_t)field * nnz, sizeof(double) * nnz, hipMemcpyDeviceToHost),
+                      "export copy");
+            }
+            std::vector<std::tuple<int64_t, int64_t, double>> e;
+            e.reserve(nnz);
+            for (int64_t r = 0; r < N; ++r)
+                for (int64_t q = op->csr_ptr[r]; q < op->csr_ptr[r + 1]; ++q)
+                    e.emplace_back(op->kt.perm[r], op->kt.perm[op->csr_col[q]], dvals ? hv[q] : 0.0);
+            std::sort(e.begin(), e.end());
+            if (ptr) {
+                ptr->assign(N + 1, 0);
+                for (auto& t : e) (*ptr)[std::get<0>(t) + 1]++;
+                for (int64_t i = 0; i < N; ++i) (*ptr)[i + 1] += (*ptr)[i];
+            }
+            if (cols) for (auto& t : e) cols->push_back(std::get<1>(t));
+            if (vals) for (auto& t : e) vals->push_back(std::get<2>(t));
+        };
+        switch (what) {
+            case FPDE_EXPORT_CSR_ROWPTR: dof_csr(nullptr, &iv, nullptr, nullptr); break;
+            case FPDE_EXPORT_CSR_COLS: dof_csr(nullptr, nullptr, &iv, nullptr); break;
+            case FPDE_EXPORT_CSR_B:
+            case FPDE_EXPORT_CSR_M:
+                if (op->plan_only) fail(FPDE_ESTATE, "plan-only operator");
+                is_int = false;
+                dof_csr(what == FPDE_EXPORT_CSR_B ? op->d_B : op->d_M, nullptr, nullptr, &dv);
+                break;
+            case FPDE_EXPORT_K_PERM: iv = op->kt.perm; break;
+            case FPDE_EXPORT_K_LEAFPTR:
+                for (int64_t c = op->kt.first_leaf(); c < op->kt.ncl; ++c) iv.push_back(op->kt.beg[c]);
+                iv.push_back(N);
+                break;
+            case FPDE_EXPORT_K_FAR: for (auto& p : op->kfar) { iv.push_back(p.first); iv.push_back(p.second); } break;
+            case FPDE_EXPORT_K_NEAR: for (auto& p : op->knear) { iv.push_back(p.first); iv.push_back(p.second); } break;
+            case FPDE_EXPORT_RHO_PERM: iv = op->rt.perm; break;
+            case FPDE_EXPORT_RHO_FAR: for (auto& p : op->rfar) { iv.push_back(p.first); iv.push_back(p.second); } break;
+            case FPDE_EXPORT_RHO_NEAR: for (auto& p : op->rnear) { iv.push_back(p.first); iv.push_back(p.second); } break;
+            case FPDE_EXPORT_RHO:
+                if (op->plan_only) fail(FPDE_ESTATE, "plan-only operator");
+                is_int = false;
+                dv.resize(op->Q.nq);
+                hipck(hipMemcpy(dv.data(), op->d_rho + (int64_t)field * op->Q.nq, sizeof(double) * op->Q.nq,
+                                hipMemcpyDeviceToHost), "export rho");
+                break;
+            case FPDE_EXPORT_PAIRS:
+                for (auto& p : op->pairs) {
+                    iv.push_back(p.kind); iv.push_back(p.c0); iv.push_back(p.c1);
+                    for (int a = 0; a < 3; ++a) iv.push_back(p.v[a]);
+                    iv.push_back(p.v[4]); iv.push_back(p.v[5]);
+                }
+                break;
+            case FPDE_EXPORT_K_BOXES:
+            case FPDE_EXPORT_RHO_BOXES: {
+                is_int = false;
+                const Tree& t = what == FPDE_EXPORT_K_BOXES ? op->kt : op->rt;
+                for (int64_t c = 0; c < t.ncl; ++c) {
+                    for (int k = 0; k < t.dim; ++k) dv.push_back(t.lo[c * t.dim + k]);
+                    for (int k = 0; k < t.dim; ++k) dv.push_back(t.hi[c * t.dim + k]);
+                }
+                break;
+            }
+            default: fail(FPDE_EINVAL, "unknown export");
+        }
+        const int64_t n = is_int ? (int64_t)iv.size() : (int64_t)dv.size();
+        if (dst) {
+            if (*count < n) fail(FPDE_EINVAL, "destination too small");
+            if (is_int) std::memcpy(dst, iv.data(), sizeof(int64_t) * n);
+            else std::memcpy(dst, dv.data(), sizeof(double) * n);
+        }
+        *count = n;
+    });
+}
+
+void fpde_destroy(fpde_op* op) {
+    if (!op) return;
+    if (op->stream) {
+        hipStreamSynchronize(op->stream);
+        hipStreamDestroy(op->stream);
+    }
+    delete op;
+}
+
+const char* fpde_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Internal declarations shared by the host planner (fpde_host.cpp) and the
+// HIP kernels (fpde_kernels.hip).  Plain pointers only; all device arrays are
+// structure-of-arrays in HBM.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace fpde {
+
+constexpr int kMaxP = 8;        // Chebyshev points per dimension supported by the kernels
+constexpr int kMaxNq = 8;       // Gauss points per direction supported by the kernels
+constexpr int kMaxDeg = 16;     // max cells around a node handled by the near-block kernel
+
+// ---------------------------------------------------------------- build kernels
+
+// Local matrices of touching pairs (Sec. 4).  pairs: [np][8] int32 rows
+// (kind, cell0 v0 v1 v2, cell1 v0 v1 v2, pad) with canonical vertices; kind 0
+// identical, 1 edge, 2 vertex (1D: two vertices per cell).  out: [F][np][25],
+// entry a*5+b (a <= b) over the local dof list of the case, already multiplied
+// by the pair weight (2 for distinct cells, 1 for identical).
+hipError_t launch_singular(int dim, int64_t np, const int32_t* pairs, const double* coords,
+                           int64_t n_nodes, int F, const double* s, const double* kappa,
+                           double a_scale, double s_bar, int nq, const double* g01,
+                           const double* w01, double* out, hipStream_t st);
+
+// out[f*nslots + i] = sum_{k in [ptr[i],ptr[i+1])} w[k] * src[f*src_stride + idx[k]]
+hipError_t launch_segsum(int64_t nslots, const int64_t* ptr, const int64_t* idx, const double* w,
+                         int F, const double* src, int64_t src_stride, double* out,
+                         hipStream_t st);
+
+// s, sqrt(kappa) at the quadrature points: qs[f][q], qk[f][q]
+hipError_t launch_quad_fields(int dim, int64_t nc, int nqe, const int32_t* cells,
+                              const double* lam /*[dim+1][nqe]*/, int F, int64_t n_nodes,
+                              const double* s, const double* kappa, double* qs, double* qk,
+                              hipStream_t st);
+
+// Generic H2 description (one tree).  Clusters in heap order, leaves contiguous.
+struct H2Tree {
+    int dim, p, k, L;
+    int64_t ncl, nleaf, first_leaf;
+    const int64_t* beg;        // [ncl] tree-order ranges
+    const int64_t* end;
+    const double* axes;        // [ncl][dim][p] Chebyshev points per axis
+    const double* E;           // [ncl][dim][p][p] child->parent 1D transfers, [b][a]
+    const double* node_s;      // [F][ncl][k]
+    const double* node_k;      // [F][ncl][k]  sqrt(kappa)
+    const int64_t* far_ptr;    // [ncl+1] by target cluster
+    const int64_t* far_src;    // [nfar]
+};
+
+// Chebyshev transfer matrices E (Sec. 5.3 nested bases).
+hipError_t launch_transfer(const H2Tree& t, double* E, hipStream_t st);
+// xh[f][parent][alpha][r] = sum_children E^T xh[child]   (one level)
+hipError_t launch_up_level(const H2Tree& t, int level, int F, int R, double* xh, hipStream_t st);
+// yh[f][child][beta][r] += E yh[parent]                 (one level)
+hipError_t launch_down_level(const H2Tree& t, int level, int F, int R, double* yh, hipStream_t st);
+// yh[f][s][alpha][r] = fac * sum_far sum_beta gamma(xi_alpha, xi'_beta) xh[f][s'][beta][r]
+hipError_t launch_coupling(const H2Tree& t, int F, int R, double fac, double a_scale,
+                           const double* xh, double* yh, hipStream_t st);
+
+// Density tree leaf operations (Sec. 6.2): moments m[f][leaf][beta] = sum l_beta(q) w(q)
+hipError_t launch_rho_moments(const H2Tree& t, const int64_t* perm, const double* qx,
+                              const double* qw, int64_t nq_all, int F, double* xh, hipStream_t st);
+// rho[f][q] += sum_alpha l_alpha(q) yh[f][leaf][alpha] for interior q
+hipError_t launch_rho_eval(const H2Tree& t, const int64_t* perm, const double* qx,
+                           const uint8_t* q_int, int64_t nq_all, int F, const double* yh,
+                           double* rho, hipStream_t st);
+// near sums with the mesh-dependent kernel gamma_T (eq. e:g-t)
+hipError_t launch_rho_near(const H2Tree& t, const int64_t* perm, const int64_t* near_ptr,
+                           const int64_t* near_src, const double* qx, const double* qw,
+                           const double* qs, const double* qk, const uint8_t* q_int, int nqe,
+                           const int32_t* cells, int64_t nc, int64_t nq_all, int F, double a_scale,
+                           double* rho, hipStream_t st);
+// exterior density beyond |x| = R (eq. e:rho), added at interior points
+hipError_t launch_rho_exterior(int dim, int64_t nq_all, const double* qx, const double* qs,
+                               const double* qk, const uint8_t* q_int, int F, double R,
+                               double s_out, double k_out_sqrt, double a_scale, int n_theta,
+                               double* rho, hipStream_t st);
+// mass local matrices of interior cells: out[f][ci][6] (a<=b over 3 vertices, 2 in 1D -> 3)
+hipError_t launch_mass_local(int dim, int64_t n_int_cells, const int64_t* int_cells, int nqe,
+                             const double* lam, const double* qw, const double* rho, int64_t nq_all,
+                             int F, double* out, hipStream_t st);
+
+// Leaf bases U[t][alpha] = sum_{tau in S_i} sum_q w psi_i(q) l_alpha(q) (eq. eq:triple_product)
+hipError_t launch_basis_n(const H2Tree& t, int64_t N, const int64_t* perm, const int64_t* nc_ptr,
+                          const int64_t* nc_cell, const int8_t* nc_slot, int nqe, const double* qx,
+                          const double* qw, const double* lam, int64_t nq_all, double* U,
+                          hipStream_t st);
+
+// Near leaf blocks of K~ (eq. e:k-near): nb[f][pair][cap][cap]
+struct NearPlan {
+    int64_t npairs, cap;
+    const int64_t* tgt;        // [npairs] target leaf (heap id)
+    const int64_t* src;        // [npairs] source leaf
+    const int64_t* patch_ptr;  // [nleaf+1] cells of the patch of each leaf (sorted)
+    const int64_t* patch_cell; // [...]
+    const int64_t* row_ptr;    // [N+1] per tree position: entries into row_lcell/row_slot
+    const int32_t* row_lcell;  // local patch index of each cell around the row node
+    const int8_t* row_slot;    // vertex slot of the row node in that cell
+    const int64_t* nc_ptr;     // node -> cells (global)
+    const int64_t* nc_cell;
+    const int8_t* nc_slot;
+};
+hipError_t launch_near_blocks_lds(const H2Tree& t, const NearPlan& np, int64_t max_patch,
+                                  const int64_t* perm, const int32_t* cells, int nqe, int64_t nc,
+                                  const double* qx, const double* qw, const double* qs,
+                                  const double* qk, const double* lam, int64_t nq_all, int F,
+                                  double a_scale, double* nb, hipStream_t st);
+
+// Load vector F_i = sum_q w psi_i(q) f(q) for dofs i (node -> cell lists)
+hipError_t launch_load_nv(int64_t N, int nv, const int64_t* nc_ptr, const int64_t* nc_cell,
+                          const int8_t* nc_slot, const int32_t* cells, int64_t nc, int nqe,
+                          const double* lam, const double* qw, const uint8_t* cell_int,
+                          const double* f_nodal, double* F, hipStream_t st);
+
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* z,
+                        hipStream_t st);
+hipError_t launch_fill(int64_t n, double v, double* x, hipStream_t st);
+
+// ---------------------------------------------------------------- apply kernels
+
+struct ApplyPlan {
+    int64_t N, nleaf, first_leaf, cap;
+    const int64_t* perm;          // tree position -> dof
+    const int64_t* leaf_beg;      // [nleaf+1]
+    const int64_t* csr_ptr;       // [N+1] tree-ordered rows
+    const int32_t* csr_col;       // tree positions
+    const double* csr_val;        // [F][nnz]  B + M
+    int64_t nnz;
+    const int64_t* near_ptr;      // [nleaf+1] pairs of each target leaf
+    const int64_t* near_src;      // [npairs] source leaf index (0-based leaf index)
+    const double* near_blk;       // [F][npairs][cap][cap]
+    int64_t npairs;
+    const double* U;              // [N][k]
+    int k;
+};
+
+// x_tree[f][t][r] = x[f][perm[t]][r]  (dtype 0 double, 1 float)
+hipError_t launch_gather(const ApplyPlan& a, int F, int R, int dtype, const void* x, double* xt,
+                         hipStream_t st);
+// xh[f][leaf][alpha][r] = sum_{t in leaf} U[t][alpha] xt[f][t][r]
+hipError_t launch_leaf_up(const ApplyPlan& a, const H2Tree& t, int F, int R, const double* xt,
+                          double* xh, hipStream_t st);
+// y[f][perm[t]][r] = (B+M) xt + K_near xt + U yh     (parts select terms)
+hipError_t launch_leaf_out(const ApplyPlan& a, const H2Tree& t, int parts, int F, int R,
+                           const double* csr_val_override, const double* xt, const double* yh,
+                           int dtype, void* y, hipStream_t st);
+
+}  // namespace fpde

@@ -1,0 +1,132 @@
+"""Python binding of libfpde with the same names as the C ABI.
+
+PyTorch is used only for device memory and streams: every step of the build
+and of the apply runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+from ._abi import check, lib
+
+
+def opts_struct(opts: dict | None = None, plan_only: bool = False) -> _abi.Opts:
+    o = _abi.Opts()
+    check(lib().fpde_opts_default(C.byref(o)), "fpde_opts_default")
+    for key, val in (opts or {}).items():
+        if key == "precision":
+            o.precision = _abi.PREC_MIXED if val in ("mixed", _abi.PREC_MIXED) else _abi.PREC_FP64
+        elif hasattr(o, key):
+            setattr(o, key, val)
+    if plan_only:
+        o.flags |= _abi.FLAG_PLAN_ONLY
+    return o
+
+
+def gauss_legendre(n: int):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    check(lib().fpde_gauss_legendre(n, x.ctypes.data_as(C.POINTER(C.c_double)),
+                                    w.ctypes.data_as(C.POINTER(C.c_double))), "fpde_gauss_legendre")
+    return x, w
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Operator:
+    """fpde_build / fpde_apply / fpde_solve / fpde_load_vector / fpde_export / fpde_stats."""
+
+    def __init__(self, mesh, s, kappa, opts: dict | None = None, plan_only: bool = False):
+        self._h = C.c_void_p()
+        coords = np.ascontiguousarray(mesh.coords, dtype=np.float64)
+        cells = np.ascontiguousarray(mesh.cells, dtype=np.int32)
+        cint = np.ascontiguousarray(mesh.cell_interior, dtype=np.uint8)
+        s = np.ascontiguousarray(np.atleast_2d(s), dtype=np.float64)
+        kappa = np.ascontiguousarray(np.atleast_2d(kappa), dtype=np.float64)
+        if s.shape != kappa.shape or s.shape[1] != coords.shape[1]:
+            raise ValueError("s and kappa must be [F][n_nodes]")
+        m = _abi.Mesh(mesh.dim, coords.shape[1], mesh.n_dofs, coords.ctypes.data_as(C.POINTER(C.c_double)),
+                      cells.shape[1], cells.ctypes.data_as(C.POINTER(C.c_int32)),
+                      cint.ctypes.data_as(C.POINTER(C.c_uint8)), float(mesh.exterior_radius))
+        o = opts_struct(opts, plan_only)
+        check(lib().fpde_build(C.byref(m), s.shape[0], s.ctypes.data_as(C.POINTER(C.c_double)),
+                               kappa.ctypes.data_as(C.POINTER(C.c_double)), C.byref(o), C.byref(self._h)),
+              "fpde_build")
+        self.n_fields = s.shape[0]
+        self.n_dofs = int(mesh.n_dofs)
+        self.n_nodes = int(coords.shape[1])
+        self.dim = int(mesh.dim)
+
+    # ------------------------------------------------------------------ apply
+    def apply(self, x, y=None, parts: int = _abi.PART_ALL, stream=None):
+        """y = A x for device tensors x, y of shape [F, N, R] (float64 or float32)."""
+        import torch
+        if x.dim() == 2:
+            x = x.unsqueeze(-1)
+        if tuple(x.shape[:2]) != (self.n_fields, self.n_dofs) or not x.is_cuda:
+            raise ValueError(f"x must be a device tensor [F={self.n_fields}, N={self.n_dofs}, R]")
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        dtype = _abi.F64 if x.dtype == torch.float64 else _abi.F32
+        if x.dtype not in (torch.float64, torch.float32) or y.dtype != x.dtype or y.shape != x.shape:
+            raise ValueError("x, y must share shape and dtype float64/float32")
+        check(lib().fpde_apply_parts(self._h, parts, dtype, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                     x.shape[2], _stream_handle(stream)), "fpde_apply")
+        return y
+
+    def load_vector(self, f_nodal, stream=None):
+        import torch
+        f = f_nodal.contiguous()
+        out = torch.empty(self.n_dofs, dtype=torch.float64, device=f.device)
+        check(lib().fpde_load_vector(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(out.data_ptr()),
+                                     _stream_handle(stream)), "fpde_load_vector")
+        return out
+
+    def solve(self, F, u=None, rtol: float = 1e-10, maxit: int = 10000, stream=None):
+        import torch
+        if F.dim() == 2:
+            F = F.unsqueeze(-1)
+        F = F.contiguous()
+        if u is None:
+            u = torch.zeros_like(F)
+        info = _abi.SolveInfo()
+        check(lib().fpde_solve(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(u.data_ptr()), F.shape[2], rtol,
+                               maxit, C.byref(info), _stream_handle(stream)), "fpde_solve")
+        return u, {"iterations": info.iterations, "rel_residual": info.rel_residual,
+                   "converged": bool(info.converged)}
+
+    # ------------------------------------------------------------------ inspection
+    def export(self, what: str, field: int = 0) -> np.ndarray:
+        code = _abi.EXPORT[what]
+        n = C.c_int64(0)
+        check(lib().fpde_export(self._h, code, field, None, C.byref(n)), "fpde_export")
+        out = np.zeros(n.value, dtype=np.float64 if what in _abi.EXPORT_IS_FLOAT else np.int64)
+        check(lib().fpde_export(self._h, code, field, C.c_void_p(out.ctypes.data), C.byref(n)), "fpde_export")
+        return out
+
+    def stats(self) -> dict:
+        s = _abi.Stats()
+        check(lib().fpde_stats(self._h, C.byref(s)), "fpde_stats")
+        return {name: getattr(s, name) for name, _ in s._fields_}
+
+    def close(self):
+        if self._h:
+            lib().fpde_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
