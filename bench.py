@@ -1,0 +1,167 @@
+"""Benchmark of the stiffness-operator apply on one MI355X.
+
+One step = one application y = A x of the whole decomposed operator
+(A = B + M + K~: CSR near field + weighted mass, dense near leaf blocks, H2
+far field) to the workload's right-hand side(s), inputs resident in HBM.
+
+Metric: DOF-matvecs/s = N * F * R * steps / elapsed.  The default workload is
+the 2D unit square with 128 x 128 cells split in two (16129 dofs, 131072 cells
+including the exterior band), jittered nodes, variable order and diffusivity,
+leaf 64, 5 Chebyshev points per dimension, eta = 1, one right-hand side.
+
+Prints one JSON line (see the contract in the repository docs) with a
+roofline entry for the dominant kernel (fused CSR + near-block + basis
+output) measured with HIP events on the apply stream, and a CPU baseline of
+the oracle on a bounded sample of rows of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name: str):
+    from fpde_inputs import configs
+    if name == "square":
+        return configs.square(128), {"workload": "square-128x128-P1 (16129 dofs, 131072 cells), variable s and kappa",
+                                     "n": 128, "leaf": 64, "cheb_p": 5, "eta": 1.0, "nrhs": 1, "fields": 1}
+    if name == "square-small":
+        return configs.square(32), {"workload": "square-32x32-P1", "n": 32, "nrhs": 1, "fields": 1}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def algorithmic_bytes_out(op, st, F, R, elem=8):
+    """HBM bytes one launch of the fused output kernel must move (per definition, no re-reads):
+    near blocks (sum |s||s'| entries), CSR values + columns + row pointers, basis rows,
+    leaf coefficients, x (read once) and y (written once)."""
+    near_leaf = op.export("K_LEAFPTR")
+    sizes = near_leaf[1:] - near_leaf[:-1]
+    pairs = op.export("K_NEAR").reshape(-1, 2)
+    first = (1 << (int(st["k_levels"]) - 1)) - 1
+    near_entries = int((sizes[pairs[:, 0] - first] * sizes[pairs[:, 1] - first]).sum())
+    N = st["n_dofs"]
+    nnz = st["csr_nnz"]
+    k = st["k_rank"]
+    b = F * near_entries * elem
+    b += F * nnz * 8 + nnz * 4 + (N + 1) * 8
+    b += N * k * 8 + F * st["k_leaves"] * k * R * 8
+    b += 2 * F * N * R * 8
+    return b, near_entries
+
+
+def cpu_baseline(P, seconds: float = 15.0):
+    """Oracle rows of A_h x computed one by one on the host cores (bounded sample)."""
+    import numpy as np
+    from oracle.sampled import SampledOracle
+    np.seterr(divide="ignore", invalid="ignore")
+    t0 = time.perf_counter()
+    so = SampledOracle(P.mesh, P.s[0], P.kappa[0], P.opts)
+    t_setup = time.perf_counter() - t0
+    rng = np.random.default_rng(11)
+    rows = rng.choice(P.mesh.n_dofs, size=64, replace=False)
+    done = 0
+    t1 = time.perf_counter()
+    for r in rows:
+        so.row_apply([int(r)], P.x[0, :, 0])
+        done += 1
+        if time.perf_counter() - t1 > seconds:
+            break
+    el = time.perf_counter() - t1
+    try:
+        import threadpoolctl
+        cores = max(i["num_threads"] for i in threadpoolctl.threadpool_info()) if threadpoolctl.threadpool_info() else 1
+    except Exception:
+        cores = os.cpu_count() or 1
+    return {"value": done / el, "unit": "DOF-matvecs/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{done} rows of A_h x on the same workload computed entry by entry by the FP64 oracle "
+                      f"(tree/partition/basis setup {t_setup:.1f} s excluded, rows {el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="square")
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(1)
+
+    import numpy as np
+    import torch
+    import paper_2302_02863_amd as fp
+
+    P, cfg = workload(args.workload)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    op = fp.Operator(P.mesh, P.s, P.kappa, P.opts)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    st = op.stats()
+    F, N, R = P.x.shape
+    x = torch.tensor(P.x, device=dev)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        op.apply(x, y, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        op.apply(x, y, stream=stream)          # one hipGraph launch per apply
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    # same launches without the graph, HIP events on the apply stream between the phases
+    op.profile(True)
+    for _ in range(args.steps):
+        op.apply(x, y, stream=stream)
+    torch.cuda.synchronize()
+    prof = op.profile(False)
+    value = N * F * R * args.steps / el
+    out_ms = prof["ms_out"] / max(1, prof["n_applies"])
+    b_out, near_entries = algorithmic_bytes_out(op, st, F, R)
+    achieved = b_out / (out_ms * 1e-3) / 1e9
+    res = {
+        "metric": "DOF-matvecs/s of stiffness apply at 1e-6 rel err; mixed vs FP64 path speedup",
+        "value": value,
+        "unit": "DOF-matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": cfg,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_out (fused CSR + near blocks + downsweep + basis output)",
+                     "bytes_per_launch": b_out, "avg_ms": out_ms},
+        "phases_ms_per_apply": {k: prof[k] / max(1, prof["n_applies"]) for k in ("ms_gather", "ms_far", "ms_out",
+                                                                               "ms_total")},
+        "build_s": build_s,
+        "build_phase_ms": {k: st[k] for k in ("t_plan_ms", "t_singular_ms", "t_rho_ms", "t_mass_ms", "t_bases_ms",
+                                              "t_near_blocks_ms")},
+        "counts": {k: st[k] for k in ("n_dofs", "csr_nnz", "k_near", "k_far", "k_leaves", "rho_near", "rho_far")},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(P)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

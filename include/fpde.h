@@ -166,6 +166,19 @@ fpde_status fpde_load_vector(fpde_op *op, const double *f_nodal, double *F, void
 fpde_status fpde_solve(fpde_op *op, const double *F, double *u, int64_t nrhs, double rtol,
                        int32_t maxit, fpde_solve_info *info, void *hip_stream);
 
+/* Device-time profile of fpde_apply.  While profiling is on, each apply runs
+ * the same kernels as its captured graph, serialised on the apply's stream
+ * with HIP events between the phases: gather (vectors to tree order), far (H2
+ * upsweep, coupling, downsweep), out (CSR + near leaf blocks, the dominant
+ * kernel), far_out (downsweep to the leaves and U yh added to y).
+ * fpde_profile(op, 1, NULL) resets and starts recording; fpde_profile(op, 0,
+ * out) stops, waits for the recorded events and returns the sums. */
+typedef struct {
+    int64_t n_applies;
+    double ms_gather, ms_far, ms_out, ms_far_out, ms_total;
+} fpde_profile_t;
+fpde_status fpde_profile(fpde_op *op, int32_t enable, fpde_profile_t *out);
+
 /* Counts, memory and build-phase timings. */
 fpde_status fpde_stats(const fpde_op *op, fpde_stats_t *stats);
 

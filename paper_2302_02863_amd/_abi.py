@@ -48,6 +48,11 @@ class Stats(C.Structure):
         [(n, C.c_int64) for n in ("apply_bytes_near", "apply_bytes_csr", "apply_bytes_bases")]
 
 
+class Profile(C.Structure):
+    _fields_ = [("n_applies", C.c_int64), ("ms_gather", C.c_double), ("ms_far", C.c_double),
+                ("ms_out", C.c_double), ("ms_far_out", C.c_double), ("ms_total", C.c_double)]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double), ("converged", C.c_int32)]
 
@@ -72,11 +77,12 @@ def lib():
         L.fpde_solve.argtypes = [vp, vp, vp, C.c_int64, C.c_double, C.c_int32, C.POINTER(SolveInfo), vp]
         L.fpde_stats.argtypes = [vp, C.POINTER(Stats)]
         L.fpde_export.argtypes = [vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_int64)]
+        L.fpde_profile.argtypes = [vp, C.c_int32, C.POINTER(Profile)]
         L.fpde_destroy.argtypes = [vp]
         L.fpde_destroy.restype = None
         L.fpde_last_error.restype = C.c_char_p
         for n in ("fpde_opts_default", "fpde_gauss_legendre", "fpde_build", "fpde_apply", "fpde_apply_parts",
-                  "fpde_load_vector", "fpde_solve", "fpde_stats", "fpde_export"):
+                  "fpde_load_vector", "fpde_solve", "fpde_stats", "fpde_export", "fpde_profile"):
             getattr(L, n).restype = C.c_int32
         _lib = L
     return _lib

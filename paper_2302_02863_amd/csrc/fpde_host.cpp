@@ -3,8 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -142,7 +144,13 @@ struct fpde_op {
     int64_t* d_near_src = nullptr;
     double* d_near = nullptr;
     double* d_U = nullptr;
+    double* d_St = nullptr;         // [F][nfar][k][k] coupling matrices (transposed)
     int64_t cap = 0;
+    int ls = 0;                     // subtree-root level of the LDS subtree upsweep (per-level path)
+    int ls2 = 0;                    // subtree-root level of the short far chain
+    int32_t* d_csr_col_dof = nullptr;   // CSR columns as dof indices
+    // captured apply graphs keyed by (parts, dtype, x, y, R)
+    std::map<std::tuple<int, int, const void*, void*, int64_t>, hipGraphExec_t> graphs;
     // apply workspace
     int64_t ws_R = 0;
     double* d_xt = nullptr;
@@ -152,6 +160,12 @@ struct fpde_op {
     int64_t sw_n = 0;
     double *d_r = nullptr, *d_p = nullptr, *d_Ap = nullptr, *d_red = nullptr;
     fpde_stats_t stats{};
+    // profiling: events recorded per apply (gather begin, gather end, far end, out end)
+    bool profiling = false;
+    std::vector<std::array<hipEvent_t, 5>> prof_ev;
+    hipStream_t stream2 = nullptr;            // side stream of the captured fork/join graph
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    double* d_tmp = nullptr;                  // [F][nfar][k][R] per-pair coupling products
 };
 
 // ------------------------------------------------------------------ helpers
@@ -578,6 +592,16 @@ void build_device(fpde_op& op) {
         op.d_U = A.alloc<double>(m.N * k);
         hipck(launch_basis_n(h, m.N, td.perm, op.d_nc_ptr, op.d_nc_cell, op.d_nc_slot, nqe, d_qx, op.d_qw,
                              op.d_lam, nq, op.d_U, st), "basis");
+        {
+            std::vector<int64_t> ftgt;
+            for (auto& pr : op.kfar) ftgt.push_back(pr.first);
+            int64_t* d_ftgt = A.upload(ftgt, st);
+            op.d_St = A.alloc<double>((int64_t)F * op.kfar.size() * k * k);
+            hipck(launch_coupling_store(h, (int64_t)op.kfar.size(), d_ftgt, F, -2.0, op.opts.a_scale, op.d_St, st),
+                  "coupling store");
+            hipck(hipStreamSynchronize(st), "coupling sync");
+            A.release(d_ftgt);
+        }
         hipck(hipStreamSynchronize(st), "basis sync");
         op.stats.t_bases_ms = tm.stop();
 
@@ -648,6 +672,23 @@ void build_device(fpde_op& op) {
                         (void*)np.row_ptr, (void*)np.row_lcell, (void*)np.row_slot})
             A.release(q);
         op.stats.t_near_blocks_ms = tm2.stop();
+        // deepest subtree whose U rows fit the 64 KB LDS budget of the fused upsweep (R = 1)
+        int depth = 0;
+        int max_depth = kt.L;
+        if (const char* env = std::getenv("FPDE_MAX_SUBTREE_DEPTH")) max_depth = std::min(max_depth, std::atoi(env));
+        while (depth < max_depth) {
+            const int64_t rows = (int64_t(1) << (depth + 1)) * op.cap;
+            const int64_t ncl_sub = (int64_t(2) << (depth + 1)) - 1;
+            if ((rows * k + rows + ncl_sub * k + ncl_sub * d * p * p) * 8 > 64 * 1024) break;
+            ++depth;
+        }
+        op.ls = kt.L - depth;
+        // short far chain: deepest subtree-root level whose top tree fits one block's LDS
+        op.ls2 = kt.L;
+        while (op.ls2 > 0 && !far_v2_fits(h, op.ls2, 1)) --op.ls2;
+        std::vector<int32_t> cdof(op.csr_col.size());
+        for (size_t e = 0; e < cdof.size(); ++e) cdof[e] = (int32_t)kt.perm[op.csr_col[e]];
+        op.d_csr_col_dof = A.upload(cdof, st);
     }
     // keep only what apply / load / export need
     A.release(d_qs);
@@ -691,7 +732,12 @@ void fill_stats(fpde_op& op) {
 void ensure_ws(fpde_op& op, int64_t R) {
     if (op.ws_R >= R) return;
     const int d = op.mesh.dim, p = op.opts.cheb_p, k = d == 2 ? p * p : p;
-    if (op.d_xt) { op.arena.release(op.d_xt); op.arena.release(op.d_xh); op.arena.release(op.d_yh); }
+    if (op.d_xt) {
+        op.arena.release(op.d_xt); op.arena.release(op.d_xh); op.arena.release(op.d_yh); op.arena.release(op.d_tmp);
+        for (auto& kv : op.graphs) hipGraphExecDestroy(kv.second);
+        op.graphs.clear();
+    }
+    op.d_tmp = op.arena.alloc<double>((int64_t)op.F * std::max<size_t>(1, op.kfar.size()) * k * R);
     op.d_xt = op.arena.alloc<double>((int64_t)op.F * (op.mesh.N + op.cap) * R);
     op.d_xh = op.arena.alloc<double>((int64_t)op.F * op.kt.ncl * k * R);
     op.d_yh = op.arena.alloc<double>((int64_t)op.F * op.kt.ncl * k * R);
@@ -723,19 +769,53 @@ void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64
     a.npairs = (int64_t)op.knear.size();
     a.U = op.d_U;
     a.k = h.k;
-    // x in tree order (the [N, N+cap) tail stays zero for padded near blocks)
-    hipck(launch_gather(a, F, (int)R, dtype, x, op.d_xt, st), "gather");
-    if (parts & FPDE_PART_KFAR) {
-        hipck(launch_leaf_up(a, h, F, (int)R, op.d_xt, op.d_xh, st), "leaf up");
-        for (int lev = kt.L - 1; lev >= 0; --lev) hipck(launch_up_level(h, lev, F, (int)R, op.d_xh, st), "up");
-        hipck(launch_coupling(h, F, (int)R, -2.0, op.opts.a_scale, op.d_xh, op.d_yh, st), "coupling");
-        for (int lev = 0; lev < kt.L; ++lev) hipck(launch_down_level(h, lev, F, (int)R, op.d_yh, st), "down");
-    }
     const double* cv = nullptr;
     if ((parts & FPDE_PART_B) && (parts & FPDE_PART_M)) cv = op.d_BM;
     else if (parts & FPDE_PART_B) cv = op.d_B;
     else if (parts & FPDE_PART_M) cv = op.d_M;
-    hipck(launch_leaf_out(a, h, parts, F, (int)R, cv, op.d_xt, op.d_yh, dtype, y, st), "leaf out");
+    // the short far chain keeps subtrees and the top tree in LDS; wide R falls back to per-level sweeps
+    const bool v2 = far_v2_fits(h, op.ls2, (int)R);
+    if (!v2) {
+        hipck(launch_gather(a, F, (int)R, dtype, x, op.d_xt, st), "gather");
+        if (parts & FPDE_PART_KFAR) {
+            hipck(launch_leaf_up(a, h, F, (int)R, op.d_xt, op.d_xh, st), "leaf up");
+            for (int lev = kt.L - 1; lev >= 0; --lev) hipck(launch_up_level(h, lev, F, (int)R, op.d_xh, st), "up");
+            hipck(launch_coupling_apply(h, F, (int)R, op.d_St, op.d_xh, op.d_yh, st), "coupling");
+            for (int lev = 0; lev < kt.L; ++lev) hipck(launch_down_level(h, lev, F, (int)R, op.d_yh, st), "down");
+        }
+        hipck(launch_leaf_out(a, h, parts, F, (int)R, cv, op.d_xt, op.d_yh, dtype, y, st), "leaf out");
+        return;
+    }
+    const int64_t nfar = (int64_t)op.kfar.size();
+    if (op.profiling) {   // same kernels as the graph, serialised, with events between the phases
+        std::array<hipEvent_t, 5> ev{};
+        for (auto& e : ev) hipck(hipEventCreate(&e), "event");
+        hipck(launch_apply_v3(a, h, op.ls2, op.d_csr_col_dof, parts, F, (int)R, cv, op.d_St, nfar, dtype, x,
+                              op.d_xh, op.d_tmp, y, st, st, nullptr, nullptr, ev.data()), "apply");
+        op.prof_ev.push_back(ev);
+        return;
+    }
+    auto key = std::make_tuple(parts, dtype, x, y, R);
+    auto it = op.graphs.find(key);
+    if (it == op.graphs.end()) {
+        hipStream_t cs = op.stream;
+        hipGraph_t g = nullptr;
+        hipck(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+        hipError_t le = launch_apply_v3(a, h, op.ls2, op.d_csr_col_dof, parts, F, (int)R, cv, op.d_St, nfar, dtype,
+                                        x, op.d_xh, op.d_tmp, y, cs, op.stream2, op.ev_fork, op.ev_join, nullptr);
+        hipError_t ce = hipStreamEndCapture(cs, &g);
+        hipck(le, "apply launch");
+        hipck(ce, "end capture");
+        hipGraphExec_t ex = nullptr;
+        hipck(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate");
+        hipGraphDestroy(g);
+        if (op.graphs.size() > 64) {
+            for (auto& kv : op.graphs) hipGraphExecDestroy(kv.second);
+            op.graphs.clear();
+        }
+        it = op.graphs.emplace(key, ex).first;
+    }
+    hipck(hipGraphLaunch(it->second, st), "graph launch");
 }
 
 }  // namespace
@@ -817,6 +897,9 @@ fpde_status fpde_build(const fpde_mesh* mesh, int32_t n_fields, const double* s,
             int ndev = 0;
             if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(FPDE_EDEVICE, "no HIP device");
             hipck(hipStreamCreateWithFlags(&op->stream, hipStreamNonBlocking), "stream");
+            hipck(hipStreamCreateWithFlags(&op->stream2, hipStreamNonBlocking), "stream");
+            hipck(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming), "event");
+            hipck(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming), "event");
             build_device(*op);
         }
         fill_stats(*op);
@@ -851,6 +934,32 @@ fpde_status fpde_solve(fpde_op* op, const double* Fv, double* u, int64_t nrhs, d
     (void)op; (void)Fv; (void)u; (void)nrhs; (void)rtol; (void)maxit; (void)info; (void)hip_stream;
     g_err = "fpde_solve: not available in this build";
     return FPDE_ESTATE;
+}
+
+fpde_status fpde_profile(fpde_op* op, int32_t enable, fpde_profile_t* out) {
+    return guarded([&] {
+        if (!op) fail(FPDE_EINVAL, "op is NULL");
+        fpde_profile_t acc{};
+        for (auto& ev : op->prof_ev) {
+            hipck(hipEventSynchronize(ev[4]), "event sync");
+            float a = 0, b = 0, c = 0, d = 0, e = 0;
+            hipEventElapsedTime(&a, ev[0], ev[1]);
+            hipEventElapsedTime(&b, ev[1], ev[2]);
+            hipEventElapsedTime(&c, ev[2], ev[3]);
+            hipEventElapsedTime(&d, ev[3], ev[4]);
+            hipEventElapsedTime(&e, ev[0], ev[4]);
+            acc.ms_gather += a;
+            acc.ms_far += b;
+            acc.ms_out += c;
+            acc.ms_far_out += d;
+            acc.ms_total += e;
+            acc.n_applies++;
+            for (auto& e : ev) hipEventDestroy(e);
+        }
+        op->prof_ev.clear();
+        op->profiling = enable != 0;
+        if (out) *out = acc;
+    });
 }
 
 fpde_status fpde_stats(const fpde_op* op, fpde_stats_t* s) {
@@ -949,10 +1058,20 @@ fpde_status fpde_export(const fpde_op* op, int32_t what, int32_t field, void* ds
 
 void fpde_destroy(fpde_op* op) {
     if (!op) return;
+    for (auto& kv : op->graphs) hipGraphExecDestroy(kv.second);
+    op->graphs.clear();
+    for (auto& ev : op->prof_ev)
+        for (auto& e : ev) hipEventDestroy(e);
     if (op->stream) {
         hipStreamSynchronize(op->stream);
         hipStreamDestroy(op->stream);
     }
+    if (op->stream2) {
+        hipStreamSynchronize(op->stream2);
+        hipStreamDestroy(op->stream2);
+    }
+    if (op->ev_fork) hipEventDestroy(op->ev_fork);
+    if (op->ev_join) hipEventDestroy(op->ev_join);
     delete op;
 }
 

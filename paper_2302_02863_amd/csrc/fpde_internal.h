@@ -148,4 +148,46 @@ hipError_t launch_leaf_out(const ApplyPlan& a, const H2Tree& t, int parts, int F
                            const double* csr_val_override, const double* xt, const double* yh,
                            int dtype, void* y, hipStream_t st);
 
+// Far-field apply in five launches: gather + subtree upsweep, top upsweep,
+// coupling with stored S, top downsweep, fused output (see fpde_kernels.hip).
+hipError_t launch_coupling_store(const H2Tree& t, int64_t nfar, const int64_t* far_tgt, int F, double fac,
+                                 double a_scale, double* St, hipStream_t st);
+// ev (optional, 4 events): recorded before the upsweep, after the subtree
+// upsweep (gather included), before and after the output kernel.
+hipError_t launch_apply_fused(const ApplyPlan& a, const H2Tree& t, int ls, int parts, int F, int R,
+                              const double* csr_val, const double* St, int dtype, const void* x, double* xt,
+                              double* xh, double* yh, void* y, hipStream_t st, hipEvent_t* ev);
+hipError_t launch_coupling_apply(const H2Tree& t, int F, int R, const double* St, const double* xh, double* yh,
+                                 hipStream_t st);
+// Fork/join apply: gather; near-field output on st while the far-field chain runs on `side`;
+// join and add the far field.  ev (optional, 5 events, requires side == st): before gather,
+// after gather, after the far chain, after the near output, after the far output.
+hipError_t launch_apply_forkjoin(const ApplyPlan& a, const H2Tree& t, int ls, int parts, int F, int R,
+                                 const double* csr_val, const double* St, int64_t nfar, int dtype, const void* x,
+                                 double* xt, double* xh, double* yh, double* tmp, void* y, hipStream_t st,
+                                 hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+
+// Far-field launch plan: subtree root level ls (LDS-resident subtrees), top
+// level lt (levels <= lt in one LDS-resident block), dynamic LDS sizes.
+struct FarLaunch {
+    int ls, lt;
+    size_t lds_sub, lds_top, lds_down, lds_out;
+};
+bool far_launch_plan(const H2Tree& t, int64_t cap, int ls, int R, FarLaunch* fl);
+hipError_t launch_apply_forkjoin_t(const ApplyPlan& a, const H2Tree& t, const FarLaunch& fl, int parts, int F, int R,
+                                   const double* csr_val, const double* St, int64_t nfar, int dtype, const void* x,
+                                   double* xt, double* xh, double* yh, double* tmp, void* y, hipStream_t st,
+                                   hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+
+bool far_v2_fits(const H2Tree& t, int ls, int R);
+hipError_t launch_apply_v2(const ApplyPlan& a, const H2Tree& t, int ls, const int32_t* csr_col_dof, int parts, int F,
+                           int R, const double* csr_val, const double* St, int dtype, const void* x, double* xh,
+                           double* yh, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork, hipEvent_t join,
+                           hipEvent_t* ev);
+
+hipError_t launch_apply_v3(const ApplyPlan& a, const H2Tree& t, int ls, const int32_t* csr_col_dof, int parts, int F,
+                           int R, const double* csr_val, const double* St, int64_t nfar, int dtype, const void* x,
+                           double* xh, double* tmp, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
+                           hipEvent_t join, hipEvent_t* ev);
+
 }  // namespace fpde

@@ -115,6 +115,12 @@ class Operator:
         check(lib().fpde_export(self._h, code, field, C.c_void_p(out.ctypes.data), C.byref(n)), "fpde_export")
         return out
 
+    def profile(self, enable: bool) -> dict:
+        """Start (enable=True, resets) or stop (enable=False) device-event profiling of apply."""
+        pr = _abi.Profile()
+        check(lib().fpde_profile(self._h, 1 if enable else 0, C.byref(pr)), "fpde_profile")
+        return {name: getattr(pr, name) for name, _ in pr._fields_}
+
     def stats(self) -> dict:
         s = _abi.Stats()
         check(lib().fpde_stats(self._h, C.byref(s)), "fpde_stats")

@@ -136,6 +136,41 @@ def test_many_rhs_fields_and_float32():
     assert np.abs(y32.cpu().numpy() - y64).max() <= 1e-6 * np.abs(y64).max()
 
 
+def test_wide_rhs_fallback_and_profiled_path():
+    """Many right-hand sides take the per-level sweep path; profiling runs the fused launches
+    without the graph.  Both must equal the graph path / oracle."""
+    import paper_2302_02863_amd as fp
+    P, ref, op = _case("square")
+    A = ref["B"] + ref["K"] + ref["M"]
+    rng = np.random.default_rng(9)
+    for R in (40, 3):
+        x = rng.standard_normal((1, op.n_dofs, R))
+        y = _apply(op, x, fp.PART_ALL)[0]
+        yr = A @ x[0]
+        assert np.linalg.norm(y - yr) / np.linalg.norm(yr) < TOL, R
+    y_graph = _apply(op, P.x, fp.PART_ALL)
+    op.profile(True)
+    y_prof = _apply(op, P.x, fp.PART_ALL)
+    pr = op.profile(False)
+    assert pr["n_applies"] == 1 and pr["ms_out"] > 0
+    assert np.array_equal(y_graph, y_prof)
+
+
+def test_top_level_sweeps(monkeypatch):
+    """Force a shallow LDS subtree so the single-block top upsweep/downsweep kernels run."""
+    import paper_2302_02863_amd as fp
+    P = configs.square(16, 8, leaf_size=8, leaf_size_rho=32, cheb_p=3)
+    ref = assemble_h2(P.mesh, P.s[0], P.kappa[0], P.opts)
+    A = ref["B"] + ref["K"] + ref["M"]
+    for depth in ("0", "1"):
+        monkeypatch.setenv("FPDE_MAX_SUBTREE_DEPTH", depth)
+        op = fp.Operator(P.mesh, P.s, P.kappa, P.opts)
+        y = _apply(op, P.x, fp.PART_ALL)[0, :, 0]
+        yr = A @ P.x[0, :, 0]
+        assert np.linalg.norm(y - yr) / np.linalg.norm(yr) < TOL, depth
+        op.close()
+
+
 def test_bitwise_reproducible():
     import paper_2302_02863_amd as fp
     P, ref, op = _case("square")
