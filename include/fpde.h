@@ -167,12 +167,14 @@ fpde_status fpde_solve(fpde_op *op, const double *F, double *u, int64_t nrhs, do
                        int32_t maxit, fpde_solve_info *info, void *hip_stream);
 
 /* Device-time profile of fpde_apply.  While profiling is on, each apply runs
- * the same kernels as its captured graph, serialised on the apply's stream
- * with HIP events between the phases: gather (vectors to tree order), far (H2
- * upsweep, coupling, downsweep), out (CSR + near leaf blocks, the dominant
- * kernel), far_out (downsweep to the leaves and U yh added to y).
- * fpde_profile(op, 1, NULL) resets and starts recording; fpde_profile(op, 0,
- * out) stops, waits for the recorded events and returns the sums. */
+ * the same kernels as its captured graph, serialised on the apply's stream,
+ * with HIP events: far = the H2 chain (upsweep, top levels, coupling), out =
+ * start-to-stop timestamps of the near-field kernel (CSR + near leaf blocks,
+ * the dominant kernel, launched with hipExtLaunchKernelGGL events), far_out =
+ * downsweep walk and U yh added to y, total = whole apply.  ms_gather is 0
+ * (the vectors are read in place).  fpde_profile(op, 1, NULL) resets and
+ * starts recording; fpde_profile(op, 0, out) stops, waits for the recorded
+ * events and returns the sums. */
 typedef struct {
     int64_t n_applies;
     double ms_gather, ms_far, ms_out, ms_far_out, ms_total;

@@ -46,6 +46,28 @@ from .rules import gauss01
 # pair enumeration
 # ----------------------------------------------------------------------------
 
+def canonical_pair(mesh, c, c2):
+    """Kind and canonical vertex tuples of two touching cells (c < c2, or c == c2)."""
+    vc = [int(v) for v in mesh.cells[:, c]]
+    if c == c2:
+        return ("I", tuple(sorted(vc)), tuple(sorted(vc)))
+    v2 = [int(v) for v in mesh.cells[:, c2]]
+    shared = sorted(set(vc) & set(v2))
+    if len(shared) == mesh.dim + 1:
+        raise ValueError("duplicate cell")
+    if mesh.dim == 2 and len(shared) == 2:
+        e0, e1 = shared
+        t0 = [v for v in vc if v not in shared][0]
+        t1 = [v for v in v2 if v not in shared][0]
+        return ("E", (e0, e1, t0), (e0, e1, t1))
+    if len(shared) == 1:
+        P = shared[0]
+        o0 = sorted(v for v in vc if v != P)
+        o1 = sorted(v for v in v2 if v != P)
+        return ("V", (P, *o0), (P, *o1))
+    raise ValueError("unexpected sharing")
+
+
 def touching_pairs(mesh):
     """All touching pairs with at least one interior cell, canonical orientation.
 
@@ -63,28 +85,24 @@ def touching_pairs(mesh):
     for c in range(nc):
         vc = [int(v) for v in cells[c]]
         if interior[c]:
-            out.append(("I", c, c, tuple(sorted(vc)), tuple(sorted(vc))))
+            kind, a, b = canonical_pair(mesh, c, c)
+            out.append((kind, c, c, a, b))
         nbrs = sorted({c2 for v in vc for c2 in node_cells[v] if c2 > c})
         for c2 in nbrs:
             if not (interior[c] or interior[c2]):
                 continue
-            v2 = [int(v) for v in cells[c2]]
-            shared = sorted(set(vc) & set(v2))
-            if len(shared) == mesh.dim + 1:
-                raise ValueError("duplicate cell")
-            if mesh.dim == 2 and len(shared) == 2:
-                e0, e1 = shared
-                t0 = [v for v in vc if v not in shared][0]
-                t1 = [v for v in v2 if v not in shared][0]
-                out.append(("E", c, c2, (e0, e1, t0), (e0, e1, t1)))
-            elif len(shared) == 1:
-                P = shared[0]
-                o0 = sorted(v for v in vc if v != P)
-                o1 = sorted(v for v in v2 if v != P)
-                out.append(("V", c, c2, (P, *o0), (P, *o1)))
-            else:
-                raise ValueError("unexpected sharing")
+            kind, a, b = canonical_pair(mesh, c, c2)
+            out.append((kind, c, c2, a, b))
     return out
+
+
+def pair_local_dofs(mesh, kind, v0, v1):
+    """Local dof list of a canonical pair (order of the local matrices)."""
+    if kind == "I":
+        return list(v0)
+    if kind == "E":
+        return [v0[0], v0[1], v0[2], v1[2]]
+    return list(v0) + list(v1[1:]) if mesh.dim == 2 else [v0[0], v0[1], v1[1]]
 
 
 # ----------------------------------------------------------------------------
@@ -253,6 +271,17 @@ def local_matrix_1d(kind, x0, x1, s0, s1, k0, k1, a_scale, s_bar, n):
     raise ValueError(kind)
 
 
+def pair_matrix(mesh, s, kappa, opts, kind, v0, v1):
+    """Local matrix of a canonical pair (without the pair weight)."""
+    i0 = np.array(v0)
+    i1 = np.array(v1)
+    if mesh.dim == 2:
+        return local_matrix_2d(kind, mesh.coords[:, i0], mesh.coords[:, i1], s[i0], s[i1], kappa[i0], kappa[i1],
+                               opts["a_scale"], opts["s_bar"], opts["nq_sing"])
+    return local_matrix_1d(kind, mesh.coords[0, i0], mesh.coords[0, i1], s[i0], s[i1], kappa[i0], kappa[i1],
+                           opts["a_scale"], opts["s_bar"], opts["nq_sing"])
+
+
 # ----------------------------------------------------------------------------
 # assembly of B
 # ----------------------------------------------------------------------------
@@ -271,12 +300,7 @@ def assemble_B(mesh, s, kappa, opts, all_columns=False, rows=None):
     sb = opts["s_bar"]
     n = opts["nq_sing"]
     for kind, c0, c1, v0, v1 in touching_pairs(mesh):
-        if kind == "I":
-            loc = list(v0)
-        elif kind == "E":
-            loc = [v0[0], v0[1], v0[2], v1[2]]
-        else:
-            loc = list(v0) + list(v1[1:]) if mesh.dim == 2 else [v0[0], v0[1], v1[1]]
+        loc = pair_local_dofs(mesh, kind, v0, v1)
         if want is not None and not (want & set(loc)):
             continue
         i0 = np.array(v0)

@@ -149,6 +149,13 @@ struct fpde_op {
     int ls = 0;                     // subtree-root level of the LDS subtree upsweep (per-level path)
     int ls2 = 0;                    // subtree-root level of the short far chain
     int32_t* d_csr_col_dof = nullptr;   // CSR columns as dof indices
+    // near leaf blocks packed per target leaf: panel[f][poff[li] + row*pstride[li] + col]
+    double* d_panel = nullptr;
+    int64_t *d_poff = nullptr, *d_pstride = nullptr, *d_pcols_ptr = nullptr;
+    int32_t* d_pcols = nullptr;
+    int64_t panel_max_stride = 0, panel_total = 0;
+    unsigned int* d_tickets = nullptr;     // [F] ticket counters of the one-kernel upsweep (self-resetting)
+    int ls3 = -1;                          // subtree-root level of the one-kernel upsweep (-1: unavailable)
     // captured apply graphs keyed by (parts, dtype, x, y, R)
     std::map<std::tuple<int, int, const void*, void*, int64_t>, hipGraphExec_t> graphs;
     // apply workspace
@@ -668,6 +675,34 @@ void build_device(fpde_op& op) {
         op.d_leaf_beg = A.upload(leaf_beg, st);
         op.d_near_ptr = A.upload(near_ptr, st);
         op.d_near_src = A.upload(near_src_leaf, st);
+        {   // panels: columns of each leaf = concatenated source leaves of its near pairs
+            std::vector<int64_t> pcol_off(np.npairs), poff(nleaf + 1, 0), pstride(nleaf), pcols_ptr(nleaf + 1, 0);
+            std::vector<int32_t> pcols;
+            for (int64_t li = 0; li < nleaf; ++li) {
+                int64_t ncol = 0;
+                for (int64_t e = near_ptr[li]; e < near_ptr[li + 1]; ++e) {
+                    const int64_t ls_ = near_src_leaf[e];
+                    pcol_off[e] = ncol;
+                    for (int64_t j = leaf_beg[ls_]; j < leaf_beg[ls_ + 1]; ++j) pcols.push_back((int32_t)j);
+                    ncol += leaf_beg[ls_ + 1] - leaf_beg[ls_];
+                }
+                pcols_ptr[li + 1] = (int64_t)pcols.size();
+                pstride[li] = (ncol + 3) / 4 * 4;
+                poff[li + 1] = poff[li] + op.cap * pstride[li];
+                op.panel_max_stride = std::max(op.panel_max_stride, pstride[li]);
+            }
+            op.panel_total = poff[nleaf];
+            int64_t* d_pcol_off = A.upload(pcol_off, st);
+            op.d_poff = A.upload(poff, st);
+            op.d_pstride = A.upload(pstride, st);
+            op.d_pcols_ptr = A.upload(pcols_ptr, st);
+            op.d_pcols = A.upload(pcols, st);
+            op.d_panel = A.alloc<double>((int64_t)F * op.panel_total);
+            hipck(launch_pack_panels(nleaf, op.cap, np.npairs, op.d_near_ptr, op.d_near_src, op.d_leaf_beg, d_pcol_off,
+                                     op.d_poff, op.d_pstride, op.d_pcols_ptr, op.d_near, F, op.d_panel, st), "pack");
+            hipck(hipStreamSynchronize(st), "pack sync");
+            A.release(d_pcol_off);
+        }
         for (void* q : {(void*)np.tgt, (void*)np.src, (void*)np.patch_ptr, (void*)np.patch_cell,
                         (void*)np.row_ptr, (void*)np.row_lcell, (void*)np.row_slot})
             A.release(q);
@@ -689,6 +724,15 @@ void build_device(fpde_op& op) {
         std::vector<int32_t> cdof(op.csr_col.size());
         for (size_t e = 0; e < cdof.size(); ++e) cdof[e] = (int32_t)kt.perm[op.csr_col[e]];
         op.d_csr_col_dof = A.upload(cdof, st);
+        op.ls3 = -1;
+        for (int l = kt.L; l >= 0; --l)
+            if (up_all_fits(h, op.cap, l)) {
+                op.ls3 = l;
+                break;
+            }
+        op.d_tickets = A.alloc<unsigned int>(F);
+        hipck(hipMemsetAsync(op.d_tickets, 0, sizeof(unsigned int) * F, st), "tickets");
+        hipck(hipStreamSynchronize(st), "tickets sync");
     }
     // keep only what apply / load / export need
     A.release(d_qs);
@@ -787,11 +831,23 @@ void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64
         return;
     }
     const int64_t nfar = (int64_t)op.kfar.size();
+    const bool panels = R == 1 && op.panel_max_stride * 8 <= 64 * 1024;
+    auto launch = [&](hipStream_t s0, hipStream_t s1, hipEvent_t fk, hipEvent_t jn, hipEvent_t* ev) -> hipError_t {
+        if (panels && op.ls3 >= 0)
+            return launch_apply_v5(a, h, op.ls3, op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr,
+                                   op.panel_max_stride, op.d_panel, parts, F, cv, op.d_St, nfar, dtype, x, op.d_xt,
+                                   op.d_xh, op.d_tmp, op.d_tickets, y, s0, s1, fk, jn, ev);
+        if (panels)
+            return launch_apply_v4(a, h, op.ls2, op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr,
+                                   op.panel_max_stride, op.d_panel, parts, F, cv, op.d_St, nfar, dtype, x, op.d_xt,
+                                   op.d_xh, op.d_tmp, y, s0, s1, fk, jn, ev);
+        return launch_apply_v3(a, h, op.ls2, op.d_csr_col_dof, parts, F, (int)R, cv, op.d_St, nfar, dtype, x, op.d_xh,
+                               op.d_tmp, y, s0, s1, fk, jn, ev);
+    };
     if (op.profiling) {   // same kernels as the graph, serialised, with events between the phases
         std::array<hipEvent_t, 5> ev{};
         for (auto& e : ev) hipck(hipEventCreate(&e), "event");
-        hipck(launch_apply_v3(a, h, op.ls2, op.d_csr_col_dof, parts, F, (int)R, cv, op.d_St, nfar, dtype, x,
-                              op.d_xh, op.d_tmp, y, st, st, nullptr, nullptr, ev.data()), "apply");
+        hipck(launch(st, st, nullptr, nullptr, ev.data()), "apply");
         op.prof_ev.push_back(ev);
         return;
     }
@@ -801,8 +857,7 @@ void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64
         hipStream_t cs = op.stream;
         hipGraph_t g = nullptr;
         hipck(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
-        hipError_t le = launch_apply_v3(a, h, op.ls2, op.d_csr_col_dof, parts, F, (int)R, cv, op.d_St, nfar, dtype,
-                                        x, op.d_xh, op.d_tmp, y, cs, op.stream2, op.ev_fork, op.ev_join, nullptr);
+        hipError_t le = launch(cs, op.stream2, op.ev_fork, op.ev_join, nullptr);
         hipError_t ce = hipStreamEndCapture(cs, &g);
         hipck(le, "apply launch");
         hipck(ce, "end capture");
@@ -942,13 +997,12 @@ fpde_status fpde_profile(fpde_op* op, int32_t enable, fpde_profile_t* out) {
         fpde_profile_t acc{};
         for (auto& ev : op->prof_ev) {
             hipck(hipEventSynchronize(ev[4]), "event sync");
-            float a = 0, b = 0, c = 0, d = 0, e = 0;
-            hipEventElapsedTime(&a, ev[0], ev[1]);
-            hipEventElapsedTime(&b, ev[1], ev[2]);
+            // ev0 start, ev1 end of the far chain, ev2/ev3 start/stop of the near-field kernel, ev4 end
+            float b = 0, c = 0, d = 0, e = 0;
+            hipEventElapsedTime(&b, ev[0], ev[1]);
             hipEventElapsedTime(&c, ev[2], ev[3]);
             hipEventElapsedTime(&d, ev[3], ev[4]);
             hipEventElapsedTime(&e, ev[0], ev[4]);
-            acc.ms_gather += a;
             acc.ms_far += b;
             acc.ms_out += c;
             acc.ms_far_out += d;

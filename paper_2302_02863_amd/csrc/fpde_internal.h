@@ -190,4 +190,22 @@ hipError_t launch_apply_v3(const ApplyPlan& a, const H2Tree& t, int ls, const in
                            double* xh, double* tmp, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
                            hipEvent_t join, hipEvent_t* ev);
 
+// Near leaf blocks repacked per target leaf into row-major panels (see fpde_kernels.hip)
+hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const int64_t* near_ptr,
+                              const int64_t* near_src, const int64_t* leaf_beg, const int64_t* pcol_off,
+                              const int64_t* poff, const int64_t* pstride, const int64_t* pcols_ptr, const double* nb,
+                              int F, double* panel, hipStream_t st);
+hipError_t launch_apply_v4(const ApplyPlan& a, const H2Tree& t, int ls, const int64_t* poff, const int64_t* pstride,
+                           const int32_t* pcols, const int64_t* pcols_ptr, int64_t max_stride, const double* panel,
+                           int parts, int F, const double* csr_val, const double* St, int64_t nfar, int dtype,
+                           const void* x, double* xt, double* xh, double* tmp, void* y, hipStream_t st,
+                           hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+
+bool up_all_fits(const H2Tree& t, int64_t cap, int ls);
+hipError_t launch_apply_v5(const ApplyPlan& a, const H2Tree& t, int ls, const int64_t* poff, const int64_t* pstride,
+                           const int32_t* pcols, const int64_t* pcols_ptr, int64_t max_stride, const double* panel,
+                           int parts, int F, const double* csr_val, const double* St, int64_t nfar, int dtype,
+                           const void* x, double* xt, double* xh, double* tmp, unsigned int* tickets, void* y,
+                           hipStream_t st, hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+
 }  // namespace fpde

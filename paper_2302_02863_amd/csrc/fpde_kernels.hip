@@ -5,6 +5,7 @@
 // All floating point here is FP64.  64-wide wavefronts: reductions use
 // cross-lane shuffles; every output element has exactly one writer, so the
 // results are bitwise reproducible from run to run.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -2433,10 +2434,7 @@ hipError_t launch_apply_v3(const ApplyPlan& a, const H2Tree& t, int ls, const in
                            double* xh, double* tmp, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
                            hipEvent_t join, hipEvent_t* ev) {
     const bool far = (parts & 8) != 0;
-    if (ev) {
-        hipEventRecord(ev[0], st);
-        hipEventRecord(ev[1], st);
-    }
+    if (ev) hipEventRecord(ev[0], st);
     hipStream_t fs = st;
     if (far && side != st) {
         hipEventRecord(fork, st);
@@ -2444,17 +2442,345 @@ hipError_t launch_apply_v3(const ApplyPlan& a, const H2Tree& t, int ls, const in
         fs = side;
     }
     if (far) FPDE_DISPATCH_DP(t.dim, t.p, far_v3_t, a, t, ls, F, R, St, nfar, dtype, x, xh, tmp, fs);
-    if (ev) hipEventRecord(ev[2], fs);
+    if (ev) hipEventRecord(ev[1], fs);
     const int64_t nrb = (a.cap + 15) / 16;
-    hipLaunchKernelGGL(k_near_out_v2, dim3((unsigned)(a.nleaf * nrb), F), dim3(256), 0, st, a, csr_col_dof, parts, F, R,
-                       csr_val, dtype, x, y);
-    if (ev) hipEventRecord(ev[3], st);
+    if (ev)   // start/stop timestamps of exactly this kernel
+        hipExtLaunchKernelGGL(k_near_out_v2, dim3((unsigned)(a.nleaf * nrb), F), dim3(256), 0, st, ev[2], ev[3], 0, a,
+                              csr_col_dof, parts, F, R, csr_val, dtype, x, y);
+    else
+        hipLaunchKernelGGL(k_near_out_v2, dim3((unsigned)(a.nleaf * nrb), F), dim3(256), 0, st, a, csr_col_dof, parts,
+                           F, R, csr_val, dtype, x, y);
     if (far) {
         if (fs != st) {
             hipEventRecord(join, fs);
             hipStreamWaitEvent(st, join, 0);
         }
         FPDE_DISPATCH_DP(t.dim, t.p, far_out_v3_t, a, t, F, R, tmp, dtype, y, st);
+    }
+    if (ev) hipEventRecord(ev[4], st);
+    return hipGetLastError();
+}
+
+}  // namespace fpde
+
+// ============================================================ near field as packed leaf panels
+
+namespace fpde {
+
+// Repack the near blocks of each target leaf into one row-major panel
+// panel[f][poff[li] + it*pstride[li] + col], columns = concatenated source leaves.
+FPDE_KERNEL void k_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const int64_t* near_ptr,
+                               const int64_t* near_src, const int64_t* leaf_beg, const int64_t* pcol_off,
+                               const int64_t* poff, const int64_t* pstride, const int64_t* pcols_ptr, const double* nb,
+                               int F, double* panel) {
+    // one block per (leaf, field); threads stride over (row, column)
+    const int64_t li = blockIdx.x;
+    const int f = blockIdx.y;
+    const int64_t nt = leaf_beg[li + 1] - leaf_beg[li];
+    const int64_t ps = pstride[li];
+    for (int64_t e = near_ptr[li]; e < near_ptr[li + 1]; ++e) {
+        const int64_t ls_ = near_src[e];
+        const int64_t ns = leaf_beg[ls_ + 1] - leaf_beg[ls_];
+        const int64_t co = pcol_off[e];
+        const double* blk = nb + ((int64_t)f * npairs + e) * cap * cap;
+        for (int64_t i = threadIdx.x; i < cap * ns; i += blockDim.x) {
+            const int64_t it = i / ns, j = i % ns;
+            panel[(int64_t)f * poff[nleaf] + poff[li] + it * ps + co + j] = it < nt ? blk[it * cap + j] : 0.0;
+        }
+    }
+    // zero the alignment padding of each row
+    const int64_t ncols = pcols_ptr[li + 1] - pcols_ptr[li];
+    for (int64_t i = threadIdx.x; i < cap * (ps - ncols); i += blockDim.x) {
+        const int64_t it = i / (ps - ncols), j = ncols + i % (ps - ncols);
+        panel[(int64_t)f * poff[nleaf] + poff[li] + it * ps + j] = 0.0;
+    }
+}
+
+hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const int64_t* near_ptr,
+                              const int64_t* near_src, const int64_t* leaf_beg, const int64_t* pcol_off,
+                              const int64_t* poff, const int64_t* pstride, const int64_t* pcols_ptr, const double* nb,
+                              int F, double* panel, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack_panels, dim3((unsigned)nleaf, F), dim3(256), 0, st, nleaf, cap, npairs, near_ptr, near_src,
+                       leaf_beg, pcol_off, poff, pstride, pcols_ptr, nb, F, panel);
+    return hipGetLastError();
+}
+
+// y[f][perm[row]] = (B+M)_row . xt + panel_row . xt[cols]; one block per (leaf, 16-row block),
+// one right-hand side.  The leaf's panel columns of x are staged in LDS once per block.
+FPDE_KERNEL void k_near_panel(ApplyPlan a, const int64_t* poff, const int64_t* pstride, const int32_t* pcols,
+                              const int64_t* pcols_ptr, const double* panel, int use_near, const double* csr_val, int F,
+                              const double* xt, int dtype, void* y) {
+    extern __shared__ double xs[];
+    const int f = blockIdx.y;
+    const int64_t nrb = (a.cap + 15) / 16;
+    const int64_t li = blockIdx.x / nrb;
+    const int rb = (int)(blockIdx.x % nrb);
+    const double* xf = xt + (int64_t)f * a.N;
+    const int64_t c0 = pcols_ptr[li], ncols = pcols_ptr[li + 1] - c0;
+    if (use_near)   // padding columns of the row stride hold 0 in the panel and in xs
+        for (int64_t c = threadIdx.x; c < pstride[li]; c += blockDim.x) xs[c] = c < ncols ? xf[pcols[c0 + c]] : 0.0;
+    __syncthreads();
+    const int g = threadIdx.x & 15;
+    const int64_t it = (int64_t)rb * 16 + (threadIdx.x >> 4);
+    const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
+    if (it >= nt) return;
+    const int64_t row = lb + it;
+    double acc = 0.0;
+    if (csr_val) {
+        const double* v = csr_val + (int64_t)f * a.nnz;
+        for (int64_t e = a.csr_ptr[row] + g; e < a.csr_ptr[row + 1]; e += 16) acc += v[e] * xf[a.csr_col[e]];
+    }
+    if (use_near) {
+        const int64_t ps = pstride[li];
+        const double* pr = panel + (int64_t)f * poff[a.nleaf] + poff[li] + it * ps;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int64_t c = 2 * g;
+        // 4 x 16-byte loads per lane in flight
+        for (; c + 96 + 2 <= ps; c += 128) {
+            const double2 p0 = *(const double2*)(pr + c);
+            const double2 p1 = *(const double2*)(pr + c + 32);
+            const double2 p2 = *(const double2*)(pr + c + 64);
+            const double2 p3 = *(const double2*)(pr + c + 96);
+            a0 += p0.x * xs[c] + p0.y * xs[c + 1];
+            a1 += p1.x * xs[c + 32] + p1.y * xs[c + 33];
+            a2 += p2.x * xs[c + 64] + p2.y * xs[c + 65];
+            a3 += p3.x * xs[c + 96] + p3.y * xs[c + 97];
+        }
+        for (; c + 2 <= ps; c += 32) {
+            const double2 p0 = *(const double2*)(pr + c);
+            a0 += p0.x * xs[c] + p0.y * xs[c + 1];
+        }
+        acc += (a0 + a1) + (a2 + a3);
+    }
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    if (g == 0) {
+        const int64_t dst = (int64_t)f * a.N + a.perm[row];
+        if (dtype == 0) ((double*)y)[dst] = acc;
+        else ((float*)y)[dst] = (float)acc;
+    }
+}
+
+hipError_t launch_near_panel(const ApplyPlan& a, const int64_t* poff, const int64_t* pstride, const int32_t* pcols,
+                             const int64_t* pcols_ptr, int64_t max_stride, const double* panel, int use_near,
+                             const double* csr_val, int F, const double* xt, int dtype, void* y, hipStream_t st,
+                             hipEvent_t e0, hipEvent_t e1) {
+    const int64_t nrb = (a.cap + 15) / 16;
+    const size_t lds = sizeof(double) * (max_stride > 0 ? max_stride : 1);
+    if (e0)
+        hipExtLaunchKernelGGL(k_near_panel, dim3((unsigned)(a.nleaf * nrb), F), dim3(256), lds, st, e0, e1, 0, a, poff,
+                              pstride, pcols, pcols_ptr, panel, use_near, csr_val, F, xt, dtype, y);
+    else
+        hipLaunchKernelGGL(k_near_panel, dim3((unsigned)(a.nleaf * nrb), F), dim3(256), lds, st, a, poff, pstride, pcols,
+                           pcols_ptr, panel, use_near, csr_val, F, xt, dtype, y);
+    return hipGetLastError();
+}
+
+// Apply with panels (one right-hand side): main stream gather + panel near field,
+// side stream far chain (x read in place), join, far output.
+hipError_t launch_apply_v4(const ApplyPlan& a, const H2Tree& t, int ls, const int64_t* poff, const int64_t* pstride,
+                           const int32_t* pcols, const int64_t* pcols_ptr, int64_t max_stride, const double* panel,
+                           int parts, int F, const double* csr_val, const double* St, int64_t nfar, int dtype,
+                           const void* x, double* xt, double* xh, double* tmp, void* y, hipStream_t st,
+                           hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev) {
+    const int R = 1;
+    const bool far = (parts & 8) != 0;
+    if (ev) hipEventRecord(ev[0], st);
+    hipStream_t fs = st;
+    if (far && side != st) {
+        hipEventRecord(fork, st);
+        hipStreamWaitEvent(side, fork, 0);
+        fs = side;
+    }
+    if (far) FPDE_DISPATCH_DP(t.dim, t.p, far_v3_t, a, t, ls, F, R, St, nfar, dtype, x, xh, tmp, fs);
+    if (ev) hipEventRecord(ev[1], fs);
+    hipLaunchKernelGGL(k_gather, dim3(grid1((int64_t)F * a.N)), dim3(256), 0, st, a.N, a.perm, F, R, dtype, x, xt);
+    hipError_t e = launch_near_panel(a, poff, pstride, pcols, pcols_ptr, max_stride, panel, (parts & 4) != 0, csr_val, F,
+                                     xt, dtype, y, st, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+    if (e != hipSuccess) return e;
+    if (far) {
+        if (fs != st) {
+            hipEventRecord(join, fs);
+            hipStreamWaitEvent(st, join, 0);
+        }
+        FPDE_DISPATCH_DP(t.dim, t.p, far_out_v3_t, a, t, F, R, tmp, dtype, y, st);
+    }
+    if (ev) hipEventRecord(ev[4], st);
+    return hipGetLastError();
+}
+
+}  // namespace fpde
+
+// ============================================================ apply v5: one-kernel upsweep
+
+namespace fpde {
+
+// Upsweep of the whole tree in one launch.  Block b owns the subtree rooted at
+// cluster (2^ls - 1 + b): leaf coefficients (one lane per coefficient, the
+// leaf's x rows staged in LDS), then the subtree levels in LDS.  Each block
+// publishes its results with a device-scope release fence and takes a ticket;
+// the block holding the last ticket (acquire fence) computes levels ls-1..0 and
+// resets the ticket counter.  No block ever waits for another.
+template <int D, int P>
+__global__ __launch_bounds__(512) void k_up_all(ApplyPlan a, H2Tree t, int ls, int F, int dtype, const void* x,
+                                                double* xh, unsigned int* tickets) {
+    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
+    extern __shared__ double sm[];
+    __shared__ unsigned int s_ticket;
+    const int f = blockIdx.y;
+    const int64_t c = ((int64_t(1) << ls) - 1) + blockIdx.x;
+    const int depth = t.L - ls;
+    const int64_t ncs = (int64_t(2) << depth) - 1;
+    double* sc = sm;                          // [ncs][K]
+    double* sE = sc + ncs * K;                // [ncs][EP]
+    double* sx = sE + ncs * EP;               // [waves][a.cap] x rows of the leaf being processed
+    auto gid = [&](int64_t l) -> int64_t {
+        int lev = 0;
+        while (((int64_t(2) << lev) - 1) <= l) ++lev;
+        const int64_t w = int64_t(1) << lev;
+        return (c + 1) * w - 1 + (l - (w - 1));
+    };
+    for (int64_t i = threadIdx.x; i < ncs * EP; i += blockDim.x) sE[i] = t.E[gid(i / EP) * EP + i % EP];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int64_t nl = int64_t(1) << depth;
+    const int64_t l0 = ((c + 1) << depth) - 1;
+    double* sxw = sx + (int64_t)wv * a.cap;
+    for (int64_t li = wv; li < nl; li += nw) {
+        const int64_t cc = l0 + li;
+        const int64_t rb = t.beg[cc], n = t.end[cc] - rb;
+        for (int64_t j = lane; j < n; j += 64) sxw[j] = ldx(x, (int64_t)f * a.N + a.perm[rb + j], dtype);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // lanes (half, alpha): with K <= 32 the two half-waves split the rows
+        const int half = K <= 32 ? (lane >> 5) : 0;
+        const int al = K <= 32 ? (lane & 31) : lane;
+        const int64_t jb = K <= 32 ? (half ? (n + 1) / 2 : 0) : 0;
+        const int64_t je = K <= 32 ? (half ? n : (n + 1) / 2) : n;
+        double v = 0.0;
+        if (al < K) {
+            const double* u = a.U + rb * K + al;
+            double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            int64_t j = jb;
+            for (; j + 8 <= je; j += 8) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) s[q] += u[(j + q) * K] * sxw[j + q];
+            }
+            for (; j < je; ++j) s[0] += u[j * K] * sxw[j];
+            v = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+        }
+        if (K <= 32) v += __shfl_xor(v, 32, 64);
+        if (lane < K) {
+            sc[(nl - 1 + li) * K + lane] = v;
+            xh[((int64_t)f * t.ncl + cc) * K + lane] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    __syncthreads();
+    for (int lev = t.L - 1; lev >= ls; --lev) {
+        const int64_t w = int64_t(1) << (lev - ls);
+        const int64_t lfirst = w - 1;
+        for (int64_t i = threadIdx.x; i < w * K; i += blockDim.x) {
+            const int64_t lc = lfirst + i / K;
+            const int al = (int)(i % K);
+            const int64_t l1 = 2 * lc + 1, l2 = 2 * lc + 2;
+            const double v = up_t<D, P>(sE + l1 * EP, sE + l2 * EP, sc + l1 * K, sc + l2 * K, al, 1);
+            sc[lc * K + al] = v;
+            xh[((int64_t)f * t.ncl + gid(lc)) * K + al] = v;
+        }
+        __syncthreads();
+    }
+    if (ls == 0) return;
+    // publish, take a ticket
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_ticket = atomicAdd(&tickets[f], 1u);
+    __syncthreads();
+    if (s_ticket != (unsigned int)((int64_t(1) << ls) - 1)) return;
+    __threadfence();
+    if (threadIdx.x == 0) atomicExch(&tickets[f], 0u);
+    // top levels ls-1..0 from every block's level-ls coefficients (LDS reused)
+    const int64_t ntop = (int64_t(2) << ls) - 1;
+    double* tx = sm;                     // [ntop][K]
+    double* tE = tx + ntop * K;          // [ntop][EP]
+    __syncthreads();
+    for (int64_t i = threadIdx.x + ((int64_t(1) << ls) - 1) * K; i < ntop * K; i += blockDim.x)
+        tx[i] = __builtin_nontemporal_load(&xh[(int64_t)f * t.ncl * K + i]);
+    for (int64_t i = threadIdx.x + EP; i < ntop * EP; i += blockDim.x) tE[i] = t.E[i];
+    __syncthreads();
+    for (int lev = ls - 1; lev >= 0; --lev) {
+        const int64_t c0 = (int64_t(1) << lev) - 1, w = int64_t(1) << lev;
+        for (int64_t i = threadIdx.x; i < w * K; i += blockDim.x) {
+            const int64_t cc = c0 + i / K;
+            const int al = (int)(i % K);
+            const int64_t ch1 = 2 * cc + 1, ch2 = 2 * cc + 2;
+            const double v = up_t<D, P>(tE + ch1 * EP, tE + ch2 * EP, tx + ch1 * K, tx + ch2 * K, al, 1);
+            tx[cc * K + al] = v;
+            xh[((int64_t)f * t.ncl + cc) * K + al] = v;
+        }
+        __syncthreads();
+    }
+}
+
+template <int D, int P>
+static void up_all_t(const ApplyPlan& a, const H2Tree& t, int ls, int F, int dtype, const void* x, double* xh,
+                     unsigned int* tickets, hipStream_t fs) {
+    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
+    const int64_t ncs = (int64_t(2) << (t.L - ls)) - 1, ntop = (int64_t(2) << ls) - 1;
+    const int64_t nl = int64_t(1) << (t.L - ls);
+    const int waves = (int)(nl < 8 ? nl : 8);
+    const int64_t sub = ncs * (K + EP) + waves * a.cap, top = ntop * (K + EP);
+    const size_t lds = sizeof(double) * (sub > top ? sub : top);
+    hipLaunchKernelGGL((k_up_all<D, P>), dim3((unsigned)(int64_t(1) << ls), F), dim3(64 * waves), lds, fs, a, t, ls, F,
+                       dtype, x, xh, tickets);
+}
+
+template <int D, int P>
+static void pairs_t(const H2Tree& t, int64_t nfar, int F, const double* St, const double* xh, double* tmp,
+                    hipStream_t fs) {
+    constexpr int K = KR<D, P>::K;
+    if (nfar > 0)
+        hipLaunchKernelGGL((k_coupling_pairs_t<D, P>), dim3(grid1((int64_t)F * nfar * K)), dim3(256), 0, fs, t, nfar, F,
+                           1, St, xh, tmp);
+}
+
+// LDS budget of k_up_all
+bool up_all_fits(const H2Tree& t, int64_t cap, int ls) {
+    const int64_t K = t.k, EP = (int64_t)t.dim * t.p * t.p;
+    const int64_t ncs = (int64_t(2) << (t.L - ls)) - 1, ntop = (int64_t(2) << ls) - 1;
+    const int64_t sub = ncs * (K + EP) + 8 * cap, top = ntop * (K + EP);
+    return (sub > top ? sub : top) * 8 <= 64 * 1024 && K <= 64;
+}
+
+hipError_t launch_apply_v5(const ApplyPlan& a, const H2Tree& t, int ls, const int64_t* poff, const int64_t* pstride,
+                           const int32_t* pcols, const int64_t* pcols_ptr, int64_t max_stride, const double* panel,
+                           int parts, int F, const double* csr_val, const double* St, int64_t nfar, int dtype,
+                           const void* x, double* xt, double* xh, double* tmp, unsigned int* tickets, void* y,
+                           hipStream_t st, hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev) {
+    const bool far = (parts & 8) != 0;
+    if (ev) hipEventRecord(ev[0], st);
+    hipStream_t fs = st;
+    if (far && side != st) {
+        hipEventRecord(fork, st);
+        hipStreamWaitEvent(side, fork, 0);
+        fs = side;
+    }
+    if (far) {
+        FPDE_DISPATCH_DP(t.dim, t.p, up_all_t, a, t, ls, F, dtype, x, xh, tickets, fs);
+        FPDE_DISPATCH_DP(t.dim, t.p, pairs_t, t, nfar, F, St, xh, tmp, fs);
+    }
+    if (ev) hipEventRecord(ev[1], fs);
+    hipLaunchKernelGGL(k_gather, dim3(grid1((int64_t)F * a.N)), dim3(256), 0, st, a.N, a.perm, F, 1, dtype, x, xt);
+    hipError_t e = launch_near_panel(a, poff, pstride, pcols, pcols_ptr, max_stride, panel, (parts & 4) != 0, csr_val, F,
+                                     xt, dtype, y, st, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+    if (e != hipSuccess) return e;
+    if (far) {
+        if (fs != st) {
+            hipEventRecord(join, fs);
+            hipStreamWaitEvent(st, join, 0);
+        }
+        FPDE_DISPATCH_DP(t.dim, t.p, far_out_v3_t, a, t, F, 1, tmp, dtype, y, st);
     }
     if (ev) hipEventRecord(ev[4], st);
     return hipGetLastError();
