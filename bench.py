@@ -60,8 +60,8 @@ def measured_traffic(kernel_name):
     """HBM traffic of the dominant kernel from the committed rocprofv3 counter record,
     valid only while the kernel source is unchanged (else None)."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "traffic_k_near_out_square128.json")
-    src = os.path.join(ROOT, "paper_2302_02863_amd", "csrc", "fpde_kernels.hip")
+    rec_path = os.path.join(ROOT, "profiles", "traffic_k_near_panel_square128.json")
+    src = os.path.join(ROOT, "paper_2302_02863_amd", "csrc", "fpde_near.hip")
     try:
         rec = json.load(open(rec_path))
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()

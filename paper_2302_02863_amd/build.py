@@ -26,6 +26,7 @@ HOST_FLAGS = ["-ffp-contract=off"]
 
 SOURCES = [
     ("fpde_kernels.hip", HIP_FLAGS),
+    ("fpde_near.hip", HIP_FLAGS),
     ("fpde_host.cpp", HOST_FLAGS),
     ("fpde_plan.cpp", HOST_FLAGS),
 ]

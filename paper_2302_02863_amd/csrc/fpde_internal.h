@@ -190,7 +190,11 @@ hipError_t launch_apply_v3(const ApplyPlan& a, const H2Tree& t, int ls, const in
                            double* xh, double* tmp, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
                            hipEvent_t join, hipEvent_t* ev);
 
-// Near leaf blocks repacked per target leaf into row-major panels (see fpde_kernels.hip)
+// Near leaf blocks repacked per target leaf into row-major panels (fpde_near.hip)
+hipError_t launch_near_panel(const ApplyPlan& a, const int64_t* poff, const int64_t* pstride, const int32_t* pcols,
+                             const int64_t* pcols_ptr, int64_t max_stride, const double* panel, int use_near,
+                             const double* csr_val, int F, const double* xt, int dtype, void* y, hipStream_t st,
+                             hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const int64_t* near_ptr,
                               const int64_t* near_src, const int64_t* leaf_beg, const int64_t* pcol_off,
                               const int64_t* poff, const int64_t* pstride, const int64_t* pcols_ptr, const double* nb,
