@@ -107,9 +107,10 @@ typedef struct {
 } fpde_stats_t;
 
 typedef struct {
-    int32_t iterations;      /* CG iterations of the last (or worst) system */
-    double  rel_residual;    /* ||F - A u|| / ||F|| at exit                  */
+    int32_t iterations;      /* CG iterations (worst system, summed over passes) */
+    double  rel_residual;    /* max over systems of ||F - A u|| / ||F|| at exit   */
     int32_t converged;
+    int32_t refinements;     /* iterative-refinement passes                       */
 } fpde_solve_info;
 
 typedef struct fpde_op fpde_op;
@@ -140,6 +141,9 @@ fpde_status fpde_build(const fpde_mesh *mesh, int32_t n_fields, const double *s,
 #define FPDE_PART_KNEAR  0x4
 #define FPDE_PART_KFAR   0x8
 #define FPDE_PART_ALL    0xF
+/* With FPDE_PREC_MIXED: apply with the FP64 operator data instead of the
+ * mixed-precision copies (ignored by an FP64 operator). */
+#define FPDE_PART_FP64   0x10
 
 /* y = A x for F fields and nrhs right-hand sides (Sec. 3: y = (B+M)x + K~x).
  *   dtype     FPDE_F64: x, y are double; FPDE_F32: float
@@ -148,7 +152,8 @@ fpde_status fpde_build(const fpde_mesh *mesh, int32_t n_fields, const double *s,
 fpde_status fpde_apply(fpde_op *op, int32_t dtype, const void *x, void *y, int64_t nrhs,
                        void *hip_stream);
 
-/* As fpde_apply restricted to a subset of FPDE_PART_* (for inspection). */
+/* As fpde_apply restricted to a subset of FPDE_PART_* (for inspection), or
+ * with FPDE_PART_ALL | FPDE_PART_FP64 for the FP64 apply of a mixed operator. */
 fpde_status fpde_apply_parts(fpde_op *op, int32_t parts, int32_t dtype, const void *x, void *y,
                              int64_t nrhs, void *hip_stream);
 
@@ -157,12 +162,23 @@ fpde_status fpde_apply_parts(fpde_op *op, int32_t parts, int32_t dtype, const vo
 fpde_status fpde_load_vector(fpde_op *op, const double *f_nodal, double *F, void *hip_stream);
 
 /* Solve A u = F by conjugate gradients (the paper solves with CG, Sec. 7) for
- * every field and right-hand side.  F, u device [F][N][nrhs] double; u holds
- * the initial guess on entry.  In FPDE_PREC_MIXED the inner CG uses the
- * mixed-precision apply inside an iterative-refinement loop on the FP64
- * residual.  Synchronises hip_stream; info (host, may be NULL) receives the
- * worst system's iteration count and relative residual.
- * Errors: FPDE_ENOCONV when maxit is reached, FPDE_EDEVICE. */
+ * every field and right-hand side, each system independently.
+ *   F, u      device [F][N][nrhs] double, must not alias; u holds the initial
+ *             guess on entry and the solution on exit
+ *   rtol      stop when ||F_s - A u_s||_2 <= rtol ||F_s||_2 for every system s,
+ *             the residual computed with the FP64 apply
+ *   maxit     bound on the total number of CG iterations
+ * The solve is an iterative-refinement loop on the FP64 residual: each pass
+ * runs unpreconditioned CG on A d = r from d = 0 and adds d to u.  An FP64
+ * operator's CG runs to 0.5 rtol in one pass (a second pass only corrects
+ * drift of the recursive residual); an FPDE_PREC_MIXED operator's CG uses the
+ * mixed-precision apply and stops each pass at a relative reduction of 1e-4.
+ * CG iterations run as captured HIP graphs; the host polls convergence every
+ * few iterations.  Synchronises hip_stream.  info (host, may be NULL): total
+ * CG iterations of the worst system summed over passes, final worst relative
+ * residual, converged flag, number of refinement passes.
+ * Errors: FPDE_EINVAL, FPDE_ESTATE (plan-only), FPDE_ENOCONV (maxit reached,
+ * stagnation or breakdown; u and info hold the last iterate), FPDE_EDEVICE. */
 fpde_status fpde_solve(fpde_op *op, const double *F, double *u, int64_t nrhs, double rtol,
                        int32_t maxit, fpde_solve_info *info, void *hip_stream);
 

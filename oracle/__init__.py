@@ -19,7 +19,7 @@ h2         KD cluster tree, admissibility, Chebyshev interpolation; the
            H2-consistent K~ (Sec. 5) and the point-collocation density (Sec. 6.2),
            evaluated entrywise with directly computed (non-nested) bases.
 exterior   analytic density beyond the auxiliary ball (eq. e:rho).
-solve      dense Cholesky / CG solve of the Galerkin system.
+solve      dense Cholesky and textbook CG solves of the Galerkin system (O8).
 
 Parity status of every function is listed in its module header.
 """

@@ -1,0 +1,47 @@
+"""Solves of the Galerkin system A_h u = F (oracle; test infrastructure).
+
+* ``solve_dense``: the discrete solution of Sec. 2 by a dense Cholesky
+  factorisation of the symmetric positive definite A_h (the paper solves the
+  same system with conjugate gradients, Sec. 7; the solution is the same).
+* ``conjugate_gradient``: textbook unpreconditioned CG (Hestenes-Stiefel) on
+  a dense matrix, used to compare iteration counts and stopping behaviour
+  (relative residual ||F - A u|| / ||F||).
+
+Pinned by tests/test_oracle_solve.py: CG and Cholesky agree, the residual of
+both vanishes to rounding, and the closed-form solutions of the fractional
+Laplacian are reproduced (tests/test_oracle_assembly.py).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+
+def solve_dense(A: np.ndarray, F: np.ndarray) -> np.ndarray:
+    """u = A^{-1} F for SPD A (F may hold several right-hand sides as columns)."""
+    c = scipy.linalg.cho_factor(np.asarray(A, dtype=np.float64), lower=True)
+    return scipy.linalg.cho_solve(c, np.asarray(F, dtype=np.float64))
+
+
+def conjugate_gradient(A: np.ndarray, F: np.ndarray, rtol: float = 1e-10, maxit: int = 10000,
+                       u0: np.ndarray | None = None):
+    """Unpreconditioned CG for one right-hand side.  Returns (u, iterations, rel_residual)."""
+    F = np.asarray(F, dtype=np.float64)
+    u = np.zeros_like(F) if u0 is None else np.array(u0, dtype=np.float64)
+    r = F - A @ u
+    p = r.copy()
+    rr = float(r @ r)
+    fn = float(np.sqrt(F @ F))
+    if fn == 0.0:
+        return u, 0, 0.0
+    it = 0
+    while np.sqrt(rr) > rtol * fn and it < maxit:
+        Ap = A @ p
+        alpha = rr / float(p @ Ap)
+        u += alpha * p
+        r -= alpha * Ap
+        rr_new = float(r @ r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+    return u, it, float(np.sqrt(rr)) / fn

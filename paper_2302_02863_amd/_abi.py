@@ -16,7 +16,7 @@ STATUS_NAMES = {0: "FPDE_OK", -1: "FPDE_EINVAL", -2: "FPDE_EDOMAIN", -3: "FPDE_E
 PREC_FP64, PREC_MIXED = 0, 1
 F64, F32 = 0, 1
 FLAG_PLAN_ONLY = 0x1
-PART_B, PART_M, PART_KNEAR, PART_KFAR, PART_ALL = 0x1, 0x2, 0x4, 0x8, 0xF
+PART_B, PART_M, PART_KNEAR, PART_KFAR, PART_ALL, PART_FP64 = 0x1, 0x2, 0x4, 0x8, 0xF, 0x10
 
 EXPORT = dict(CSR_ROWPTR=1, CSR_COLS=2, CSR_B=3, CSR_M=4, K_PERM=5, K_LEAFPTR=6, K_FAR=7, K_NEAR=8,
               RHO_PERM=9, RHO_FAR=10, RHO_NEAR=11, RHO=12, PAIRS=13, K_BOXES=14, RHO_BOXES=15)
@@ -54,7 +54,8 @@ class Profile(C.Structure):
 
 
 class SolveInfo(C.Structure):
-    _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double), ("converged", C.c_int32)]
+    _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double), ("converged", C.c_int32),
+                ("refinements", C.c_int32)]
 
 
 _lib = None

@@ -27,6 +27,9 @@ HOST_FLAGS = ["-ffp-contract=off"]
 SOURCES = [
     ("fpde_kernels.hip", HIP_FLAGS),
     ("fpde_near.hip", HIP_FLAGS),
+    ("fpde_apply.hip", HIP_FLAGS),
+    ("fpde_multi.hip", HIP_FLAGS),
+    ("fpde_solve.hip", HIP_FLAGS),
     ("fpde_host.cpp", HOST_FLAGS),
     ("fpde_plan.cpp", HOST_FLAGS),
 ]

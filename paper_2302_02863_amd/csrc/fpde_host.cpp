@@ -146,26 +146,35 @@ struct fpde_op {
     double* d_U = nullptr;
     double* d_St = nullptr;         // [F][nfar][k][k] coupling matrices (transposed)
     int64_t cap = 0;
-    int ls = 0;                     // subtree-root level of the LDS subtree upsweep (per-level path)
-    int ls2 = 0;                    // subtree-root level of the short far chain
+    int ls2 = 0;                    // subtree-root level of the multi-RHS far chain
     int32_t* d_csr_col_dof = nullptr;   // CSR columns as dof indices
-    // near leaf blocks packed per target leaf: panel[f][poff[li] + row*pstride[li] + col]
+    // near leaf blocks packed per target leaf: panel[f][poff[li] + row*pstride[li] + col], columns dof-indexed
     double* d_panel = nullptr;
     int64_t *d_poff = nullptr, *d_pstride = nullptr, *d_pcols_ptr = nullptr;
     int32_t* d_pcols = nullptr;
     int64_t panel_max_stride = 0, panel_total = 0;
-    unsigned int* d_tickets = nullptr;     // [F] ticket counters of the one-kernel upsweep (self-resetting)
-    int ls3 = -1;                          // subtree-root level of the one-kernel upsweep (-1: unavailable)
+    unsigned int* d_tickets = nullptr;     // [F][ncl] ticket counters of the one-launch upsweep (self-resetting)
+    UpPlan up[2]{};                        // one-launch upsweep plan per precision (0 FP64, 1 FP32)
+    struct {                               // FP32 operator data of a mixed-precision operator
+        float *U = nullptr, *E = nullptr, *St = nullptr, *panel = nullptr;
+        float *xh = nullptr, *tmp = nullptr;   // workspace
+    } f32;
     // captured apply graphs keyed by (parts, dtype, x, y, R)
     std::map<std::tuple<int, int, const void*, void*, int64_t>, hipGraphExec_t> graphs;
+    bool mixed = false;                    // built with FPDE_PREC_MIXED
     // apply workspace
     int64_t ws_R = 0;
     double* d_xt = nullptr;
     double* d_xh = nullptr;
     double* d_yh = nullptr;
-    // solve workspace
-    int64_t sw_n = 0;
-    double *d_r = nullptr, *d_p = nullptr, *d_Ap = nullptr, *d_red = nullptr;
+    // solve workspace ([F][N][R] vectors, per-block partial sums, per-system scalars)
+    int64_t sw_R = 0;
+    double *d_r = nullptr, *d_p = nullptr, *d_Ap = nullptr, *d_d = nullptr, *d_rout = nullptr;
+    double *d_part1 = nullptr, *d_part2 = nullptr, *d_bb = nullptr, *d_rro = nullptr;
+    CgScalars cg{};
+    int* h_nact = nullptr;                    // pinned host copy of the active-system count
+    // captured CG iterations keyed by (precision, R)
+    std::map<std::pair<int, int64_t>, hipGraphExec_t> cg_graphs;
     fpde_stats_t stats{};
     // profiling: events recorded per apply (gather begin, gather end, far end, out end)
     bool profiling = false;
@@ -683,7 +692,7 @@ void build_device(fpde_op& op) {
                 for (int64_t e = near_ptr[li]; e < near_ptr[li + 1]; ++e) {
                     const int64_t ls_ = near_src_leaf[e];
                     pcol_off[e] = ncol;
-                    for (int64_t j = leaf_beg[ls_]; j < leaf_beg[ls_ + 1]; ++j) pcols.push_back((int32_t)j);
+                    for (int64_t j = leaf_beg[ls_]; j < leaf_beg[ls_ + 1]; ++j) pcols.push_back((int32_t)kt.perm[j]);
                     ncol += leaf_beg[ls_ + 1] - leaf_beg[ls_];
                 }
                 pcols_ptr[li + 1] = (int64_t)pcols.size();
@@ -707,31 +716,37 @@ void build_device(fpde_op& op) {
                         (void*)np.row_ptr, (void*)np.row_lcell, (void*)np.row_slot})
             A.release(q);
         op.stats.t_near_blocks_ms = tm2.stop();
-        // deepest subtree whose U rows fit the 64 KB LDS budget of the fused upsweep (R = 1)
-        int depth = 0;
-        int max_depth = kt.L;
-        if (const char* env = std::getenv("FPDE_MAX_SUBTREE_DEPTH")) max_depth = std::min(max_depth, std::atoi(env));
-        while (depth < max_depth) {
-            const int64_t rows = (int64_t(1) << (depth + 1)) * op.cap;
-            const int64_t ncl_sub = (int64_t(2) << (depth + 1)) - 1;
-            if ((rows * k + rows + ncl_sub * k + ncl_sub * d * p * p) * 8 > 64 * 1024) break;
-            ++depth;
-        }
-        op.ls = kt.L - depth;
-        // short far chain: deepest subtree-root level whose top tree fits one block's LDS
-        op.ls2 = kt.L;
-        while (op.ls2 > 0 && !far_v2_fits(h, op.ls2, 1)) --op.ls2;
         std::vector<int32_t> cdof(op.csr_col.size());
         for (size_t e = 0; e < cdof.size(); ++e) cdof[e] = (int32_t)kt.perm[op.csr_col[e]];
         op.d_csr_col_dof = A.upload(cdof, st);
-        op.ls3 = -1;
-        for (int l = kt.L; l >= 0; --l)
-            if (up_all_fits(h, op.cap, l)) {
-                op.ls3 = l;
-                break;
-            }
-        op.d_tickets = A.alloc<unsigned int>(F);
-        hipck(hipMemsetAsync(op.d_tickets, 0, sizeof(unsigned int) * F, st), "tickets");
+        // launch plans: the one-launch upsweep of the single-vector apply (per
+        // precision) and the subtree-root level of the multi-RHS far chain.
+        // FPDE_MAX_SUBTREE_DEPTH caps the subtree depths (exercises the deep
+        // ticket chains and top sweeps on small trees).
+        int max_depth = kt.L;
+        if (const char* env = std::getenv("FPDE_MAX_SUBTREE_DEPTH"))
+            max_depth = std::max(0, std::min(max_depth, std::atoi(env)));
+        for (int pr = 0; pr < 2; ++pr) {
+            UpPlan u = plan_up_tree(h, op.cap, pr);
+            u.d0 = std::min(u.d0, max_depth);
+            u.ds = std::max(1, std::min(u.ds, max_depth));
+            op.up[pr] = u;
+        }
+        op.ls2 = kt.L;
+        while (op.ls2 > 0 && !multi_fits(h, op.ls2, 1)) --op.ls2;
+        op.d_tickets = A.alloc<unsigned int>((int64_t)F * kt.ncl);
+        hipck(hipMemsetAsync(op.d_tickets, 0, sizeof(unsigned int) * F * kt.ncl, st), "tickets");
+        if (op.mixed) {   // FP32 copies of the bases, transfers, coupling matrices and panels
+            const int64_t nU = m.N * k, nE = kt.ncl * (int64_t)d * p * p, nS = (int64_t)F * op.kfar.size() * k * k;
+            op.f32.U = A.alloc<float>(nU);
+            op.f32.E = A.alloc<float>(nE);
+            op.f32.St = A.alloc<float>(nS);
+            op.f32.panel = A.alloc<float>((int64_t)F * op.panel_total);
+            hipck(launch_to_float(nU, op.d_U, op.f32.U, st), "to float");
+            hipck(launch_to_float(nE, op.kdev.E, op.f32.E, st), "to float");
+            if (nS > 0) hipck(launch_to_float(nS, op.d_St, op.f32.St, st), "to float");
+            hipck(launch_to_float((int64_t)F * op.panel_total, op.d_panel, op.f32.panel, st), "to float");
+        }
         hipck(hipStreamSynchronize(st), "tickets sync");
     }
     // keep only what apply / load / export need
@@ -780,19 +795,24 @@ void ensure_ws(fpde_op& op, int64_t R) {
         op.arena.release(op.d_xt); op.arena.release(op.d_xh); op.arena.release(op.d_yh); op.arena.release(op.d_tmp);
         for (auto& kv : op.graphs) hipGraphExecDestroy(kv.second);
         op.graphs.clear();
+        for (auto& kv : op.cg_graphs) hipGraphExecDestroy(kv.second);
+        op.cg_graphs.clear();
     }
     op.d_tmp = op.arena.alloc<double>((int64_t)op.F * std::max<size_t>(1, op.kfar.size()) * k * R);
     op.d_xt = op.arena.alloc<double>((int64_t)op.F * (op.mesh.N + op.cap) * R);
     op.d_xh = op.arena.alloc<double>((int64_t)op.F * op.kt.ncl * k * R);
     op.d_yh = op.arena.alloc<double>((int64_t)op.F * op.kt.ncl * k * R);
+    if (op.mixed && !op.f32.xh) {   // single-vector FP32 workspace
+        op.f32.xh = op.arena.alloc<float>((int64_t)op.F * op.kt.ncl * k);
+        op.f32.tmp = op.arena.alloc<float>((int64_t)op.F * std::max<size_t>(1, op.kfar.size()) * k);
+    }
     op.ws_R = R;
 }
 
-void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64_t R, hipStream_t st) {
-    if (op.plan_only) fail(FPDE_ESTATE, "operator was built with FPDE_FLAG_PLAN_ONLY");
-    if (dtype != FPDE_F64 && dtype != FPDE_F32) fail(FPDE_EINVAL, "dtype must be FPDE_F64 or FPDE_F32");
-    if (R < 1 || !x || !y) fail(FPDE_EINVAL, "bad vectors");
-    ensure_ws(op, R);
+// Enqueue one apply on s0 (far chain forked to s1 through fk/jn when s1 != s0).
+// ev: optional 5 profiling events (requires s1 == s0).  Capturable.
+hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void* y, int64_t R, hipStream_t s0,
+                         hipStream_t s1, hipEvent_t fk, hipEvent_t jn, hipEvent_t* ev) {
     const int F = op.F, p = op.opts.cheb_p;
     const Tree& kt = op.kt;
     H2Tree h = make_h2(kt, op.kdev, p);
@@ -817,37 +837,48 @@ void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64
     if ((parts & FPDE_PART_B) && (parts & FPDE_PART_M)) cv = op.d_BM;
     else if (parts & FPDE_PART_B) cv = op.d_B;
     else if (parts & FPDE_PART_M) cv = op.d_M;
-    // the short far chain keeps subtrees and the top tree in LDS; wide R falls back to per-level sweeps
-    const bool v2 = far_v2_fits(h, op.ls2, (int)R);
-    if (!v2) {
-        hipck(launch_gather(a, F, (int)R, dtype, x, op.d_xt, st), "gather");
-        if (parts & FPDE_PART_KFAR) {
-            hipck(launch_leaf_up(a, h, F, (int)R, op.d_xt, op.d_xh, st), "leaf up");
-            for (int lev = kt.L - 1; lev >= 0; --lev) hipck(launch_up_level(h, lev, F, (int)R, op.d_xh, st), "up");
-            hipck(launch_coupling_apply(h, F, (int)R, op.d_St, op.d_xh, op.d_yh, st), "coupling");
-            for (int lev = 0; lev < kt.L; ++lev) hipck(launch_down_level(h, lev, F, (int)R, op.d_yh, st), "down");
-        }
-        hipck(launch_leaf_out(a, h, parts, F, (int)R, cv, op.d_xt, op.d_yh, dtype, y, st), "leaf out");
-        return;
-    }
     const int64_t nfar = (int64_t)op.kfar.size();
-    const bool panels = R == 1 && op.panel_max_stride * 8 <= 64 * 1024;
-    auto launch = [&](hipStream_t s0, hipStream_t s1, hipEvent_t fk, hipEvent_t jn, hipEvent_t* ev) -> hipError_t {
-        if (panels && op.ls3 >= 0)
-            return launch_apply_v5(a, h, op.ls3, op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr,
-                                   op.panel_max_stride, op.d_panel, parts, F, cv, op.d_St, nfar, dtype, x, op.d_xt,
-                                   op.d_xh, op.d_tmp, op.d_tickets, y, s0, s1, fk, jn, ev);
-        if (panels)
-            return launch_apply_v4(a, h, op.ls2, op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr,
-                                   op.panel_max_stride, op.d_panel, parts, F, cv, op.d_St, nfar, dtype, x, op.d_xt,
-                                   op.d_xh, op.d_tmp, y, s0, s1, fk, jn, ev);
-        return launch_apply_v3(a, h, op.ls2, op.d_csr_col_dof, parts, F, (int)R, cv, op.d_St, nfar, dtype, x, op.d_xh,
-                               op.d_tmp, y, s0, s1, fk, jn, ev);
-    };
+    const bool f32 = op.mixed && !(parts & FPDE_PART_FP64);
+    const int pr = f32 ? 1 : 0;
+    const size_t esz = f32 ? sizeof(float) : sizeof(double);
+    if (R == 1 && op.up[pr].ok && op.panel_max_stride * (int64_t)esz <= 64 * 1024) {
+        PanelPlan pp{op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr, op.panel_max_stride, op.d_csr_col_dof};
+        if (f32) {
+            OpData<float> od{op.f32.U, op.f32.E, op.f32.St, op.f32.panel, op.f32.xh, op.f32.tmp};
+            return launch_apply_single(a, h, pp, op.up[1], parts, F, cv, nfar, od, dtype, x, y, op.d_tickets, s0, s1,
+                                       fk, jn, ev);
+        }
+        OpData<double> od{op.d_U, op.kdev.E, op.d_St, op.d_panel, op.d_xh, op.d_tmp};
+        return launch_apply_single(a, h, pp, op.up[0], parts, F, cv, nfar, od, dtype, x, y, op.d_tickets, s0, s1, fk,
+                                   jn, ev);
+    }
+    // several right-hand sides (FP64 data): LDS-resident subtrees and top tree
+    if (multi_fits(h, op.ls2, (int)R))
+        return launch_apply_multi(a, h, op.ls2, op.d_csr_col_dof, parts, F, (int)R, cv, op.d_St, nfar, dtype, x,
+                                  op.d_xh, op.d_tmp, y, s0, s1, fk, jn, ev);
+    // wide R: per-level sweeps, one stream
+    hipError_t e = launch_gather(a, F, (int)R, dtype, x, op.d_xt, s0);
+    if (e != hipSuccess) return e;
+    if (parts & FPDE_PART_KFAR) {
+        if ((e = launch_leaf_up(a, h, F, (int)R, op.d_xt, op.d_xh, s0)) != hipSuccess) return e;
+        for (int lev = kt.L - 1; lev >= 0; --lev)
+            if ((e = launch_up_level(h, lev, F, (int)R, op.d_xh, s0)) != hipSuccess) return e;
+        if ((e = launch_coupling_apply(h, F, (int)R, op.d_St, op.d_xh, op.d_yh, s0)) != hipSuccess) return e;
+        for (int lev = 0; lev < kt.L; ++lev)
+            if ((e = launch_down_level(h, lev, F, (int)R, op.d_yh, s0)) != hipSuccess) return e;
+    }
+    return launch_leaf_out(a, h, parts, F, (int)R, cv, op.d_xt, op.d_yh, dtype, y, s0);
+}
+
+void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64_t R, hipStream_t st) {
+    if (op.plan_only) fail(FPDE_ESTATE, "operator was built with FPDE_FLAG_PLAN_ONLY");
+    if (dtype != FPDE_F64 && dtype != FPDE_F32) fail(FPDE_EINVAL, "dtype must be FPDE_F64 or FPDE_F32");
+    if (R < 1 || !x || !y) fail(FPDE_EINVAL, "bad vectors");
+    ensure_ws(op, R);
     if (op.profiling) {   // same kernels as the graph, serialised, with events between the phases
         std::array<hipEvent_t, 5> ev{};
         for (auto& e : ev) hipck(hipEventCreate(&e), "event");
-        hipck(launch(st, st, nullptr, nullptr, ev.data()), "apply");
+        hipck(enqueue_apply(op, parts, dtype, x, y, R, st, st, nullptr, nullptr, ev.data()), "apply");
         op.prof_ev.push_back(ev);
         return;
     }
@@ -857,7 +888,7 @@ void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64
         hipStream_t cs = op.stream;
         hipGraph_t g = nullptr;
         hipck(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
-        hipError_t le = launch(cs, op.stream2, op.ev_fork, op.ev_join, nullptr);
+        hipError_t le = enqueue_apply(op, parts, dtype, x, y, R, cs, op.stream2, op.ev_fork, op.ev_join, nullptr);
         hipError_t ce = hipStreamEndCapture(cs, &g);
         hipck(le, "apply launch");
         hipck(ce, "end capture");
@@ -871,6 +902,168 @@ void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64
         it = op.graphs.emplace(key, ex).first;
     }
     hipck(hipGraphLaunch(it->second, st), "graph launch");
+}
+
+// ------------------------------------------------------------------ CG solve and iterative refinement
+
+void ensure_solve_ws(fpde_op& op, int64_t R) {
+    if (op.sw_R >= R) return;
+    Arena& A = op.arena;
+    for (void* q : {(void*)op.d_r, (void*)op.d_p, (void*)op.d_Ap, (void*)op.d_d, (void*)op.d_rout,
+                    (void*)op.d_part1, (void*)op.d_part2, (void*)op.d_bb, (void*)op.d_rro, (void*)op.cg.rr,
+                    (void*)op.cg.alpha, (void*)op.cg.beta, (void*)op.cg.tol2, (void*)op.cg.active,
+                    (void*)op.cg.iters, (void*)op.cg.flags, (void*)op.cg.n_active})
+        if (q) A.release(q);
+    for (auto& kv : op.cg_graphs) hipGraphExecDestroy(kv.second);
+    op.cg_graphs.clear();
+    const int64_t n = (int64_t)op.F * op.mesh.N * R, S = (int64_t)op.F * R;
+    const int64_t nb = cg_row_blocks(op.mesh.N, (int)R);
+    op.d_r = A.alloc<double>(n);
+    op.d_p = A.alloc<double>(n);
+    op.d_Ap = A.alloc<double>(n);
+    op.d_d = A.alloc<double>(n);
+    op.d_rout = A.alloc<double>(n);
+    op.d_part1 = A.alloc<double>(op.F * nb * R);
+    op.d_part2 = A.alloc<double>(op.F * nb * R);
+    op.d_bb = A.alloc<double>(S);
+    op.d_rro = A.alloc<double>(S);
+    op.cg.rr = A.alloc<double>(S);
+    op.cg.alpha = A.alloc<double>(S);
+    op.cg.beta = A.alloc<double>(S);
+    op.cg.tol2 = A.alloc<double>(S);
+    op.cg.active = A.alloc<int>(S);
+    op.cg.iters = A.alloc<int>(S);
+    op.cg.flags = A.alloc<int>(S);
+    op.cg.n_active = A.alloc<int>(1);
+    if (!op.h_nact) hipck(hipHostMalloc((void**)&op.h_nact, sizeof(int), hipHostMallocDefault), "pinned");
+    op.sw_R = R;
+}
+
+// One CG iteration on the system A d = rout (apply of precision `mixed`):
+// Ap = A p; alpha = |r|^2 / p.Ap; d += alpha p; r -= alpha Ap; beta; p = r + beta p.
+hipError_t enqueue_cg_iteration(fpde_op& op, bool mixed, int64_t R, hipStream_t s0, hipStream_t s1) {
+    const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
+    const int parts = mixed ? FPDE_PART_ALL : (FPDE_PART_ALL | FPDE_PART_FP64);
+    hipError_t e = enqueue_apply(op, parts, FPDE_F64, op.d_p, op.d_Ap, R, s0, s1, op.ev_fork, op.ev_join, nullptr);
+    if (e != hipSuccess) return e;
+    if ((e = launch_cg_rowblock(0, dm, op.d_p, op.d_Ap, nullptr, nullptr, nullptr, nullptr, op.d_part1, nullptr,
+                                s0)) != hipSuccess) return e;
+    if ((e = launch_cg_alpha(dm, op.d_part1, op.cg, s0)) != hipSuccess) return e;
+    if ((e = launch_cg_rowblock(1, dm, op.d_p, op.d_Ap, op.cg.alpha, op.d_d, op.d_r, nullptr, op.d_part1, nullptr,
+                                s0)) != hipSuccess) return e;
+    if ((e = launch_cg_beta(dm, op.d_part1, op.cg, s0)) != hipSuccess) return e;
+    return launch_cg_p(dm, op.cg, op.d_r, op.d_p, s0);
+}
+
+hipGraphExec_t cg_graph(fpde_op& op, bool mixed, int64_t R) {
+    auto key = std::make_pair(mixed ? 1 : 0, R);
+    auto it = op.cg_graphs.find(key);
+    if (it != op.cg_graphs.end()) return it->second;
+    hipGraph_t g = nullptr;
+    hipck(hipStreamBeginCapture(op.stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t le = enqueue_cg_iteration(op, mixed, R, op.stream, op.stream2);
+    hipError_t ce = hipStreamEndCapture(op.stream, &g);
+    hipck(le, "cg iteration launch");
+    hipck(ce, "end capture");
+    hipGraphExec_t ex = nullptr;
+    hipck(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate");
+    hipGraphDestroy(g);
+    op.cg_graphs.emplace(key, ex);
+    return ex;
+}
+
+// CG on A d = rout from d = 0 until |r_s| <= max(tau_in |rout_s|, rtol_abs_s) for every
+// system s (rtol_abs_s = rtol |b_s|, |b_s|^2 in d_bb).  Returns the largest
+// per-system iteration count; *breakdown is set if a system lost positivity.
+int cg_run(fpde_op& op, bool mixed, int64_t R, double tau_in, double rtol, int maxit, hipStream_t st,
+           bool* breakdown) {
+    const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
+    const int64_t S = (int64_t)op.F * R;
+    hipck(launch_cg_rowblock(3, dm, nullptr, op.d_rout, nullptr, op.d_d, op.d_r, op.d_p, op.d_part1, nullptr, st),
+          "cg start");
+    hipck(launch_cg_start(dm, op.d_part1, op.d_bb, tau_in, rtol, op.cg, st), "cg start");
+    hipck(hipMemcpyAsync(op.h_nact, op.cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
+    hipck(hipStreamSynchronize(st), "sync");
+    *breakdown = false;
+    if (*op.h_nact == 0) return 0;
+    hipGraphExec_t g = cg_graph(op, mixed, R);
+    int it = 0, chunk = 4;
+    while (it < maxit) {
+        const int n = std::min(chunk, maxit - it);
+        for (int j = 0; j < n; ++j) hipck(hipGraphLaunch(g, st), "cg graph launch");
+        it += n;
+        hipck(hipMemcpyAsync(op.h_nact, op.cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
+        hipck(hipStreamSynchronize(st), "sync");
+        if (*op.h_nact == 0) break;
+        chunk = std::min(chunk * 2, 32);
+    }
+    std::vector<int> iters(S), flags(S);
+    hipck(hipMemcpy(iters.data(), op.cg.iters, sizeof(int) * S, hipMemcpyDeviceToHost), "copy");
+    hipck(hipMemcpy(flags.data(), op.cg.flags, sizeof(int) * S, hipMemcpyDeviceToHost), "copy");
+    for (int f : flags) if (f) *breakdown = true;
+    return *std::max_element(iters.begin(), iters.end());
+}
+
+// rout = b - A_fp64 u, per-system |rout|^2 (d_rro) and |b|^2 (d_bb); returns max_s |rout_s| / |b_s|
+double outer_residual(fpde_op& op, const double* b, double* u, int64_t R, hipStream_t st) {
+    const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
+    const int64_t S = (int64_t)op.F * R;
+    apply_impl(op, FPDE_PART_ALL | FPDE_PART_FP64, FPDE_F64, u, op.d_Ap, R, st);
+    hipck(launch_cg_rowblock(2, dm, op.d_Ap, b, nullptr, nullptr, op.d_rout, nullptr, op.d_part1, op.d_part2, st),
+          "residual");
+    hipck(launch_cg_sum2(dm, op.d_part1, op.d_part2, op.d_rro, op.d_bb, st), "residual norms");
+    std::vector<double> rr(S), bb(S);
+    hipck(hipMemcpyAsync(rr.data(), op.d_rro, sizeof(double) * S, hipMemcpyDeviceToHost, st), "copy");
+    hipck(hipMemcpyAsync(bb.data(), op.d_bb, sizeof(double) * S, hipMemcpyDeviceToHost, st), "copy");
+    hipck(hipStreamSynchronize(st), "sync");
+    double worst = 0.0;
+    for (int64_t s = 0; s < S; ++s) {
+        const double rel = bb[s] > 0.0 ? std::sqrt(rr[s] / bb[s]) : (rr[s] > 0.0 ? INFINITY : 0.0);
+        if (!(rel <= worst)) worst = rel;   // NaN propagates
+    }
+    return worst;
+}
+
+// Inner relative tolerance of the mixed-precision CG inside the refinement loop.
+constexpr double kMixedInnerTol = 1e-4;
+constexpr int kMaxRefinements = 60;
+
+void solve_impl(fpde_op& op, const double* b, double* u, int64_t R, double rtol, int maxit, fpde_solve_info* info,
+                hipStream_t st) {
+    if (op.plan_only) fail(FPDE_ESTATE, "operator was built with FPDE_FLAG_PLAN_ONLY");
+    if (!b || !u || R < 1) fail(FPDE_EINVAL, "bad vectors");
+    if (!(rtol > 0.0) || maxit < 1) fail(FPDE_EINVAL, "need rtol > 0 and maxit >= 1");
+    ensure_ws(op, R);
+    ensure_solve_ws(op, R);
+    const int64_t n = (int64_t)op.F * op.mesh.N * R;
+    int total = 0, outer = 0;
+    bool breakdown = false;
+    double worst = outer_residual(op, b, u, R, st), best = worst;
+    int stalls = 0;
+    while (worst > rtol && total < maxit && outer < kMaxRefinements) {
+        const double tau = op.mixed ? kMixedInnerTol : 0.0;
+        bool bd = false;
+        total += cg_run(op, op.mixed, R, tau, 0.5 * rtol, maxit - total, st, &bd);
+        breakdown = breakdown || bd;
+        hipck(launch_vec_add(n, op.d_d, u, st), "update");
+        worst = outer_residual(op, b, u, R, st);
+        ++outer;
+        if (worst < 0.5 * best) {
+            best = worst;
+            stalls = 0;
+        } else if (++stalls >= 3) {
+            break;
+        }
+    }
+    if (info) {
+        info->iterations = total;
+        info->rel_residual = worst;
+        info->converged = worst <= rtol ? 1 : 0;
+        info->refinements = outer;
+    }
+    if (!(worst <= rtol))
+        fail(FPDE_ENOCONV, breakdown ? "fpde_solve: CG breakdown (operator not positive definite in working precision)"
+                                     : "fpde_solve: not converged within maxit / refinement limit");
 }
 
 }  // namespace
@@ -936,6 +1129,7 @@ fpde_status fpde_build(const fpde_mesh* mesh, int32_t n_fields, const double* s,
         op->opts = o;
         op->F = n_fields;
         op->plan_only = (o.flags & FPDE_FLAG_PLAN_ONLY) != 0;
+        op->mixed = o.precision == FPDE_PREC_MIXED;
         HostMesh& m = op->mesh;
         m.dim = mesh->dim;
         m.M = mesh->n_nodes;
@@ -986,9 +1180,10 @@ fpde_status fpde_load_vector(fpde_op* op, const double* f_nodal, double* F, void
 
 fpde_status fpde_solve(fpde_op* op, const double* Fv, double* u, int64_t nrhs, double rtol, int32_t maxit,
                        fpde_solve_info* info, void* hip_stream) {
-    (void)op; (void)Fv; (void)u; (void)nrhs; (void)rtol; (void)maxit; (void)info; (void)hip_stream;
-    g_err = "fpde_solve: not available in this build";
-    return FPDE_ESTATE;
+    return guarded([&] {
+        if (!op) fail(FPDE_EINVAL, "op is NULL");
+        solve_impl(*op, Fv, u, nrhs, rtol, maxit, info, (hipStream_t)hip_stream);
+    });
 }
 
 fpde_status fpde_profile(fpde_op* op, int32_t enable, fpde_profile_t* out) {
@@ -1114,6 +1309,9 @@ void fpde_destroy(fpde_op* op) {
     if (!op) return;
     for (auto& kv : op->graphs) hipGraphExecDestroy(kv.second);
     op->graphs.clear();
+    for (auto& kv : op->cg_graphs) hipGraphExecDestroy(kv.second);
+    op->cg_graphs.clear();
+    if (op->h_nact) hipHostFree(op->h_nact);
     for (auto& ev : op->prof_ev)
         for (auto& e : ev) hipEventDestroy(e);
     if (op->stream) {

@@ -148,68 +148,98 @@ hipError_t launch_leaf_out(const ApplyPlan& a, const H2Tree& t, int parts, int F
                            const double* csr_val_override, const double* xt, const double* yh,
                            int dtype, void* y, hipStream_t st);
 
-// Far-field apply in five launches: gather + subtree upsweep, top upsweep,
-// coupling with stored S, top downsweep, fused output (see fpde_kernels.hip).
 hipError_t launch_coupling_store(const H2Tree& t, int64_t nfar, const int64_t* far_tgt, int F, double fac,
                                  double a_scale, double* St, hipStream_t st);
-// ev (optional, 4 events): recorded before the upsweep, after the subtree
-// upsweep (gather included), before and after the output kernel.
-hipError_t launch_apply_fused(const ApplyPlan& a, const H2Tree& t, int ls, int parts, int F, int R,
-                              const double* csr_val, const double* St, int dtype, const void* x, double* xt,
-                              double* xh, double* yh, void* y, hipStream_t st, hipEvent_t* ev);
+// yh[f][c] = sum_{e in far(c)} S_e xh[f][src(e)]  (per-level fallback)
 hipError_t launch_coupling_apply(const H2Tree& t, int F, int R, const double* St, const double* xh, double* yh,
                                  hipStream_t st);
-// Fork/join apply: gather; near-field output on st while the far-field chain runs on `side`;
-// join and add the far field.  ev (optional, 5 events, requires side == st): before gather,
-// after gather, after the far chain, after the near output, after the far output.
-hipError_t launch_apply_forkjoin(const ApplyPlan& a, const H2Tree& t, int ls, int parts, int F, int R,
-                                 const double* csr_val, const double* St, int64_t nfar, int dtype, const void* x,
-                                 double* xt, double* xh, double* yh, double* tmp, void* y, hipStream_t st,
-                                 hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+hipError_t launch_to_float(int64_t n, const double* src, float* dst, hipStream_t st);
 
-// Far-field launch plan: subtree root level ls (LDS-resident subtrees), top
-// level lt (levels <= lt in one LDS-resident block), dynamic LDS sizes.
-struct FarLaunch {
-    int ls, lt;
-    size_t lds_sub, lds_top, lds_down, lds_out;
+// ---------------------------------------------------------------- apply, several right-hand sides (fpde_multi.hip)
+
+// LDS needed by the multi-RHS far chain with subtree roots at level ls
+bool multi_fits(const H2Tree& t, int ls, int R);
+// main stream: CSR + near blocks in place; side stream: upsweep, top levels,
+// coupling products; join; per-leaf downsweep fused with the output (FP64).
+// ev (optional, 5 events, side == st): start, far chain end, near kernel
+// start/stop, end.
+hipError_t launch_apply_multi(const ApplyPlan& a, const H2Tree& t, int ls, const int32_t* csr_col_dof, int parts,
+                              int F, int R, const double* csr_val, const double* St, int64_t nfar, int dtype,
+                              const void* x, double* xh, double* tmp, void* y, hipStream_t st, hipStream_t side,
+                              hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+
+// ---------------------------------------------------------------- apply, one right-hand side (fpde_apply.hip)
+
+// Near leaf blocks packed per target leaf into row-major panels
+// panel[f][poff[li] + row * pstride[li] + col]; columns are dof indices.
+struct PanelPlan {
+    const int64_t* poff;        // [nleaf+1]
+    const int64_t* pstride;     // [nleaf] row stride (multiple of 4)
+    const int32_t* pcols;       // [pcols_ptr[nleaf]] dof of each panel column
+    const int64_t* pcols_ptr;   // [nleaf+1]
+    int64_t max_stride;
+    const int32_t* csr_col_dof; // CSR columns of B + M as dof indices
 };
-bool far_launch_plan(const H2Tree& t, int64_t cap, int ls, int R, FarLaunch* fl);
-hipError_t launch_apply_forkjoin_t(const ApplyPlan& a, const H2Tree& t, const FarLaunch& fl, int parts, int F, int R,
-                                   const double* csr_val, const double* St, int64_t nfar, int dtype, const void* x,
-                                   double* xt, double* xh, double* yh, double* tmp, void* y, hipStream_t st,
-                                   hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
-
-bool far_v2_fits(const H2Tree& t, int ls, int R);
-hipError_t launch_apply_v2(const ApplyPlan& a, const H2Tree& t, int ls, const int32_t* csr_col_dof, int parts, int F,
-                           int R, const double* csr_val, const double* St, int dtype, const void* x, double* xh,
-                           double* yh, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork, hipEvent_t join,
-                           hipEvent_t* ev);
-
-hipError_t launch_apply_v3(const ApplyPlan& a, const H2Tree& t, int ls, const int32_t* csr_col_dof, int parts, int F,
-                           int R, const double* csr_val, const double* St, int64_t nfar, int dtype, const void* x,
-                           double* xh, double* tmp, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
-                           hipEvent_t join, hipEvent_t* ev);
-
-// Near leaf blocks repacked per target leaf into row-major panels (fpde_near.hip)
-hipError_t launch_near_panel(const ApplyPlan& a, const int64_t* poff, const int64_t* pstride, const int32_t* pcols,
-                             const int64_t* pcols_ptr, int64_t max_stride, const double* panel, int use_near,
-                             const double* csr_val, int F, const double* xt, int dtype, void* y, hipStream_t st,
-                             hipEvent_t e0, hipEvent_t e1);
+// Operator data of one precision used by the single-vector apply
+template <typename T>
+struct OpData {
+    const T* U;       // [N][K] leaf bases (tree order)
+    const T* E;       // [ncl][D][P][P] transfers
+    const T* St;      // [F][nfar][K][K] coupling matrices, transposed
+    const T* panel;   // [F][panel_total]
+    T* xh;            // [F][ncl][K] workspace
+    T* tmp;           // [F][nfar][K] workspace
+};
+// One-launch upsweep: leaf-stage subtree depth d0, upper-stage depth ds
+struct UpPlan {
+    int d0, ds;
+    bool ok;
+};
+UpPlan plan_up_tree(const H2Tree& t, int64_t cap, int prec /*0 double, 1 float*/);
 hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const int64_t* near_ptr,
                               const int64_t* near_src, const int64_t* leaf_beg, const int64_t* pcol_off,
                               const int64_t* poff, const int64_t* pstride, const int64_t* pcols_ptr, const double* nb,
                               int F, double* panel, hipStream_t st);
-hipError_t launch_apply_v4(const ApplyPlan& a, const H2Tree& t, int ls, const int64_t* poff, const int64_t* pstride,
-                           const int32_t* pcols, const int64_t* pcols_ptr, int64_t max_stride, const double* panel,
-                           int parts, int F, const double* csr_val, const double* St, int64_t nfar, int dtype,
-                           const void* x, double* xt, double* xh, double* tmp, void* y, hipStream_t st,
-                           hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+hipError_t launch_near_panel(const ApplyPlan& a, const PanelPlan& pp, const double* panel, int use_near,
+                             const double* csr_val, int F, int dtype, const void* x, void* y, hipStream_t st,
+                             hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_near_panel(const ApplyPlan& a, const PanelPlan& pp, const float* panel, int use_near,
+                             const double* csr_val, int F, int dtype, const void* x, void* y, hipStream_t st,
+                             hipEvent_t e0, hipEvent_t e1);
+// tickets: [F][ncl] zero-initialised counters (left at zero by every launch).
+// ev (optional, 5 events, side == st): start, far chain end, near kernel start/stop, end.
+hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up, int parts,
+                               int F, const double* csr_val, int64_t nfar, const OpData<double>& od, int dtype,
+                               const void* x, void* y, unsigned int* tickets, hipStream_t st, hipStream_t side,
+                               hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up, int parts,
+                               int F, const double* csr_val, int64_t nfar, const OpData<float>& od, int dtype,
+                               const void* x, void* y, unsigned int* tickets, hipStream_t st, hipStream_t side,
+                               hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
 
-bool up_all_fits(const H2Tree& t, int64_t cap, int ls);
-hipError_t launch_apply_v5(const ApplyPlan& a, const H2Tree& t, int ls, const int64_t* poff, const int64_t* pstride,
-                           const int32_t* pcols, const int64_t* pcols_ptr, int64_t max_stride, const double* panel,
-                           int parts, int F, const double* csr_val, const double* St, int64_t nfar, int dtype,
-                           const void* x, double* xt, double* xh, double* tmp, unsigned int* tickets, void* y,
-                           hipStream_t st, hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+// ---------------------------------------------------------------- CG solve (fpde_solve.hip)
+
+struct CgDims {
+    int64_t N;      // rows per system
+    int R, F;       // right-hand sides, fields: S = F * R systems
+    int64_t nb;     // row blocks of the reductions (cg_row_blocks)
+};
+struct CgScalars {  // device arrays of S entries (n_active: one int)
+    double *rr, *alpha, *beta, *tol2;
+    int *active, *iters, *flags, *n_active;
+};
+int64_t cg_row_blocks(int64_t N, int R);
+// op 0: part1 = a.b;  1: u += alpha a, r -= alpha b, part1 = r.r;
+// 2: r = b - a, part1 = r.r, part2 = b.b;  3: r = p = b, u = 0, part1 = b.b
+hipError_t launch_cg_rowblock(int op, const CgDims& d, const double* a, const double* b, const double* alpha,
+                              double* u, double* r, double* p, double* part1, double* part2, hipStream_t st);
+hipError_t launch_cg_alpha(const CgDims& d, const double* part, const CgScalars& c, hipStream_t st);
+hipError_t launch_cg_beta(const CgDims& d, const double* part, const CgScalars& c, hipStream_t st);
+hipError_t launch_cg_p(const CgDims& d, const CgScalars& c, const double* r, double* p, hipStream_t st);
+hipError_t launch_cg_start(const CgDims& d, const double* part, const double* bb0, double tau_in, double rtol,
+                           const CgScalars& c, hipStream_t st);
+hipError_t launch_cg_sum2(const CgDims& d, const double* part1, const double* part2, double* o1, double* o2,
+                          hipStream_t st);
+hipError_t launch_vec_add(int64_t n, const double* d, double* u, hipStream_t st);
 
 }  // namespace fpde

@@ -1,0 +1,360 @@
+// Operator apply for several right-hand sides per field (R > 1) in FP64:
+// main stream: CSR rows of B + M and the near leaf blocks read in place
+// (k_near_out_m); side stream: subtree upsweep, top levels, coupling products
+// per far pair; join: per-leaf downsweep walk fused with the output.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fpde_device.h"
+
+namespace fpde {
+
+// levels ls-1 .. 0 with every transfer of levels 1..ls resident in LDS; one block per field
+template <int D, int P>
+__global__ __launch_bounds__(1024) void k_up_top_m(H2Tree t, int ls, int F, int R, double* xh) {
+    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
+    extern __shared__ double sm[];
+    const int f = blockIdx.x;
+    const int64_t ntop = (int64_t(2) << ls) - 1;
+    const int64_t KRr = (int64_t)K * R;
+    double* sx = sm;                     // [ntop][K][R]
+    double* sE = sx + ntop * KRr;        // [ntop][EP] (index = heap id)
+    for (int64_t i = threadIdx.x + ((int64_t(1) << ls) - 1) * KRr; i < ntop * KRr; i += blockDim.x)
+        sx[i] = xh[(int64_t)f * t.ncl * KRr + i];
+    for (int64_t i = threadIdx.x + EP; i < ntop * EP; i += blockDim.x) sE[i] = t.E[i];
+    __syncthreads();
+    for (int lev = ls - 1; lev >= 0; --lev) {
+        const int64_t c0 = (int64_t(1) << lev) - 1, w = int64_t(1) << lev;
+        for (int64_t i = threadIdx.x; i < w * KRr; i += blockDim.x) {
+            const int64_t cc = c0 + i / KRr;
+            const int al = (int)((i / R) % K), r = (int)(i % R);
+            const int64_t ch1 = 2 * cc + 1, ch2 = 2 * cc + 2;
+            const double v = up_t<D, P>(sE + ch1 * EP, sE + ch2 * EP, sx + ch1 * KRr + r, sx + ch2 * KRr + r, al, R);
+            sx[cc * KRr + (int64_t)al * R + r] = v;
+            xh[((int64_t)f * t.ncl + cc) * KRr + (int64_t)al * R + r] = v;
+        }
+        __syncthreads();
+    }
+}
+
+template <int D, int P>
+FPDE_KERNEL void k_coupling_pairs_m(H2Tree t, int64_t nfar, int F, int R, const double* St, const double* xh,
+                                    double* tmp) {
+    constexpr int K = KR<D, P>::K;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)K * R;
+    if (i >= (int64_t)F * nfar * per) return;
+    const int f = (int)(i / (nfar * per));
+    int64_t rem = i - (int64_t)f * nfar * per;
+    const int64_t e = rem / per;
+    rem %= per;
+    const int al = (int)(rem / R), r = (int)(rem % R);
+    const double* S = St + ((int64_t)f * nfar + e) * K * K + al;
+    const double* xs = xh + (((int64_t)f * t.ncl + t.far_src[e]) * K) * R + r;
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < K; ++b) acc += S[b * K] * xs[(int64_t)b * R];
+    tmp[i] = acc;
+}
+
+// Near field + CSR reading the caller's x: CSR columns are dof indices (csr_col_dof),
+// near-block columns map through perm.  One 16-lane group per row, 16 rows per block.
+FPDE_KERNEL void k_near_out_m(ApplyPlan a, const int32_t* csr_col_dof, int parts, int F, int R,
+                               const double* csr_val, int dtype, const void* x, void* y) {
+    const int f = blockIdx.y;
+    const int64_t nrb = (a.cap + 15) / 16;
+    const int64_t li = blockIdx.x / nrb;
+    const int rb = (int)(blockIdx.x % nrb);
+    const int g = threadIdx.x & 15;
+    const int64_t it = (int64_t)rb * 16 + (threadIdx.x >> 4);
+    const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
+    if (it >= nt) return;
+    const int64_t row = lb + it;
+    const int64_t xo = (int64_t)f * a.N * R;
+    const int64_t cap = a.cap;
+    const int64_t e0 = a.near_ptr[li], e1 = a.near_ptr[li + 1];
+    const int64_t c0 = 4 * g;
+    for (int r = 0; r < R; ++r) {
+        double acc = 0.0;
+        if (csr_val) {
+            const double* v = csr_val + (int64_t)f * a.nnz;
+            for (int64_t e = a.csr_ptr[row] + g; e < a.csr_ptr[row + 1]; e += 16)
+                acc += v[e] * ldx(x, xo + (int64_t)csr_col_dof[e] * R + r, dtype);
+        }
+        if (parts & 4) {
+            if ((cap & 3) == 0) {
+                int64_t e = e0;
+                for (; e + 4 <= e1; e += 4) {
+                    double2 b0[4], b1[4];
+                    int64_t sb[4], ns[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t ls_ = a.near_src[e + u];
+                        sb[u] = a.leaf_beg[ls_];
+                        ns[u] = a.leaf_beg[ls_ + 1] - sb[u];
+                        const double* blk = a.near_blk + (((int64_t)f * a.npairs + e + u) * cap + it) * cap + c0;
+                        if (c0 < ns[u]) {
+                            b0[u] = *(const double2*)(blk);
+                            b1[u] = *(const double2*)(blk + 2);
+                        } else {
+                            b0[u] = make_double2(0.0, 0.0);
+                            b1[u] = make_double2(0.0, 0.0);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t m = ns[u] - c0;
+                        const double v4[4] = {b0[u].x, b0[u].y, b1[u].x, b1[u].y};
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (j < m) acc += v4[j] * ldx(x, xo + a.perm[sb[u] + c0 + j] * R + r, dtype);
+                    }
+                }
+                for (; e < e1; ++e) {
+                    const int64_t ls_ = a.near_src[e];
+                    const int64_t sb = a.leaf_beg[ls_], ns = a.leaf_beg[ls_ + 1] - sb;
+                    const double* blk = a.near_blk + (((int64_t)f * a.npairs + e) * cap + it) * cap;
+                    for (int64_t jc = c0; jc < c0 + 4 && jc < ns; ++jc)
+                        acc += blk[jc] * ldx(x, xo + a.perm[sb + jc] * R + r, dtype);
+                }
+                for (e = e0; e < e1 && cap > 64; ++e) {
+                    const int64_t ls_ = a.near_src[e];
+                    const int64_t sb = a.leaf_beg[ls_], ns = a.leaf_beg[ls_ + 1] - sb;
+                    const double* blk = a.near_blk + (((int64_t)f * a.npairs + e) * cap + it) * cap;
+                    for (int64_t jc = 64 + g; jc < ns; jc += 16) acc += blk[jc] * ldx(x, xo + a.perm[sb + jc] * R + r, dtype);
+                }
+            } else {
+                for (int64_t e = e0; e < e1; ++e) {
+                    const int64_t ls_ = a.near_src[e];
+                    const int64_t sb = a.leaf_beg[ls_], ns = a.leaf_beg[ls_ + 1] - sb;
+                    const double* blk = a.near_blk + (((int64_t)f * a.npairs + e) * cap + it) * cap;
+                    for (int64_t jc = g; jc < ns; jc += 16) acc += blk[jc] * ldx(x, xo + a.perm[sb + jc] * R + r, dtype);
+                }
+            }
+        }
+        for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+        if (g == 0) {
+            const int64_t dst = ((int64_t)f * a.N + a.perm[row]) * R + r;
+            if (dtype == 0) ((double*)y)[dst] = acc;
+            else ((float*)y)[dst] = (float)acc;
+        }
+    }
+}
+
+// LDS needed by the v2 far chain; false when the per-level path must be used
+bool multi_fits(const H2Tree& t, int ls, int R) {
+    const int64_t K = t.k, EP = (int64_t)t.dim * t.p * t.p;
+    const int64_t ncs = (int64_t(2) << (t.L - ls)) - 1, ntop = (int64_t(2) << ls) - 1;
+    const int64_t lim = 64 * 1024 / 8;
+    return ncs * K * R + ncs * EP <= lim && ntop * K * R + ntop * EP <= lim &&
+           (int64_t)(t.L + 1) * (K * R + EP) <= lim && K <= 64;
+}
+// One wave per leaf (up to 8 leaves per 512-thread block); x read once per row.
+template <int D, int P>
+__global__ __launch_bounds__(512) void k_up_sub_m(ApplyPlan a, H2Tree t, int ls, int F, int R, int dtype,
+                                                  const void* x, double* xh) {
+    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
+    constexpr int CH = K < 16 ? K : 16;
+    constexpr int MAXROWS = 4;   // rows per lane held in registers (leaf <= 256 rows)
+    extern __shared__ double sm[];
+    const int f = blockIdx.y;
+    const int64_t c = ((int64_t(1) << ls) - 1) + blockIdx.x;
+    const int depth = t.L - ls;
+    const int64_t ncs = (int64_t(2) << depth) - 1;
+    double* sc = sm;
+    double* sE = sc + ncs * K * R;
+    auto gid = [&](int64_t l) -> int64_t {
+        int lev = 0;
+        while (((int64_t(2) << lev) - 1) <= l) ++lev;
+        const int64_t w = int64_t(1) << lev;
+        return (c + 1) * w - 1 + (l - (w - 1));
+    };
+    for (int64_t i = threadIdx.x; i < ncs * EP; i += blockDim.x) sE[i] = t.E[gid(i / EP) * EP + i % EP];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int64_t nl = int64_t(1) << depth;
+    const int64_t l0 = ((c + 1) << depth) - 1;
+    for (int64_t li = wv; li < nl; li += nw) {
+        const int64_t cc = l0 + li;
+        const int64_t rb = t.beg[cc], re = t.end[cc];
+        for (int r = 0; r < R; ++r) {
+            double xv[MAXROWS];
+#pragma unroll
+            for (int m = 0; m < MAXROWS; ++m) {
+                const int64_t j = rb + lane + 64 * m;
+                xv[m] = j < re ? ldx(x, ((int64_t)f * a.N + a.perm[j]) * R + r, dtype) : 0.0;
+            }
+            for (int a0 = 0; a0 < K; a0 += CH) {
+                double acc[CH];
+#pragma unroll
+                for (int q = 0; q < CH; ++q) acc[q] = 0.0;
+#pragma unroll
+                for (int m = 0; m < MAXROWS; ++m) {
+                    const int64_t j = rb + lane + 64 * m;
+                    if (j < re) {
+                        const double* u = a.U + j * K + a0;
+#pragma unroll
+                        for (int q = 0; q < CH; ++q)
+                            if (a0 + q < K) acc[q] += u[q] * xv[m];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < CH; ++q) {
+                    const double v = wave_sum(acc[q]);
+                    if (lane == q && a0 + q < K) {
+                        sc[((nl - 1 + li) * K + a0 + q) * R + r] = v;
+                        xh[(((int64_t)f * t.ncl + cc) * K + a0 + q) * R + r] = v;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int lev = t.L - 1; lev >= ls; --lev) {
+        const int64_t w = int64_t(1) << (lev - ls);
+        const int64_t lfirst = w - 1;
+        for (int64_t i = threadIdx.x; i < w * K * R; i += blockDim.x) {
+            const int64_t lc = lfirst + i / ((int64_t)K * R);
+            const int al = (int)((i / R) % K), r = (int)(i % R);
+            const int64_t l1 = 2 * lc + 1, l2 = 2 * lc + 2;
+            const double v = up_t<D, P>(sE + l1 * EP, sE + l2 * EP, sc + l1 * K * R + r, sc + l2 * K * R + r, al, R);
+            sc[(lc * K + al) * R + r] = v;
+            xh[(((int64_t)f * t.ncl + gid(lc)) * K + al) * R + r] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// y[perm[row]] += U[row] . yh_total(leaf), yh(c) = sum of the pair products of far(c)
+template <int D, int P>
+FPDE_KERNEL void k_far_out_m(ApplyPlan a, H2Tree t, int F, int R, const double* tmp, int dtype, void* y) {
+    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
+    extern __shared__ double sm[];
+    const int f = blockIdx.y;
+    const int64_t nrb = (a.cap * R + 63) / 64;
+    const int64_t li = blockIdx.x / nrb;
+    const int rb = (int)(blockIdx.x % nrb);
+    const int64_t leafc = t.first_leaf + li;
+    const int64_t KRr = (int64_t)K * R;
+    const int L = t.L;
+    const int64_t nfar = t.far_ptr[t.ncl];
+    double* sy = sm;
+    double* sE = sy + (int64_t)(L + 1) * KRr;
+    // output row of this thread and its basis row, fetched before the walk
+    const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
+    const int g = threadIdx.x & 3;
+    const int64_t item = (int64_t)rb * 64 + (threadIdx.x >> 2);
+    const int64_t it = item / R;
+    const int r = (int)(item % R);
+    const bool ok = it < nt;
+    double u[(K + 3) / 4];
+#pragma unroll
+    for (int q = 0; q < (K + 3) / 4; ++q) u[q] = (ok && 4 * q + g < K) ? a.U[(lb + it) * K + 4 * q + g] : 0.0;
+    for (int64_t i = threadIdx.x; i < (int64_t)(L + 1) * KRr; i += blockDim.x) {
+        const int lev = (int)(i / KRr);
+        const int64_t cc = ((leafc + 1) >> (L - lev)) - 1;
+        const int64_t w = i % KRr;
+        const int64_t e0 = t.far_ptr[cc], e1 = t.far_ptr[cc + 1];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int64_t e = e0;
+        for (; e + 4 <= e1; e += 4) {   // four independent loads in flight
+            s0 += tmp[((int64_t)f * nfar + e) * KRr + w];
+            s1 += tmp[((int64_t)f * nfar + e + 1) * KRr + w];
+            s2 += tmp[((int64_t)f * nfar + e + 2) * KRr + w];
+            s3 += tmp[((int64_t)f * nfar + e + 3) * KRr + w];
+        }
+        for (; e < e1; ++e) s0 += tmp[((int64_t)f * nfar + e) * KRr + w];
+        sy[i] = (s0 + s1) + (s2 + s3);
+    }
+    for (int64_t i = threadIdx.x; i < (int64_t)(L + 1) * EP; i += blockDim.x) {
+        const int lev = (int)(i / EP);
+        const int64_t cc = ((leafc + 1) >> (L - lev)) - 1;
+        sE[i] = lev == 0 ? 0.0 : t.E[cc * EP + i % EP];
+    }
+    __syncthreads();
+    for (int lev = 1; lev <= L; ++lev) {
+        for (int64_t i = threadIdx.x; i < KRr; i += blockDim.x) {
+            const int be = (int)(i / R), rr = (int)(i % R);
+            sy[lev * KRr + i] += down_t<D, P>(sE + lev * EP, sy + (lev - 1) * KRr + rr, be, R);
+        }
+        __syncthreads();
+    }
+    const double* cur = sy + L * KRr;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < (K + 3) / 4; ++q)
+        if (4 * q + g < K) acc += u[q] * cur[(int64_t)(4 * q + g) * R + r];
+    acc += __shfl_xor(acc, 1, 4);
+    acc += __shfl_xor(acc, 2, 4);
+    if (ok && g == 0) {
+        const int64_t dst = ((int64_t)f * a.N + a.perm[lb + it]) * R + r;
+        if (dtype == 0) ((double*)y)[dst] += acc;
+        else ((float*)y)[dst] = (float)((double)((float*)y)[dst] + acc);
+    }
+}
+
+template <int D, int P>
+static void far_m_t(const ApplyPlan& a, const H2Tree& t, int ls, int F, int R, const double* St, int64_t nfar,
+                     int dtype, const void* x, double* xh, double* tmp, hipStream_t fs) {
+    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
+    const int depth = t.L - ls;
+    const int64_t ncs = (int64_t(2) << depth) - 1;
+    const int64_t nl = int64_t(1) << depth;
+    const int threads = 64 * (int)(nl < 8 ? nl : 8);
+    const size_t lds_sub = sizeof(double) * (ncs * K * R + ncs * EP);
+    hipLaunchKernelGGL((k_up_sub_m<D, P>), dim3((unsigned)(int64_t(1) << ls), F), dim3(threads), lds_sub, fs, a, t,
+                       ls, F, R, dtype, x, xh);
+    if (ls > 0) {
+        const int64_t ntop = (int64_t(2) << ls) - 1;
+        const size_t lds_top = sizeof(double) * (ntop * K * R + ntop * EP);
+        hipLaunchKernelGGL((k_up_top_m<D, P>), dim3(F), dim3(1024), lds_top, fs, t, ls, F, R, xh);
+    }
+    if (nfar > 0)
+        hipLaunchKernelGGL((k_coupling_pairs_m<D, P>), dim3(grid1((int64_t)F * nfar * K * R)), dim3(256), 0, fs, t,
+                           nfar, F, R, St, xh, tmp);
+}
+
+template <int D, int P>
+static void far_out_m_t(const ApplyPlan& a, const H2Tree& t, int F, int R, const double* tmp, int dtype, void* y,
+                         hipStream_t st) {
+    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
+    const int64_t nrb = (a.cap * R + 63) / 64;
+    const size_t lds = sizeof(double) * ((int64_t)(t.L + 1) * K * R + (int64_t)(t.L + 1) * EP);
+    hipLaunchKernelGGL((k_far_out_m<D, P>), dim3((unsigned)(a.nleaf * nrb), F), dim3(256), lds, st, a, t, F, R, tmp,
+                       dtype, y);
+}
+
+hipError_t launch_apply_multi(const ApplyPlan& a, const H2Tree& t, int ls, const int32_t* csr_col_dof, int parts, int F,
+                           int R, const double* csr_val, const double* St, int64_t nfar, int dtype, const void* x,
+                           double* xh, double* tmp, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
+                           hipEvent_t join, hipEvent_t* ev) {
+    const bool far = (parts & 8) != 0;
+    if (ev) hipEventRecord(ev[0], st);
+    hipStream_t fs = st;
+    if (far && side != st) {
+        hipEventRecord(fork, st);
+        hipStreamWaitEvent(side, fork, 0);
+        fs = side;
+    }
+    if (far) FPDE_DISPATCH_DP(t.dim, t.p, far_m_t, a, t, ls, F, R, St, nfar, dtype, x, xh, tmp, fs);
+    if (ev) hipEventRecord(ev[1], fs);
+    const int64_t nrb = (a.cap + 15) / 16;
+    if (ev)   // start/stop timestamps of exactly this kernel
+        hipExtLaunchKernelGGL(k_near_out_m, dim3((unsigned)(a.nleaf * nrb), F), dim3(256), 0, st, ev[2], ev[3], 0, a,
+                              csr_col_dof, parts, F, R, csr_val, dtype, x, y);
+    else
+        hipLaunchKernelGGL(k_near_out_m, dim3((unsigned)(a.nleaf * nrb), F), dim3(256), 0, st, a, csr_col_dof, parts,
+                           F, R, csr_val, dtype, x, y);
+    if (far) {
+        if (fs != st) {
+            hipEventRecord(join, fs);
+            hipStreamWaitEvent(st, join, 0);
+        }
+        FPDE_DISPATCH_DP(t.dim, t.p, far_out_m_t, a, t, F, R, tmp, dtype, y, st);
+    }
+    if (ev) hipEventRecord(ev[4], st);
+    return hipGetLastError();
+}
+
+}  // namespace fpde

@@ -93,18 +93,26 @@ class Operator:
                                      _stream_handle(stream)), "fpde_load_vector")
         return out
 
-    def solve(self, F, u=None, rtol: float = 1e-10, maxit: int = 10000, stream=None):
+    def solve(self, F, u=None, rtol: float = 1e-10, maxit: int = 10000, stream=None, raise_on_noconv=True):
+        """Solve A u = F (device float64 [F, N, R] or [F, N]); u is the initial guess (zeros if None)."""
         import torch
         if F.dim() == 2:
             F = F.unsqueeze(-1)
+        if tuple(F.shape[:2]) != (self.n_fields, self.n_dofs) or not F.is_cuda or F.dtype != torch.float64:
+            raise ValueError(f"F must be a float64 device tensor [F={self.n_fields}, N={self.n_dofs}, R]")
         F = F.contiguous()
         if u is None:
             u = torch.zeros_like(F)
+        elif u.shape != F.shape or u.dtype != torch.float64 or not u.is_contiguous():
+            raise ValueError("u must be a contiguous float64 tensor shaped like F")
         info = _abi.SolveInfo()
-        check(lib().fpde_solve(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(u.data_ptr()), F.shape[2], rtol,
-                               maxit, C.byref(info), _stream_handle(stream)), "fpde_solve")
-        return u, {"iterations": info.iterations, "rel_residual": info.rel_residual,
-                   "converged": bool(info.converged)}
+        st = lib().fpde_solve(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(u.data_ptr()), F.shape[2], rtol,
+                              maxit, C.byref(info), _stream_handle(stream))
+        out = {"iterations": info.iterations, "rel_residual": info.rel_residual,
+               "converged": bool(info.converged), "refinements": info.refinements}
+        if st != _abi.FPDE_OK and (raise_on_noconv or st != _abi.FPDE_ENOCONV):
+            check(st, "fpde_solve")
+        return u, out
 
     # ------------------------------------------------------------------ inspection
     def export(self, what: str, field: int = 0) -> np.ndarray:

@@ -156,19 +156,57 @@ def test_wide_rhs_fallback_and_profiled_path():
     assert np.array_equal(y_graph, y_prof)
 
 
+MIXED_TOL = 1e-6   # per matvec, relative 2-norm against the FP64 oracle
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mixed_precision_apply(name):
+    """FP32 near panels, bases, transfers and coupling (FP64 CSR of B + M): the
+    matvec stays within 1e-6 of the FP64 oracle; FPDE_PART_FP64 on the same
+    operator reproduces the FP64 operator bit for bit."""
+    import paper_2302_02863_amd as fp
+    P, ref, op64 = _case(name)
+    o = dict(P.opts)
+    o["precision"] = "mixed"
+    op = fp.Operator(P.mesh, P.s, P.kappa, o)
+    A = ref["B"] + ref["K"] + ref["M"]
+    rng = np.random.default_rng(21)
+    for x in (P.x[0, :, 0], rng.standard_normal(op.n_dofs), np.sin(np.pi * P.mesh.coords[0, :op.n_dofs])):
+        y = _apply(op, x.reshape(1, -1, 1), fp.PART_ALL)[0, :, 0]
+        yr = A @ x
+        err = np.linalg.norm(y - yr) / np.linalg.norm(yr)
+        assert err < MIXED_TOL, err
+    print(f"[parity] {name}: mixed apply rel err {err:.2e}")
+    y64 = _apply(op, P.x, fp.PART_ALL | fp.PART_FP64)
+    assert np.array_equal(y64, _apply(op64, P.x, fp.PART_ALL))
+    # mixed graph and profiled launches agree bit for bit
+    yg = _apply(op, P.x, fp.PART_ALL)
+    op.profile(True)
+    yp = _apply(op, P.x, fp.PART_ALL)
+    op.profile(False)
+    assert np.array_equal(yg, yp)
+    op.close()
+
+
 def test_top_level_sweeps(monkeypatch):
-    """Force a shallow LDS subtree so the single-block top upsweep/downsweep kernels run."""
+    """Cap the subtree depths so the upsweep takes a ticket at every level (and the
+    multi-RHS path runs its top sweeps); results must not change."""
     import paper_2302_02863_amd as fp
     P = configs.square(16, 8, leaf_size=8, leaf_size_rho=32, cheb_p=3)
     ref = assemble_h2(P.mesh, P.s[0], P.kappa[0], P.opts)
     A = ref["B"] + ref["K"] + ref["M"]
-    for depth in ("0", "1"):
+    for depth in ("0", "1", "2"):
         monkeypatch.setenv("FPDE_MAX_SUBTREE_DEPTH", depth)
-        op = fp.Operator(P.mesh, P.s, P.kappa, P.opts)
-        y = _apply(op, P.x, fp.PART_ALL)[0, :, 0]
-        yr = A @ P.x[0, :, 0]
-        assert np.linalg.norm(y - yr) / np.linalg.norm(yr) < TOL, depth
-        op.close()
+        for prec in ("fp64", "mixed"):
+            o = dict(P.opts)
+            o["precision"] = prec
+            op = fp.Operator(P.mesh, P.s, P.kappa, o)
+            for _ in range(3):   # tickets reset themselves between launches
+                y = _apply(op, P.x, fp.PART_ALL)[0, :, 0]
+                yr = A @ P.x[0, :, 0]
+                tol = TOL if prec == "fp64" else MIXED_TOL
+                assert np.linalg.norm(y - yr) / np.linalg.norm(yr) < tol, (depth, prec)
+            op.close()
 
 
 def test_bitwise_reproducible():
