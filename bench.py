@@ -100,14 +100,64 @@ def cpu_baseline(P, seconds: float = 15.0):
                       f"(tree/partition/basis setup {t_setup:.1f} s excluded, rows {el:.1f} s)"}
 
 
+def time_applies(op, x, y, stream, steps, warmup, parts=None):
+    import torch
+    kw = {} if parts is None else {"parts": parts}
+    for _ in range(warmup):
+        op.apply(x, y, stream=stream, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        op.apply(x, y, stream=stream, **kw)          # one hipGraph launch per apply
+    torch.cuda.synchronize()
+    return time.perf_counter() - t1
+
+
+def mixed_and_solve(P, op64, x, y64, stream, steps, warmup):
+    """Mixed-precision apply (FP32 near panels, bases, transfers, coupling; FP64 CSR of B + M)
+    against the FP64 path on the same workload, and FP64 CG versus mixed CG with iterative
+    refinement on the load vector of f = 1."""
+    import numpy as np
+    import torch
+    import paper_2302_02863_amd as fp
+    o = dict(P.opts)
+    o["precision"] = "mixed"
+    opm = fp.Operator(P.mesh, P.s, P.kappa, o)
+    ym = torch.empty_like(x)
+    el_m = time_applies(opm, x, ym, stream, steps, warmup)
+    err = float(torch.linalg.vector_norm(ym - y64) / torch.linalg.vector_norm(y64))
+    out = {"value": P.mesh.n_dofs * x.shape[0] * x.shape[2] * steps / el_m,
+           "ms_per_step": el_m / steps * 1e3, "max_rel_err_vs_fp64": err}
+    # solves: A u = F, F the load vector of f = 1 (computed by the library)
+    F = op64.load_vector(torch.ones(P.mesh.n_nodes, dtype=torch.float64, device=x.device)).reshape(1, -1, 1)
+    F = F.expand(x.shape[0], -1, -1).contiguous()
+    res = {}
+    for name, op in (("fp64", op64), ("mixed", opm)):
+        op.solve(F, rtol=1e-10, maxit=20000)        # warm-up (captures the CG graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, info = op.solve(F, rtol=1e-10, maxit=20000)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0, u, info)
+    uerr = float(torch.linalg.vector_norm(res["mixed"][1] - res["fp64"][1]) / torch.linalg.vector_norm(res["fp64"][1]))
+    out["solve"] = {"rtol": 1e-10, "fp64_ms": res["fp64"][0] * 1e3, "mixed_ms": res["mixed"][0] * 1e3,
+                    "fp64_iterations": res["fp64"][2]["iterations"],
+                    "mixed_iterations": res["mixed"][2]["iterations"],
+                    "mixed_refinements": res["mixed"][2]["refinements"],
+                    "speedup": res["fp64"][0] / res["mixed"][0],
+                    "mixed_vs_fp64_solution_rel_diff": uerr}
+    opm.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="square")
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision apply and the solves")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -141,14 +191,7 @@ def main():
     x = torch.tensor(P.x, device=dev)
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        op.apply(x, y, stream=stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        op.apply(x, y, stream=stream)          # one hipGraph launch per apply
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t1
+    el = time_applies(op, x, y, stream, args.steps, args.warmup)
     # same launches without the graph, HIP events on the apply stream between the phases
     op.profile(True)
     for _ in range(args.steps):
@@ -185,6 +228,10 @@ def main():
                                               "t_near_blocks_ms")},
         "counts": {k: st[k] for k in ("n_dofs", "csr_nnz", "k_near", "k_far", "k_leaves", "rho_near", "rho_far")},
     }
+    if not args.no_mixed:
+        mx = mixed_and_solve(P, op, x, y, stream, args.steps, args.warmup)
+        mx["speedup_vs_fp64"] = mx["value"] / value
+        res["mixed"] = mx
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(P)
     print(json.dumps(res))

@@ -22,14 +22,17 @@ namespace fpde {
 // coefficients x^_leaf = U_leaf^T x_leaf (one wave per leaf, the leaf's x rows
 // staged in LDS), then the subtree's levels in LDS.  Upper stages: every group
 // of subtrees under one ancestor ds levels up counts its finished blocks with a
-// ticket (device-scope release before, acquire after); the last block of the
-// group computes the ancestor's subtree levels from the published
-// coefficients, resets the ticket and goes on to the next group.  No block
-// ever waits for another, so the launch always drains.
+// ticket (agent-scope release fence of every thread, block barrier, one atomic
+// per block, agent-scope acquire fence in the last block); the last block of the group
+// computes the ancestor's subtree levels from the published coefficients,
+// resets the ticket and goes on to the next group.  No block ever waits for
+// another, so the launch always drains.  Loads that do not depend on other
+// blocks (U rows, transfers) are issued before the dependent ones.
 template <int D, int P, typename T>
 __global__ __launch_bounds__(512) void k_up_tree(ApplyPlan a, H2Tree t, UpPlan up, int F, int dtype, const void* x,
                                                  const T* U, const T* E, T* xh, unsigned int* tickets) {
     constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
+    constexpr int kRows = 32;   // rows per half-wave held in registers (leaves of up to 64 rows)
     extern __shared__ __align__(16) unsigned char sraw[];
     T* sm = (T*)sraw;
     __shared__ unsigned int s_ticket;
@@ -52,25 +55,36 @@ __global__ __launch_bounds__(512) void k_up_tree(ApplyPlan a, H2Tree t, UpPlan u
         T* sc = sm;                          // [ncs][K]
         T* sE = sc + ncs * K;                // [ncs][EP]
         T* sx = sE + ncs * EP;               // [waves][cap]
-        for (int64_t i = threadIdx.x; i < ncs * EP; i += blockDim.x) sE[i] = E[gid(c, i / EP) * EP + i % EP];
+        for (int64_t i = threadIdx.x + EP; i < ncs * EP; i += blockDim.x) sE[i] = E[gid(c, i / EP) * EP + i % EP];
         const int64_t nl = int64_t(1) << depth;
         const int64_t l0 = ((c + 1) << depth) - 1;
         T* sxw = sx + (int64_t)wv * a.cap;
         for (int64_t li = wv; li < nl; li += nw) {
             const int64_t cc = l0 + li;
             const int64_t rb = t.beg[cc], n = t.end[cc] - rb;
-            for (int64_t j = lane; j < n; j += 64) sxw[j] = (T)ldx(x, (int64_t)f * a.N + a.perm[rb + j], dtype);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             // lanes (half, alpha): with K <= 32 the two half-waves split the rows
             const int half = K <= 32 ? (lane >> 5) : 0;
             const int al = K <= 32 ? (lane & 31) : lane;
             const int64_t jb = K <= 32 ? (half ? (n + 1) / 2 : 0) : 0;
             const int64_t je = K <= 32 ? (half ? n : (n + 1) / 2) : n;
+            const T* u = U + rb * K + al;
+            const bool regs = K <= 32 && n <= 2 * kRows && al < K;
+            T uv[kRows];
+            if (regs) {   // the U rows of this lane, all in flight before the x gather
+#pragma unroll
+                for (int q = 0; q < kRows; ++q) uv[q] = jb + q < je ? u[(jb + q) * K] : T(0);
+            }
+            for (int64_t j = lane; j < n; j += 64) sxw[j] = (T)ldx(x, (int64_t)f * a.N + a.perm[rb + j], dtype);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             T v = 0;
-            if (al < K) {
-                const T* u = U + rb * K + al;
+            if (regs) {
+                T s[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < kRows; ++q) s[q & 3] += uv[q] * (jb + q < je ? sxw[jb + q] : T(0));
+                v = (s[0] + s[1]) + (s[2] + s[3]);
+            } else if (al < K) {
                 T s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                 int64_t j = jb;
                 for (; j + 8 <= je; j += 8) {
@@ -107,20 +121,25 @@ __global__ __launch_bounds__(512) void k_up_tree(ApplyPlan a, H2Tree t, UpPlan u
         const int ln = lc - up.ds > 0 ? lc - up.ds : 0;
         const int depth = lc - ln;
         const int64_t g = ((c + 1) >> depth) - 1;     // ancestor at level ln
-        // publish this block's coefficients, take a ticket of the group
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) s_ticket = atomicAdd(&tickets[(int64_t)f * t.ncl + g], 1u);
-        __syncthreads();
-        if (s_ticket != (unsigned int)((1u << depth) - 1)) return;
-        __threadfence();
-        if (threadIdx.x == 0) atomicExch(&tickets[(int64_t)f * t.ncl + g], 0u);
         const int64_t ncs = (int64_t(2) << depth) - 1, w0 = int64_t(1) << depth;
         T* sc = sm;
         T* sE = sc + ncs * K;
+        // transfers of the group's subtree do not depend on other blocks: load them first
+        for (int64_t i = threadIdx.x + EP; i < ncs * EP; i += blockDim.x) sE[i] = E[gid(g, i / EP) * EP + i % EP];
+        // publish: every thread's coefficient stores are released at agent scope before
+        // the barrier; one ticket per block; the last block acquires the others' stores
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_ticket = __hip_atomic_fetch_add(&tickets[(int64_t)f * t.ncl + g], 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        if (s_ticket != (unsigned int)((1u << depth) - 1)) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (threadIdx.x == 0)   // every group's blocks have arrived: reset for the next launch
+            __hip_atomic_store(&tickets[(int64_t)f * t.ncl + g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (int64_t i = threadIdx.x; i < w0 * K; i += blockDim.x)
             sc[(w0 - 1) * K + i] = __builtin_nontemporal_load(&xf[(((g + 1) << depth) - 1) * K + i]);
-        for (int64_t i = threadIdx.x + EP; i < ncs * EP; i += blockDim.x) sE[i] = E[gid(g, i / EP) * EP + i % EP];
         __syncthreads();
         for (int lev = depth - 1; lev >= 0; --lev) {
             const int64_t w = int64_t(1) << lev, lfirst = w - 1;
@@ -187,16 +206,16 @@ FPDE_KERNEL void k_far_out1(ApplyPlan a, H2Tree t, int F, const T* tmp, const T*
         const int64_t cc = ((leafc + 1) >> (L - lev)) - 1;
         const int w = (int)(i % K);
         const int64_t e0 = t.far_ptr[cc], e1 = t.far_ptr[cc + 1];
-        T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        int64_t e = e0;
-        for (; e + 4 <= e1; e += 4) {   // four independent loads in flight
-            s0 += tmp[((int64_t)f * nfar + e) * K + w];
-            s1 += tmp[((int64_t)f * nfar + e + 1) * K + w];
-            s2 += tmp[((int64_t)f * nfar + e + 2) * K + w];
-            s3 += tmp[((int64_t)f * nfar + e + 3) * K + w];
+        const T* tp = tmp + ((int64_t)f * nfar) * K + w;
+        T s[4] = {0, 0, 0, 0};
+        for (int64_t e = e0; e < e1; e += 16) {   // sixteen independent loads in flight
+            T v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = e + q < e1 ? tp[(e + q) * K] : T(0);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) s[q & 3] += v[q];
         }
-        for (; e < e1; ++e) s0 += tmp[((int64_t)f * nfar + e) * K + w];
-        sy[i] = (s0 + s1) + (s2 + s3);
+        sy[i] = (s[0] + s[1]) + (s[2] + s[3]);
     }
     for (int64_t i = threadIdx.x; i < (int64_t)(L + 1) * EP; i += blockDim.x) {
         const int lev = (int)(i / EP);

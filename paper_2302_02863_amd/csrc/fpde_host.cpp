@@ -170,7 +170,7 @@ struct fpde_op {
     // solve workspace ([F][N][R] vectors, per-block partial sums, per-system scalars)
     int64_t sw_R = 0;
     double *d_r = nullptr, *d_p = nullptr, *d_Ap = nullptr, *d_d = nullptr, *d_rout = nullptr;
-    double *d_part1 = nullptr, *d_part2 = nullptr, *d_bb = nullptr, *d_rro = nullptr;
+    double *d_part1 = nullptr, *d_part2 = nullptr, *d_part3 = nullptr, *d_bb = nullptr, *d_rro = nullptr;
     CgScalars cg{};
     int* h_nact = nullptr;                    // pinned host copy of the active-system count
     // captured CG iterations keyed by (precision, R)
@@ -910,9 +910,10 @@ void ensure_solve_ws(fpde_op& op, int64_t R) {
     if (op.sw_R >= R) return;
     Arena& A = op.arena;
     for (void* q : {(void*)op.d_r, (void*)op.d_p, (void*)op.d_Ap, (void*)op.d_d, (void*)op.d_rout,
-                    (void*)op.d_part1, (void*)op.d_part2, (void*)op.d_bb, (void*)op.d_rro, (void*)op.cg.rr,
-                    (void*)op.cg.alpha, (void*)op.cg.beta, (void*)op.cg.tol2, (void*)op.cg.active,
-                    (void*)op.cg.iters, (void*)op.cg.flags, (void*)op.cg.n_active})
+                    (void*)op.d_part1, (void*)op.d_part2, (void*)op.d_part3, (void*)op.d_bb, (void*)op.d_rro,
+                    (void*)op.cg.rr, (void*)op.cg.rr_next, (void*)op.cg.alpha, (void*)op.cg.beta, (void*)op.cg.tol2,
+                    (void*)op.cg.active, (void*)op.cg.active_next, (void*)op.cg.iters, (void*)op.cg.flags,
+                    (void*)op.cg.n_active})
         if (q) A.release(q);
     for (auto& kv : op.cg_graphs) hipGraphExecDestroy(kv.second);
     op.cg_graphs.clear();
@@ -925,9 +926,12 @@ void ensure_solve_ws(fpde_op& op, int64_t R) {
     op.d_rout = A.alloc<double>(n);
     op.d_part1 = A.alloc<double>(op.F * nb * R);
     op.d_part2 = A.alloc<double>(op.F * nb * R);
+    op.d_part3 = A.alloc<double>(op.F * nb * R);
     op.d_bb = A.alloc<double>(S);
     op.d_rro = A.alloc<double>(S);
     op.cg.rr = A.alloc<double>(S);
+    op.cg.rr_next = A.alloc<double>(S);
+    op.cg.active_next = A.alloc<int>(S);
     op.cg.alpha = A.alloc<double>(S);
     op.cg.beta = A.alloc<double>(S);
     op.cg.tol2 = A.alloc<double>(S);
@@ -940,19 +944,20 @@ void ensure_solve_ws(fpde_op& op, int64_t R) {
 }
 
 // One CG iteration on the system A d = rout (apply of precision `mixed`):
-// Ap = A p; alpha = |r|^2 / p.Ap; d += alpha p; r -= alpha Ap; beta; p = r + beta p.
+// Ap = A p; p.Ap; alpha, d += alpha p, r -= alpha Ap, r.r; beta, p = r + beta p.
 hipError_t enqueue_cg_iteration(fpde_op& op, bool mixed, int64_t R, hipStream_t s0, hipStream_t s1) {
     const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
     const int parts = mixed ? FPDE_PART_ALL : (FPDE_PART_ALL | FPDE_PART_FP64);
     hipError_t e = enqueue_apply(op, parts, FPDE_F64, op.d_p, op.d_Ap, R, s0, s1, op.ev_fork, op.ev_join, nullptr);
     if (e != hipSuccess) return e;
-    if ((e = launch_cg_rowblock(0, dm, op.d_p, op.d_Ap, nullptr, nullptr, nullptr, nullptr, op.d_part1, nullptr,
-                                s0)) != hipSuccess) return e;
-    if ((e = launch_cg_alpha(dm, op.d_part1, op.cg, s0)) != hipSuccess) return e;
-    if ((e = launch_cg_rowblock(1, dm, op.d_p, op.d_Ap, op.cg.alpha, op.d_d, op.d_r, nullptr, op.d_part1, nullptr,
-                                s0)) != hipSuccess) return e;
-    if ((e = launch_cg_beta(dm, op.d_part1, op.cg, s0)) != hipSuccess) return e;
-    return launch_cg_p(dm, op.cg, op.d_r, op.d_p, s0);
+    if ((e = launch_cg_rowblock(CG_DOT, dm, op.d_p, op.d_Ap, nullptr, nullptr, nullptr, op.d_part1, nullptr, nullptr,
+                                op.cg, s0)) != hipSuccess)
+        return e;
+    if ((e = launch_cg_rowblock(CG_UPDATE_UR, dm, op.d_p, op.d_Ap, op.d_d, op.d_r, nullptr, op.d_part2, nullptr,
+                                op.d_part1, op.cg, s0)) != hipSuccess)
+        return e;
+    return launch_cg_rowblock(CG_UPDATE_P, dm, op.d_r, nullptr, nullptr, nullptr, op.d_p, nullptr, nullptr, op.d_part2,
+                              op.cg, s0);
 }
 
 hipGraphExec_t cg_graph(fpde_op& op, bool mixed, int64_t R) {
@@ -979,8 +984,8 @@ int cg_run(fpde_op& op, bool mixed, int64_t R, double tau_in, double rtol, int m
            bool* breakdown) {
     const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
     const int64_t S = (int64_t)op.F * R;
-    hipck(launch_cg_rowblock(3, dm, nullptr, op.d_rout, nullptr, op.d_d, op.d_r, op.d_p, op.d_part1, nullptr, st),
-          "cg start");
+    hipck(launch_cg_rowblock(CG_COPY_RP, dm, nullptr, op.d_rout, op.d_d, op.d_r, op.d_p, op.d_part1, nullptr, nullptr,
+                             op.cg, st), "cg start");
     hipck(launch_cg_start(dm, op.d_part1, op.d_bb, tau_in, rtol, op.cg, st), "cg start");
     hipck(hipMemcpyAsync(op.h_nact, op.cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
     hipck(hipStreamSynchronize(st), "sync");
@@ -1009,8 +1014,8 @@ double outer_residual(fpde_op& op, const double* b, double* u, int64_t R, hipStr
     const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
     const int64_t S = (int64_t)op.F * R;
     apply_impl(op, FPDE_PART_ALL | FPDE_PART_FP64, FPDE_F64, u, op.d_Ap, R, st);
-    hipck(launch_cg_rowblock(2, dm, op.d_Ap, b, nullptr, nullptr, op.d_rout, nullptr, op.d_part1, op.d_part2, st),
-          "residual");
+    hipck(launch_cg_rowblock(CG_RESID, dm, op.d_Ap, b, nullptr, op.d_rout, nullptr, op.d_part1, op.d_part2, nullptr,
+                             op.cg, st), "residual");
     hipck(launch_cg_sum2(dm, op.d_part1, op.d_part2, op.d_rro, op.d_bb, st), "residual norms");
     std::vector<double> rr(S), bb(S);
     hipck(hipMemcpyAsync(rr.data(), op.d_rro, sizeof(double) * S, hipMemcpyDeviceToHost, st), "copy");
@@ -1024,8 +1029,10 @@ double outer_residual(fpde_op& op, const double* b, double* u, int64_t R, hipStr
     return worst;
 }
 
-// Inner relative tolerance of the mixed-precision CG inside the refinement loop.
-constexpr double kMixedInnerTol = 1e-4;
+// Inner relative tolerance of the mixed-precision CG inside the refinement loop:
+// sqrt(rtol), so that two passes reach rtol when the mixed operator is accurate
+// enough (a pass whose reduction falls short is followed by another one).
+double mixed_inner_tol(double rtol) { return std::min(1e-2, std::max(1e-7, std::sqrt(rtol))); }
 constexpr int kMaxRefinements = 60;
 
 void solve_impl(fpde_op& op, const double* b, double* u, int64_t R, double rtol, int maxit, fpde_solve_info* info,
@@ -1041,7 +1048,7 @@ void solve_impl(fpde_op& op, const double* b, double* u, int64_t R, double rtol,
     double worst = outer_residual(op, b, u, R, st), best = worst;
     int stalls = 0;
     while (worst > rtol && total < maxit && outer < kMaxRefinements) {
-        const double tau = op.mixed ? kMixedInnerTol : 0.0;
+        const double tau = op.mixed ? mixed_inner_tol(rtol) : 0.0;
         bool bd = false;
         total += cg_run(op, op.mixed, R, tau, 0.5 * rtol, maxit - total, st, &bd);
         breakdown = breakdown || bd;

@@ -225,17 +225,18 @@ struct CgDims {
     int64_t nb;     // row blocks of the reductions (cg_row_blocks)
 };
 struct CgScalars {  // device arrays of S entries (n_active: one int)
-    double *rr, *alpha, *beta, *tol2;
-    int *active, *iters, *flags, *n_active;
+    double *rr, *rr_next, *alpha, *beta, *tol2;
+    int *active, *active_next, *iters, *flags, *n_active;
 };
+enum { CG_DOT = 0, CG_UPDATE_UR = 1, CG_RESID = 2, CG_COPY_RP = 3, CG_UPDATE_P = 4 };
 int64_t cg_row_blocks(int64_t N, int R);
-// op 0: part1 = a.b;  1: u += alpha a, r -= alpha b, part1 = r.r;
-// 2: r = b - a, part1 = r.r, part2 = b.b;  3: r = p = b, u = 0, part1 = b.b
-hipError_t launch_cg_rowblock(int op, const CgDims& d, const double* a, const double* b, const double* alpha,
-                              double* u, double* r, double* p, double* part1, double* part2, hipStream_t st);
-hipError_t launch_cg_alpha(const CgDims& d, const double* part, const CgScalars& c, hipStream_t st);
-hipError_t launch_cg_beta(const CgDims& d, const double* part, const CgScalars& c, hipStream_t st);
-hipError_t launch_cg_p(const CgDims& d, const CgScalars& c, const double* r, double* p, hipStream_t st);
+// One row-block pass (see fpde_solve.hip): CG_DOT part1 = a.b; CG_UPDATE_UR u += alpha a,
+// r -= alpha b, part1 = r.r; CG_UPDATE_P p = a + beta p; CG_RESID r = b - a, part1 = r.r,
+// part2 = b.b; CG_COPY_RP r = p = b, u = 0, part1 = b.b.  part_in: the partials the
+// coefficient of CG_UPDATE_UR / CG_UPDATE_P is summed from.
+hipError_t launch_cg_rowblock(int op, const CgDims& d, const double* a, const double* b, double* u, double* r,
+                              double* p, double* part1, double* part2, const double* part_in, const CgScalars& c,
+                              hipStream_t st);
 hipError_t launch_cg_start(const CgDims& d, const double* part, const double* bb0, double tau_in, double rtol,
                            const CgScalars& c, hipStream_t st);
 hipError_t launch_cg_sum2(const CgDims& d, const double* part1, const double* part2, double* o1, double* o2,
