@@ -112,8 +112,9 @@ def test_closed_form_interval():
 @pytest.mark.slow
 def test_closed_form_disk():
     # The singular rules' relative error does not shrink with h at fixed n when
-    # s_bar > s (Remark 4.3: n must grow like log(1/h)); with 3 points per
-    # direction the error plateaus near 2%, with 6 it keeps decreasing.
+    # s_bar > s (the remark on the quadrature order in Sec. 4.4: n must grow like
+    # log(1/h)); with 3 points per direction the error plateaus near 2%, with 6
+    # it keeps decreasing.
     errs = [_closed_form_error(configs.disk(n, s_const=0.7, nq_sing=6)) for n in (8, 16)]
     assert errs[1] < 0.75 * errs[0], errs
     assert errs[1] < 0.01, errs
