@@ -61,7 +61,7 @@ def rho_direct(mesh, s, kappa, opts, Q=None, targets=None):
     if targets is None:
         targets = np.flatnonzero(mesh.cell_interior[Q["cell"]] > 0)
     allp = np.arange(Q["w"].size)
-    out = np.zeros(targets.size)
+    out = np.zeros(targets.size, dtype=np.result_type(Q["s"], Q["k"], np.float64))
     ch = max(1, 2_000_000 // allp.size)
     for s0 in range(0, targets.size, ch):
         ia = targets[s0:s0 + ch]
@@ -109,7 +109,7 @@ def assemble_split(mesh, s, kappa, opts):
     rho = rho_direct(mesh, s, kappa, opts, Q, qi) + rho_exterior_at(mesh, s, kappa, opts, Q, qi)
     M = mass_from_rho(mesh, Q, qi, rho, N)
     P = _shape_matrix(mesh, Q, qi, N)
-    K = np.zeros((N, N))
+    K = np.zeros((N, N), dtype=np.result_type(s, kappa, np.float64))
     ch = max(1, 4_000_000 // qi.size)
     for s0 in range(0, qi.size, ch):
         ia = qi[s0:s0 + ch]

@@ -114,7 +114,7 @@ def locate(mesh, pts: np.ndarray, tol: float = 1e-12):
 def field_at_points(mesh, field: np.ndarray, pts: np.ndarray):
     """P1 interpolation of a nodal field at arbitrary points (nearest node outside)."""
     cell, lam = locate(mesh, pts)
-    out = np.empty(pts.shape[1])
+    out = np.empty(pts.shape[1], dtype=np.result_type(field, np.float64))
     ok = cell >= 0
     out[ok] = (field[mesh.cells[:, cell[ok]]] * lam[:, ok]).sum(axis=0)
     out[~ok] = field[lam[0, ~ok].astype(np.int64)]

@@ -214,7 +214,7 @@ def assemble_K_h2(mesh, s, kappa, opts, K_exact=None, return_parts=False):
     if K_exact is None:
         from .assembly import assemble_split
         K_exact = assemble_split(mesh, s, kappa, opts)["K"]
-    K = np.zeros((N, N))
+    K = np.zeros((N, N), dtype=np.result_type(s, kappa, np.float64))
     for a, b in near:
         ra, rb = tree.members[a], tree.members[b]
         K[np.ix_(ra, rb)] = K_exact[np.ix_(ra, rb)]
@@ -258,7 +258,7 @@ def rho_h2(mesh, s, kappa, opts, Q=None, return_parts=False):
     far, near = partition(tree, lo, hi, opts["eta"], 2.0 * mesh.h_max())
     T = touching_cells(mesh)
     is_int = mesh.cell_interior[Q["cell"]] > 0
-    rho = np.zeros(nq)
+    rho = np.zeros(nq, dtype=np.result_type(s, kappa, np.float64))
     for a, b in near:
         ta = tree.members[a][is_int[tree.members[a]]]
         if ta.size == 0:

@@ -196,7 +196,7 @@ def local_matrix_2d(kind, X0, X1, s0, s1, k0, k1, a_scale, s_bar, n):
         xi = Z ** (1.0 / (4.0 - 2.0 * sb))
         regs = _vertex_regions(xi, E1, E2, E3) if kind == "V" else _edge_regions(xi, E1, E2, E3)
         nd = 5 if kind == "V" else 4
-        A = np.zeros((nd, nd))
+        A = np.zeros((nd, nd), dtype=np.result_type(s0, s1, k0, k1, np.float64))
         for xh, yh, phi, (a, b), fac in regs:
             lx = _lam(xh)
             ly = _lam(yh)
@@ -211,7 +211,7 @@ def local_matrix_2d(kind, X0, X1, s0, s1, k0, k1, a_scale, s_bar, n):
     if kind == "I":
         xi = Z ** (1.0 / (4.0 - 2.0 * sb))
         e2 = E2 ** (1.0 / (2.0 - 2.0 * sb))          # eta2 = t^{1/(2-2 s_bar)}
-        A = np.zeros((3, 3))
+        A = np.zeros((3, 3), dtype=np.result_type(s0, k0, np.float64))
         for xh, yh, psi, dh in _identical_regions(xi, E1, e2, E3):
             lx = _lam(xh)
             ly = _lam(yh)
@@ -256,7 +256,7 @@ def local_matrix_1d(kind, x0, x1, s0, s1, k0, k1, a_scale, s_bar, n):
         h1 = abs(x0[1] - x0[0])
         h2 = abs(x1[1] - x1[0])
         xi = Z ** (1.0 / (3.0 - 2.0 * sb))
-        A = np.zeros((3, 3))
+        A = np.zeros((3, 3), dtype=np.result_type(s0, s1, k0, k1, np.float64))
         for al_t, be_t in ((np.ones_like(U), U), (U, np.ones_like(U))):
             al = xi * al_t
             be = xi * be_t
@@ -294,7 +294,7 @@ def assemble_B(mesh, s, kappa, opts, all_columns=False, rows=None):
     """
     N = mesh.n_dofs
     ncol = mesh.n_nodes if all_columns else N
-    B = np.zeros((N, ncol))
+    B = np.zeros((N, ncol), dtype=np.result_type(s, kappa, np.float64))
     want = None if rows is None else set(int(r) for r in rows)
     a_scale = opts["a_scale"]
     sb = opts["s_bar"]
