@@ -182,6 +182,26 @@ fpde_status fpde_load_vector(fpde_op *op, const double *f_nodal, double *F, void
 fpde_status fpde_solve(fpde_op *op, const double *F, double *u, int64_t nrhs, double rtol,
                        int32_t maxit, fpde_solve_info *info, void *hip_stream);
 
+/* Gradient of J = sum_r w_r^T A_h(s, kappa) u_r with respect to the nodal
+ * order s_j and diffusivity kappa_j of every mesh node and field: the
+ * derivative of the discrete bilinear form of Sec. 2-3 (A_h as built, Thm. 6.2)
+ * for fixed s_bar.  Every dependence goes through the kernel
+ * a_scale sqrt(kappa(x) kappa(y)) |x-y|^{-(d+s(x)+s(y))} at the quadrature and
+ * Chebyshev points of the singular rules (Sec. 4), the near and far blocks of
+ * K~ (Sec. 5) and the density of M~ (Sec. 6.2, eq. e:rho); the P1 weights of
+ * s and kappa at those points carry it to the nodes.  For u the solution of
+ * A_h u = F and w the solution of A_h w = g, dJ(u)/ds = -grad_s(w, u) gives
+ * the gradient of an objective through the solve.
+ *   w, u        device [F][N][nrhs] double (dof vectors), must not alias the outputs
+ *   grad_s,
+ *   grad_kappa  device [F][n_nodes] double, overwritten (summed over nrhs)
+ * Asynchronous on hip_stream.  Costs about one build of B, the near blocks and
+ * the density (no operator data is re-stored).
+ * Errors: FPDE_EINVAL, FPDE_ESTATE (plan-only operator, or partitions that are
+ * not symmetric / nq_reg too large, reported by fpde_last_error), FPDE_EDEVICE. */
+fpde_status fpde_apply_adjoint(fpde_op *op, const double *w, const double *u, int64_t nrhs,
+                               double *grad_s, double *grad_kappa, void *hip_stream);
+
 /* Device-time profile of fpde_apply.  While profiling is on, each apply runs
  * the same kernels as its captured graph, serialised on the apply's stream,
  * with HIP events: far = the H2 chain (upsweep, top levels, coupling), out =

@@ -30,6 +30,7 @@ SOURCES = [
     ("fpde_apply.hip", HIP_FLAGS),
     ("fpde_multi.hip", HIP_FLAGS),
     ("fpde_solve.hip", HIP_FLAGS),
+    ("fpde_adjoint.hip", HIP_FLAGS),
     ("fpde_host.cpp", HOST_FLAGS),
     ("fpde_plan.cpp", HOST_FLAGS),
 ]

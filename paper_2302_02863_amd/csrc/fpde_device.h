@@ -24,6 +24,9 @@ __device__ __forceinline__ double ldx(const void* x, int64_t i, int dtype) {
     return dtype == 0 ? ((const double*)x)[i] : (double)((const float*)x)[i];
 }
 
+// |d|^{-e} from |d|^2: exp(-e/2 * log(r2))
+__device__ __forceinline__ double rpow(double r2, double e) { return exp(-0.5 * e * log(r2)); }
+
 // sum over the 64 lanes of a wavefront
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -182,6 +182,28 @@ struct fpde_op {
     hipStream_t stream2 = nullptr;            // side stream of the captured fork/join graph
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double* d_tmp = nullptr;                  // [F][nfar][k][R] per-pair coupling products
+    // ---- adjoint (fpde_apply_adjoint): build data kept on the device
+    struct {
+        bool ok = false;
+        std::string why;                      // reason when the adjoint is unavailable
+        double *s = nullptr, *k = nullptr;    // nodal fields [F][M]
+        double *qx = nullptr, *qs = nullptr, *qk = nullptr;   // quadrature points, s and sqrt(kappa) there
+        uint8_t* qint = nullptr;
+        int32_t* pairs = nullptr;             // singular pair rows (device order)
+        double *g = nullptr, *w = nullptr;    // Gauss rule of the singular rules
+        int64_t *slot_ptr = nullptr, *slot_idx = nullptr;   // node -> pair * 12 + slot
+        TreeDev rdev;                         // density tree
+        int64_t *rnear_ptr = nullptr, *rnear_src = nullptr;
+        int64_t n_icells = 0;
+        int64_t *icells = nullptr, *cell_leaf_ptr = nullptr, *patch_ptr = nullptr, *patch_cell = nullptr;
+        int32_t *cell_leaf = nullptr, *leaf_of_node = nullptr;
+        int64_t *kst_ptr = nullptr, *kst_idx = nullptr, *rst_ptr = nullptr, *rst_idx = nullptr;
+        double *kst_w = nullptr, *rst_w = nullptr;   // Chebyshev-node stencils: node -> (cluster K + alpha)
+        // workspace
+        int64_t ws_R = 0;
+        double *out12 = nullptr, *Ds = nullptr, *Dk = nullptr, *c = nullptr, *xw = nullptr, *xu = nullptr;
+        double *chat = nullptr, *mom = nullptr, *Gs = nullptr, *Gk = nullptr, *rGs = nullptr, *rGk = nullptr;
+    } adj;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -254,11 +276,15 @@ H2Tree make_h2(const Tree& t, const TreeDev& d, int p) {
 
 // Chebyshev axes of every cluster and P1 values of s, sqrt(kappa) at the nodes
 void cluster_nodes(const fpde_op& op, const Tree& t, const Locator& loc, std::vector<double>& axes,
-                   std::vector<double>& ns, std::vector<double>& nk) {
+                   std::vector<double>& ns, std::vector<double>& nk, std::vector<int64_t>* st_node = nullptr,
+                   std::vector<double>* st_w = nullptr) {
     const int d = t.dim, p = op.opts.cheb_p, k = d == 2 ? p * p : p;
     axes.assign(t.ncl * d * p, 0.0);
     ns.assign((int64_t)op.F * t.ncl * k, 0.0);
     nk.assign((int64_t)op.F * t.ncl * k, 0.0);
+    // stencil of every node: up to 3 (mesh node, P1 weight); node -1 pads
+    if (st_node) st_node->assign(t.ncl * k * 3, -1);
+    if (st_w) st_w->assign(t.ncl * k * 3, 0.0);
     const int64_t M = op.mesh.M;
     for (int64_t c = 0; c < t.ncl; ++c) {
         double* ax = &axes[c * d * p];
@@ -268,6 +294,18 @@ void cluster_nodes(const fpde_op& op, const Tree& t, const Locator& loc, std::ve
             double lam[3];
             int64_t node = -1;
             int64_t cell = loc.locate(x, lam, &node);
+            if (st_node) {
+                const int64_t o = (c * k + al) * 3;
+                if (cell < 0) {
+                    (*st_node)[o] = node;
+                    (*st_w)[o] = 1.0;
+                } else {
+                    for (int a = 0; a <= d; ++a) {
+                        (*st_node)[o + a] = op.mesh.v(a, cell);
+                        (*st_w)[o + a] = lam[a];
+                    }
+                }
+            }
             for (int f = 0; f < op.F; ++f) {
                 const double* sf = &op.s[(int64_t)f * M];
                 const double* kf = &op.kappa[(int64_t)f * M];
@@ -289,6 +327,32 @@ void cluster_nodes(const fpde_op& op, const Tree& t, const Locator& loc, std::ve
             }
         }
     }
+}
+
+// node -> list of (index, weight), entries sorted by (node, index)
+void node_csr(int64_t M, const std::vector<int64_t>& st_node, const std::vector<double>& st_w, int per,
+              std::vector<int64_t>& ptr, std::vector<int64_t>& idx, std::vector<double>& wts) {
+    std::vector<std::tuple<int64_t, int64_t, double>> e;
+    for (size_t i = 0; i < st_node.size(); ++i)
+        if (st_node[i] >= 0) e.emplace_back(st_node[i], (int64_t)(i / per), st_w[i]);
+    std::sort(e.begin(), e.end());
+    ptr.assign(M + 1, 0);
+    for (auto& x : e) ptr[std::get<0>(x) + 1]++;
+    for (int64_t i = 0; i < M; ++i) ptr[i + 1] += ptr[i];
+    idx.resize(e.size());
+    wts.resize(e.size());
+    for (size_t i = 0; i < e.size(); ++i) {
+        idx[i] = std::get<1>(e[i]);
+        wts[i] = std::get<2>(e[i]);
+    }
+}
+
+bool symmetric_pairs(std::vector<std::pair<int64_t, int64_t>> v) {
+    std::vector<std::pair<int64_t, int64_t>> w;
+    for (auto& p : v) w.push_back({p.second, p.first});
+    std::sort(v.begin(), v.end());
+    std::sort(w.begin(), w.end());
+    return v == w;
 }
 
 void far_csr(const Tree& t, const std::vector<std::pair<int64_t, int64_t>>& far,
@@ -434,6 +498,8 @@ void build_device(fpde_op& op) {
     op.d_cint = A.upload(m.interior, st);
     double* d_s = A.upload(op.s, st);
     double* d_k = A.upload(op.kappa, st);
+    op.adj.s = d_s;
+    op.adj.k = d_k;
     double* d_qx = A.upload(op.Q.x, st);
     op.d_qw = A.upload(op.Q.w, st);
     uint8_t* d_qint = A.upload(op.Q.q_int, st);
@@ -491,7 +557,26 @@ void build_device(fpde_op& op) {
         op.d_B = A.alloc<double>((int64_t)F * nnz);
         hipck(launch_segsum(nnz, d_cptr, d_cidx, nullptr, F, d_loc, np * 25, op.d_B, st), "segsum B");
         hipck(hipStreamSynchronize(st), "singular sync");
-        A.release(d_loc); A.release(d_cptr); A.release(d_cidx); A.release(d_pairs);
+        A.release(d_loc); A.release(d_cptr); A.release(d_cidx);
+        // adjoint: node -> (pair, slot) over the 6 cell-vertex slots of every pair
+        {
+            std::vector<int64_t> sn(np * 6);
+            std::vector<double> sw(np * 6, 1.0);
+            for (int64_t gp = 0; gp < np; ++gp)
+                for (int a = 0; a < 6; ++a) {
+                    const bool used = d == 2 || (a % 3) < 2;   // 1D rows use slots 0,1 and 3,4
+                    sn[gp * 6 + a] = used ? prow[gp * 8 + 1 + a] : -1;
+                }
+            std::vector<int64_t> sp, si;
+            std::vector<double> swt;
+            node_csr(m.M, sn, sw, 1, sp, si, swt);
+            for (auto& x : si) x = (x / 6) * 12 + (x % 6);   // entry -> pair * 12 + slot
+            op.adj.slot_ptr = A.upload(sp, st);
+            op.adj.slot_idx = A.upload(si, st);
+            op.adj.pairs = d_pairs;
+            op.adj.g = d_g;
+            op.adj.w = d_w;
+        }
         op.stats.t_singular_ms = tm.stop();
     }
 
@@ -501,8 +586,17 @@ void build_device(fpde_op& op) {
         const Tree& rt = op.rt;
         Locator loc;
         loc.build(m);
-        std::vector<double> axes, ns, nk;
-        cluster_nodes(op, rt, loc, axes, ns, nk);
+        std::vector<double> axes, ns, nk, stw;
+        std::vector<int64_t> stn;
+        cluster_nodes(op, rt, loc, axes, ns, nk, &stn, &stw);
+        {
+            std::vector<int64_t> sp, si;
+            std::vector<double> swt;
+            node_csr(m.M, stn, stw, 3, sp, si, swt);
+            op.adj.rst_ptr = A.upload(sp, st);
+            op.adj.rst_idx = A.upload(si, st);
+            op.adj.rst_w = A.upload(swt, st);
+        }
         std::vector<int64_t> fptr, fsrc, nptr, nsrc;
         far_csr(rt, op.rfar, fptr, fsrc);
         // near by leaf index
@@ -541,10 +635,35 @@ void build_device(fpde_op& op) {
                                       std::sqrt(op.opts.kappa_exterior), op.opts.a_scale, op.opts.n_theta,
                                       op.d_rho, st), "rho exterior");
         hipck(hipStreamSynchronize(st), "rho sync");
-        for (void* q : {(void*)td.beg, (void*)td.end, (void*)td.perm, (void*)td.axes, (void*)td.node_s,
-                        (void*)td.node_k, (void*)td.far_ptr, (void*)td.far_src, (void*)td.E, (void*)d_nptr,
-                        (void*)d_nsrc, (void*)xh, (void*)yh})
-            A.release(q);
+        A.release(xh);
+        A.release(yh);
+        A.release(d_nptr);
+        A.release(d_nsrc);
+        // the density tree stays for the adjoint, with the pair lists closed under
+        // transposition: the partition leaves out targets without interior points,
+        // the adjoint's target-major sums need those pairs too
+        op.adj.rdev = td;
+        {
+            auto closure = [](std::vector<std::pair<int64_t, int64_t>> v) {
+                const size_t n = v.size();
+                for (size_t i = 0; i < n; ++i) v.push_back({v[i].second, v[i].first});
+                std::sort(v.begin(), v.end());
+                v.erase(std::unique(v.begin(), v.end()), v.end());
+                return v;
+            };
+            const auto afar = closure(op.rfar), anear = closure(op.rnear);
+            std::vector<int64_t> ap, as, bp(rt.nleaf() + 1, 0), bs;
+            far_csr(rt, afar, ap, as);
+            for (auto& pr : anear) bp[pr.first - rt.first_leaf() + 1]++;
+            for (int64_t i = 0; i < rt.nleaf(); ++i) bp[i + 1] += bp[i];
+            for (auto& pr : anear) bs.push_back(pr.second);
+            op.adj.rdev.far_ptr = A.upload(ap, st);
+            op.adj.rdev.far_src = A.upload(as, st);
+            op.adj.rnear_ptr = A.upload(bp, st);
+            op.adj.rnear_src = A.upload(bs, st);
+            A.release(td.far_ptr);
+            A.release(td.far_src);
+        }
         op.stats.t_rho_ms = tm.stop();
 
         Timer tm2(st);
@@ -589,8 +708,17 @@ void build_device(fpde_op& op) {
         const Tree& kt = op.kt;
         Locator loc;
         loc.build(m);
-        std::vector<double> axes, ns, nk;
-        cluster_nodes(op, kt, loc, axes, ns, nk);
+        std::vector<double> axes, ns, nk, stw;
+        std::vector<int64_t> stn;
+        cluster_nodes(op, kt, loc, axes, ns, nk, &stn, &stw);
+        {
+            std::vector<int64_t> sp, si;
+            std::vector<double> swt;
+            node_csr(m.M, stn, stw, 3, sp, si, swt);
+            op.adj.kst_ptr = A.upload(sp, st);
+            op.adj.kst_idx = A.upload(si, st);
+            op.adj.kst_w = A.upload(swt, st);
+        }
         std::vector<int64_t> fptr, fsrc;
         far_csr(kt, op.kfar, fptr, fsrc);
         TreeDev& td = op.kdev;
@@ -712,9 +840,49 @@ void build_device(fpde_op& op) {
             hipck(hipStreamSynchronize(st), "pack sync");
             A.release(d_pcol_off);
         }
-        for (void* q : {(void*)np.tgt, (void*)np.src, (void*)np.patch_ptr, (void*)np.patch_cell,
-                        (void*)np.row_ptr, (void*)np.row_lcell, (void*)np.row_slot})
+        for (void* q : {(void*)np.tgt, (void*)np.src, (void*)np.row_ptr, (void*)np.row_lcell, (void*)np.row_slot})
             A.release(q);
+        {   // adjoint of the near blocks: patches, leaf of every dof, leaves whose patch holds a cell
+            op.adj.patch_ptr = (int64_t*)np.patch_ptr;
+            op.adj.patch_cell = (int64_t*)np.patch_cell;
+            std::vector<int32_t> lon(m.M, -1);
+            for (int64_t li = 0; li < nleaf; ++li)
+                for (int64_t j = leaf_beg[li]; j < leaf_beg[li + 1]; ++j) lon[kt.perm[j]] = (int32_t)li;
+            std::vector<int64_t> icells, slot_of_cell(m.nc, -1);
+            for (int64_t c = 0; c < m.nc; ++c)
+                if (m.interior[c]) {
+                    slot_of_cell[c] = (int64_t)icells.size();
+                    icells.push_back(c);
+                }
+            std::vector<std::pair<int64_t, int32_t>> cl;
+            for (int64_t li = 0; li < nleaf; ++li)
+                for (int64_t e = patch_ptr[li]; e < patch_ptr[li + 1]; ++e)
+                    if (slot_of_cell[patch_cell[e]] >= 0) cl.push_back({slot_of_cell[patch_cell[e]], (int32_t)li});
+            std::sort(cl.begin(), cl.end());
+            std::vector<int64_t> clp(icells.size() + 1, 0);
+            std::vector<int32_t> cll(cl.size());
+            for (size_t i = 0; i < cl.size(); ++i) {
+                clp[cl[i].first + 1]++;
+                cll[i] = cl[i].second;
+            }
+            for (size_t i = 0; i < icells.size(); ++i) clp[i + 1] += clp[i];
+            op.adj.n_icells = (int64_t)icells.size();
+            op.adj.icells = A.upload(icells, st);
+            op.adj.cell_leaf_ptr = A.upload(clp, st);
+            op.adj.cell_leaf = A.upload(cll, st);
+            op.adj.leaf_of_node = A.upload(lon, st);
+            op.adj.ok = true;
+            if (!symmetric_pairs(op.knear) || !symmetric_pairs(op.kfar)) {
+                op.adj.ok = false;
+                op.adj.why = "the near/far partitions are not symmetric";
+            } else if (nqe > 16) {
+                op.adj.ok = false;
+                op.adj.why = "more than 16 quadrature points per cell (nq_reg)";
+            } else if (k > 64) {
+                op.adj.ok = false;
+                op.adj.why = "more than 64 Chebyshev nodes per cluster";
+            }
+        }
         op.stats.t_near_blocks_ms = tm2.stop();
         std::vector<int32_t> cdof(op.csr_col.size());
         for (size_t e = 0; e < cdof.size(); ++e) cdof[e] = (int32_t)kt.perm[op.csr_col[e]];
@@ -750,12 +918,11 @@ void build_device(fpde_op& op) {
         hipck(hipStreamSynchronize(st), "tickets sync");
     }
     // keep only what apply / load / export need
-    A.release(d_qs);
-    A.release(d_qk);
-    A.release(d_qx);
-    A.release(d_qint);
-    A.release(d_s);
-    A.release(d_k);
+    // quadrature points and fields stay for the adjoint
+    op.adj.qx = d_qx;
+    op.adj.qs = d_qs;
+    op.adj.qk = d_qk;
+    op.adj.qint = d_qint;
     op.stats.t_total_ms = ms_since(t_all) + op.stats.t_plan_ms;
 }
 
@@ -809,13 +976,8 @@ void ensure_ws(fpde_op& op, int64_t R) {
     op.ws_R = R;
 }
 
-// Enqueue one apply on s0 (far chain forked to s1 through fk/jn when s1 != s0).
-// ev: optional 5 profiling events (requires s1 == s0).  Capturable.
-hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void* y, int64_t R, hipStream_t s0,
-                         hipStream_t s1, hipEvent_t fk, hipEvent_t jn, hipEvent_t* ev) {
-    const int F = op.F, p = op.opts.cheb_p;
+ApplyPlan make_apply_plan(const fpde_op& op, const H2Tree& h) {
     const Tree& kt = op.kt;
-    H2Tree h = make_h2(kt, op.kdev, p);
     ApplyPlan a{};
     a.N = op.mesh.N;
     a.nleaf = kt.nleaf();
@@ -833,6 +995,17 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
     a.npairs = (int64_t)op.knear.size();
     a.U = op.d_U;
     a.k = h.k;
+    return a;
+}
+
+// Enqueue one apply on s0 (far chain forked to s1 through fk/jn when s1 != s0).
+// ev: optional 5 profiling events (requires s1 == s0).  Capturable.
+hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void* y, int64_t R, hipStream_t s0,
+                         hipStream_t s1, hipEvent_t fk, hipEvent_t jn, hipEvent_t* ev) {
+    const int F = op.F, p = op.opts.cheb_p;
+    const Tree& kt = op.kt;
+    H2Tree h = make_h2(kt, op.kdev, p);
+    const ApplyPlan a = make_apply_plan(op, h);
     const double* cv = nullptr;
     if ((parts & FPDE_PART_B) && (parts & FPDE_PART_M)) cv = op.d_BM;
     else if (parts & FPDE_PART_B) cv = op.d_B;
@@ -902,6 +1075,120 @@ void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64
         it = op.graphs.emplace(key, ex).first;
     }
     hipck(hipGraphLaunch(it->second, st), "graph launch");
+}
+
+// ------------------------------------------------------------------ adjoint
+
+void ensure_adj_ws(fpde_op& op, int64_t R) {
+    auto& J = op.adj;
+    if (J.ws_R >= R) return;
+    Arena& A = op.arena;
+    for (void* q : {(void*)J.out12, (void*)J.Ds, (void*)J.Dk, (void*)J.c, (void*)J.xw, (void*)J.xu, (void*)J.chat,
+                    (void*)J.mom, (void*)J.Gs, (void*)J.Gk, (void*)J.rGs, (void*)J.rGk})
+        if (q) A.release(q);
+    const int64_t F = op.F, k = op.kt.ncl > 0 ? (op.mesh.dim == 2 ? op.opts.cheb_p * op.opts.cheb_p : op.opts.cheb_p) : 1;
+    const int64_t nq = op.Q.nq, np = (int64_t)op.pairs.size();
+    J.out12 = A.alloc<double>(F * np * 12);
+    J.Ds = A.alloc<double>(F * nq);
+    J.Dk = A.alloc<double>(F * nq);
+    J.c = A.alloc<double>(F * nq);
+    J.xw = A.alloc<double>(F * op.kt.ncl * k * R);
+    J.xu = A.alloc<double>(F * op.kt.ncl * k * R);
+    J.Gs = A.alloc<double>(F * op.kt.ncl * k);
+    J.Gk = A.alloc<double>(F * op.kt.ncl * k);
+    J.chat = A.alloc<double>(F * op.rt.ncl * k);
+    J.mom = A.alloc<double>(F * op.rt.ncl * k);
+    J.rGs = A.alloc<double>(F * op.rt.ncl * k);
+    J.rGk = A.alloc<double>(F * op.rt.ncl * k);
+    J.ws_R = R;
+}
+
+// gs, gk [F][M] = d/ds_j, d/dkappa_j of sum_r w_r^T A_h u_r
+void adjoint_impl(fpde_op& op, const double* w, const double* u, int64_t R, double* gs, double* gk, hipStream_t st) {
+    if (op.plan_only) fail(FPDE_ESTATE, "operator was built with FPDE_FLAG_PLAN_ONLY");
+    if (!op.adj.ok) fail(FPDE_ESTATE, "adjoint unavailable: " + op.adj.why);
+    if (!w || !u || !gs || !gk || R < 1) fail(FPDE_EINVAL, "bad vectors");
+    ensure_ws(op, R);
+    ensure_adj_ws(op, R);
+    auto& J = op.adj;
+    const HostMesh& m = op.mesh;
+    const int d = m.dim, F = op.F, p = op.opts.cheb_p, k = d == 2 ? p * p : p;
+    const int64_t M = m.M, N = m.N, nq = op.Q.nq, np = (int64_t)op.pairs.size();
+    const int nqe = op.Q.nqe;
+    const double as = op.opts.a_scale;
+    hipck(launch_fill((int64_t)F * M, 0.0, gs, st), "fill");
+    hipck(launch_fill((int64_t)F * M, 0.0, gk, st), "fill");
+    // singular pairs (B)
+    hipck(launch_adj_singular(d, np, J.pairs, op.d_X, M, F, J.s, J.k, as, op.opts.s_bar, op.opts.nq_sing, J.g, J.w, w,
+                              u, N, (int)R, J.out12, st), "adjoint singular");
+    hipck(launch_adj_gather(M, J.slot_ptr, J.slot_idx, nullptr, J.out12, np * 12, F, gs, M, st), "gather");
+    hipck(launch_adj_gather(M, J.slot_ptr, J.slot_idx, nullptr, J.out12 + 6, np * 12, F, gk, M, st), "gather");
+    // point densities: near blocks of K~, density near sums and exterior
+    hipck(launch_fill((int64_t)F * nq, 0.0, J.Ds, st), "fill");
+    hipck(launch_fill((int64_t)F * nq, 0.0, J.Dk, st), "fill");
+    AdjKnear P{};
+    P.dim = d;
+    P.nqe = nqe;
+    P.R = (int)R;
+    P.nc = m.nc;
+    P.nq = nq;
+    P.N = N;
+    P.cells = op.d_C;
+    P.qx = J.qx;
+    P.qw = op.d_qw;
+    P.qs = J.qs;
+    P.qk = J.qk;
+    P.lam = op.d_lam;
+    P.icells = J.icells;
+    P.cell_leaf_ptr = J.cell_leaf_ptr;
+    P.cell_leaf = J.cell_leaf;
+    P.near_ptr = op.d_near_ptr;
+    P.near_src = op.d_near_src;
+    P.patch_ptr = J.patch_ptr;
+    P.patch_cell = J.patch_cell;
+    P.leaf_of_node = J.leaf_of_node;
+    P.w = w;
+    P.u = u;
+    P.a_scale = as;
+    for (int r = 0; r < (int)R; ++r) {
+        P.r = r;
+        hipck(launch_adj_knear(P, J.n_icells, F, J.Ds, J.Dk, st), "adjoint near blocks");
+    }
+    hipck(launch_adj_c(d, m.nc, nqe, op.d_C, op.d_cint, op.d_lam, op.d_qw, w, u, N, (int)R, F, J.c, st), "adjoint c");
+    const H2Tree hr = make_h2(op.rt, J.rdev, p);
+    hipck(launch_adj_rho_near(hr, J.rdev.perm, J.rnear_ptr, J.rnear_src, J.qx, op.d_qw, J.qs, J.qk, J.c, nqe, op.d_C,
+                              m.nc, nq, F, as, J.Ds, J.Dk, st), "adjoint density near");
+    if (m.R > 0.0)
+        hipck(launch_adj_rho_ext(d, nq, J.qx, J.qs, J.qk, J.qint, J.c, F, m.R, op.opts.s_exterior,
+                                 std::sqrt(op.opts.kappa_exterior), as, op.opts.n_theta, J.Ds, J.Dk, st),
+              "adjoint exterior");
+    hipck(launch_adj_points(M, op.d_nc_ptr, op.d_nc_cell, op.d_nc_slot, nqe, op.d_lam, J.Ds, J.Dk, nq, F, gs, gk, st),
+          "adjoint points");
+    // far blocks of K~: nested coefficients of w and u
+    const H2Tree hk = make_h2(op.kt, op.kdev, p);
+    const ApplyPlan a = make_apply_plan(op, hk);
+    for (int pass = 0; pass < 2; ++pass) {
+        double* xh = pass == 0 ? J.xw : J.xu;
+        hipck(launch_gather(a, F, (int)R, FPDE_F64, pass == 0 ? w : u, op.d_xt, st), "gather");
+        hipck(launch_leaf_up(a, hk, F, (int)R, op.d_xt, xh, st), "leaf up");
+        for (int lev = op.kt.L - 1; lev >= 0; --lev) hipck(launch_up_level(hk, lev, F, (int)R, xh, st), "up");
+    }
+    const int64_t kf = op.kt.ncl * k;
+    hipck(launch_adj_far(hk, -2.0, as, J.xw, kf * R, J.xu, kf * R, (int)R, F, J.Gs, J.Gk, st), "adjoint far K");
+    hipck(launch_adj_gather(M, J.kst_ptr, J.kst_idx, J.kst_w, J.Gs, kf, F, gs, M, st), "gather");
+    hipck(launch_adj_gather(M, J.kst_ptr, J.kst_idx, J.kst_w, J.Gk, kf, F, gk, M, st), "gather");
+    // far blocks of the density: upsweep of c against the moments of the weights
+    const int64_t rf = op.rt.ncl * k;
+    for (int f = 0; f < F; ++f)
+        hipck(launch_rho_moments(hr, J.rdev.perm, J.qx, J.c + (int64_t)f * nq, nq, 1, J.chat + f * rf, st), "moments");
+    hipck(launch_rho_moments(hr, J.rdev.perm, J.qx, op.d_qw, nq, F, J.mom, st), "moments");
+    for (int lev = op.rt.L - 1; lev >= 0; --lev) {
+        hipck(launch_up_level(hr, lev, F, 1, J.chat, st), "up");
+        hipck(launch_up_level(hr, lev, F, 1, J.mom, st), "up");
+    }
+    hipck(launch_adj_far(hr, 1.0, as, J.chat, rf, J.mom, rf, 1, F, J.rGs, J.rGk, st), "adjoint far density");
+    hipck(launch_adj_gather(M, J.rst_ptr, J.rst_idx, J.rst_w, J.rGs, rf, F, gs, M, st), "gather");
+    hipck(launch_adj_gather(M, J.rst_ptr, J.rst_idx, J.rst_w, J.rGk, rf, F, gk, M, st), "gather");
 }
 
 // ------------------------------------------------------------------ CG solve and iterative refinement
@@ -1190,6 +1477,14 @@ fpde_status fpde_solve(fpde_op* op, const double* Fv, double* u, int64_t nrhs, d
     return guarded([&] {
         if (!op) fail(FPDE_EINVAL, "op is NULL");
         solve_impl(*op, Fv, u, nrhs, rtol, maxit, info, (hipStream_t)hip_stream);
+    });
+}
+
+fpde_status fpde_apply_adjoint(fpde_op* op, const double* w, const double* u, int64_t nrhs, double* grad_s,
+                               double* grad_kappa, void* hip_stream) {
+    return guarded([&] {
+        if (!op) fail(FPDE_EINVAL, "op is NULL");
+        adjoint_impl(*op, w, u, nrhs, grad_s, grad_kappa, (hipStream_t)hip_stream);
     });
 }
 

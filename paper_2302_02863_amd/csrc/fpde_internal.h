@@ -217,6 +217,52 @@ hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelP
                                const void* x, void* y, unsigned int* tickets, hipStream_t st, hipStream_t side,
                                hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
 
+// ---------------------------------------------------------------- adjoint (fpde_adjoint.hip, singular pairs in
+// fpde_kernels.hip): d/ds_j and d/dkappa_j of sum_r w_r^T A_h u_r
+
+// per pair and field: out[f][pair][12] (d/ds at the 6 cell-vertex slots, then d/dkappa)
+hipError_t launch_adj_singular(int dim, int64_t np, const int32_t* pairs, const double* coords, int64_t n_nodes,
+                               int F, const double* s, const double* kappa, double a_scale, double s_bar, int nq,
+                               const double* g01, const double* w01, const double* w, const double* u, int64_t N,
+                               int R, double* out, hipStream_t st);
+struct AdjKnear {
+    int dim, nqe, R, r;                      // r: the right-hand side of this launch
+    int64_t nc, nq, N;
+    const int32_t* cells;
+    const double *qx, *qw, *qs, *qk, *lam;   // qk: sqrt(kappa) at the points
+    const int64_t* icells;                   // interior cells
+    const int64_t* cell_leaf_ptr;            // per interior-cell index: leaves whose patch holds it
+    const int32_t* cell_leaf;
+    const int64_t *near_ptr, *near_src;      // by target leaf index -> source leaf index
+    const int64_t *patch_ptr, *patch_cell;   // by leaf index
+    const int32_t* leaf_of_node;             // [M] leaf index of a dof, -1 for other nodes
+    const double *w, *u;                     // [F][N][R]
+    double a_scale;
+};
+// point densities Ds, Dk [F][nq] (accumulated)
+hipError_t launch_adj_knear(const AdjKnear& P, int64_t n_icells, int F, double* Ds, double* Dk, hipStream_t st);
+hipError_t launch_adj_c(int dim, int64_t nc, int nqe, const int32_t* cells, const uint8_t* cell_int,
+                        const double* lam, const double* qw, const double* w, const double* u, int64_t N, int R,
+                        int F, double* c, hipStream_t st);
+hipError_t launch_adj_rho_near(const H2Tree& t, const int64_t* perm, const int64_t* near_ptr, const int64_t* near_src,
+                               const double* qx, const double* qw, const double* qs, const double* qk,
+                               const double* cq, int nqe, const int32_t* cells, int64_t nc, int64_t nq, int F,
+                               double a_scale, double* Ds, double* Dk, hipStream_t st);
+hipError_t launch_adj_rho_ext(int dim, int64_t nq, const double* qx, const double* qs, const double* qk,
+                              const uint8_t* q_int, const double* cq, int F, double R, double s_out,
+                              double k_out_sqrt, double a_scale, int n_theta, double* Ds, double* Dk,
+                              hipStream_t st);
+// gs, gk [F][M] += sum over the points of the cells of each node of lambda * D
+hipError_t launch_adj_points(int64_t M, const int64_t* nc_ptr, const int64_t* nc_cell, const int8_t* nc_slot, int nqe,
+                             const double* lam, const double* Ds, const double* Dk, int64_t nq, int F, double* gs,
+                             double* gk, hipStream_t st);
+// per Chebyshev node of every cluster: Gs, Gk [F][ncl][K]
+hipError_t launch_adj_far(const H2Tree& t, double fac, double a_scale, const double* a, int64_t af, const double* b,
+                          int64_t bf, int R, int F, double* Gs, double* Gk, hipStream_t st);
+// out[f][i] += sum_e wts[e] src[f][idx[e]]   (wts NULL: 1)
+hipError_t launch_adj_gather(int64_t n, const int64_t* ptr, const int64_t* idx, const double* wts, const double* src,
+                             int64_t src_f, int F, double* out, int64_t out_f, hipStream_t st);
+
 // ---------------------------------------------------------------- CG solve (fpde_solve.hip)
 
 struct CgDims {

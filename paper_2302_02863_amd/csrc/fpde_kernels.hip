@@ -15,8 +15,6 @@
 namespace fpde {
 
 
-// |d|^{-e} from |d|^2: exp(-e/2 * log(r2))
-__device__ __forceinline__ double rpow(double r2, double e) { return exp(-0.5 * e * log(r2)); }
 
 
 // ============================================================ singular pairs
@@ -250,6 +248,258 @@ FPDE_KERNEL void k_singular1d(SingArgs A, int f) {
             double v = wave_sum(acc[e]);
             if (lane == 0) o[i * 5 + j] = v * pre;
         }
+}
+
+// ------------------------------------------------------------ adjoint of the singular pairs
+//
+// d/ds_j and d/dkappa_j of sum_r w_r^T L u_r for one touching pair, L its local
+// matrix.  The substituted integrand is gamma(x, y) Phi Phi^T times factors
+// that do not depend on s (the substitutions of Sec. 4 only rewrite the power
+// |x - y|^{-(2 + s(x) + s(y))}), so with s(x) = sum_a lambda_a(x^) s_a:
+//   d/ds_a  (x side) = integrand * (-ln|x - y|) * lambda_a(x^)   (y side alike),
+//   d/dkappa_a       = integrand * lambda_a(x^) / (2 kappa(x)).
+// |x - y| = xi |J0 a - J1 b| (vertex, edge), xi eta1 eta2 |J0 dhat| (identical).
+// out[f][pair][12]: slots 0..5 d/ds at cell0 v0..v2, cell1 v0..v2 (canonical
+// order), slots 6..11 the same for kappa; multiplied by the pair weight.
+struct AdjVecs {
+    const double* w;   // [F][N][R]
+    const double* u;
+    int64_t N;
+    int R;
+};
+
+FPDE_KERNEL void k_adj_singular2d(SingArgs A, AdjVecs V, int f) {
+    const int lane = threadIdx.x & 63;
+    const int64_t pid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pid >= A.np) return;
+    const int32_t* P = A.pairs + pid * 8;
+    const int kind = P[0];
+    const double* s = A.s + (int64_t)f * A.M;
+    const double* kp = A.kap + (int64_t)f * A.M;
+    double X0[3][2], X1[3][2], s0[3], s1[3], k0[3], k1[3];
+    const int vv0[3] = {P[1], P[2], P[3]};
+    const int vv1[3] = {P[4], P[5], P[6]};
+    for (int a = 0; a < 3; ++a) {
+        X0[a][0] = A.X[vv0[a]]; X0[a][1] = A.X[A.M + vv0[a]];
+        X1[a][0] = A.X[vv1[a]]; X1[a][1] = A.X[A.M + vv1[a]];
+        s0[a] = s[vv0[a]]; s1[a] = s[vv1[a]];
+        k0[a] = kp[vv0[a]]; k1[a] = kp[vv1[a]];
+    }
+    // local dofs of the case (same order as the forward kernel's Phi) and
+    // C[a][b] = sum_r w_r[a] u_r[b] over them
+    const int nd = kind == 0 ? 3 : (kind == 1 ? 4 : 5);
+    int loc[5] = {P[1], P[2], P[3], kind == 1 ? P[6] : P[5], P[6]};
+    double C[5][5];
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b) {
+            double v = 0.0;
+            if (a < nd && b < nd && loc[a] < V.N && loc[b] < V.N)
+                for (int r = 0; r < V.R; ++r)
+                    v += V.w[((int64_t)f * V.N + loc[a]) * V.R + r] * V.u[((int64_t)f * V.N + loc[b]) * V.R + r];
+            C[a][b] = v;
+        }
+    const double J0[2][2] = {{X0[1][0] - X0[0][0], X0[2][0] - X0[1][0]}, {X0[1][1] - X0[0][1], X0[2][1] - X0[1][1]}};
+    const double J1[2][2] = {{X1[1][0] - X1[0][0], X1[2][0] - X1[1][0]}, {X1[1][1] - X1[0][1], X1[2][1] - X1[1][1]}};
+    const double det0 = fabs(J0[0][0] * J0[1][1] - J0[0][1] * J0[1][0]);
+    const double det1 = fabs(J1[0][0] * J1[1][1] - J1[0][1] * J1[1][0]);
+    const int nreg = kind == 0 ? 3 : (kind == 1 ? 5 : 2);
+    const int nq = A.nq;
+    const int n4 = nq * nq * nq * nq;
+    const double sb = A.s_bar;
+    const double inv4 = 1.0 / (4.0 - 2.0 * sb);
+    const double inv2 = 1.0 / (2.0 - 2.0 * sb);
+    double acc[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) acc[e] = 0.0;
+    for (int idx = lane; idx < nreg * n4; idx += 64) {
+        const int r = idx / n4;
+        int q = idx - r * n4;
+        const int i3 = q % nq; q /= nq;
+        const int i2 = q % nq; q /= nq;
+        const int i1 = q % nq;
+        const int i0 = q / nq;
+        const double z = A.g[i0], e1 = A.g[i1], t2 = A.g[i2], e3 = A.g[i3];
+        const double wt = (A.w[i0] * A.w[i1]) * (A.w[i2] * A.w[i3]);
+        const double lz = log(z);
+        double phi[5] = {0, 0, 0, 0, 0};
+        double xa0, xa1, yb0, yb1, r2, fac, sx, sy, kx, ky, lnr;
+        if (kind == 0) {
+            const double e2 = exp(inv2 * log(t2));
+            const double xi = exp(inv4 * lz);
+            double a[2], b[2], dh[2];
+            identical_region(r, e1, e2, e3, a, b, dh);
+            xa0 = xi * a[0]; xa1 = xi * a[1]; yb0 = xi * b[0]; yb1 = xi * b[1];
+            phi[0] = -dh[0]; phi[1] = dh[0] - dh[1]; phi[2] = dh[1];
+            const double d0 = J0[0][0] * dh[0] + J0[0][1] * dh[1];
+            const double d1 = J0[1][0] * dh[0] + J0[1][1] * dh[1];
+            r2 = d0 * d0 + d1 * d1;
+            sx = (1.0 - xa0) * s0[0] + (xa0 - xa1) * s0[1] + xa1 * s0[2];
+            sy = (1.0 - yb0) * s0[0] + (yb0 - yb1) * s0[1] + yb1 * s0[2];
+            kx = (1.0 - xa0) * k0[0] + (xa0 - xa1) * k0[1] + xa1 * k0[2];
+            ky = (1.0 - yb0) * k0[0] + (yb0 - yb1) * k0[1] + yb1 * k0[2];
+            const double ss = sx + sy;
+            fac = exp((2.0 * sb - ss) * inv4 * lz) * exp((2.0 - ss) * log(e1)) *
+                  exp((2.0 * sb - ss) * inv2 * log(t2));
+            lnr = inv4 * lz + log(e1) + inv2 * log(t2) + 0.5 * log(r2);
+        } else {
+            const double xi = exp(inv4 * lz);
+            Reg2 g = kind == 1 ? edge_region(r, e1, t2, e3) : vertex_region(r, e1, t2, e3);
+            xa0 = xi * g.a0; xa1 = xi * g.a1; yb0 = xi * g.b0; yb1 = xi * g.b1;
+            const double la0 = -g.a0, la1 = g.a0 - g.a1, la2 = g.a1;
+            const double lb0 = -g.b0, lb1 = g.b0 - g.b1, lb2 = g.b1;
+            if (kind == 1) {
+                phi[0] = la0 - lb0; phi[1] = la1 - lb1; phi[2] = la2; phi[3] = -lb2;
+            } else {
+                phi[0] = la0 - lb0; phi[1] = la1; phi[2] = la2; phi[3] = -lb1; phi[4] = -lb2;
+            }
+            const double d0 = (J0[0][0] * g.a0 + J0[0][1] * g.a1) - (J1[0][0] * g.b0 + J1[0][1] * g.b1);
+            const double d1 = (J0[1][0] * g.a0 + J0[1][1] * g.a1) - (J1[1][0] * g.b0 + J1[1][1] * g.b1);
+            r2 = d0 * d0 + d1 * d1;
+            sx = (1.0 - xa0) * s0[0] + (xa0 - xa1) * s0[1] + xa1 * s0[2];
+            sy = (1.0 - yb0) * s1[0] + (yb0 - yb1) * s1[1] + yb1 * s1[2];
+            kx = (1.0 - xa0) * k0[0] + (xa0 - xa1) * k0[1] + xa1 * k0[2];
+            ky = (1.0 - yb0) * k1[0] + (yb0 - yb1) * k1[1] + yb1 * k1[2];
+            fac = exp((2.0 * sb - (sx + sy)) * inv4 * lz) * g.jac;
+            lnr = inv4 * lz + 0.5 * log(r2);
+        }
+        double qf = 0.0;
+        for (int a = 0; a < 5; ++a) {
+            double ca = 0.0;
+            for (int b = 0; b < 5; ++b) ca += C[a][b] * phi[b];
+            qf += phi[a] * ca;
+        }
+        const double val = wt * A.a_scale * sqrt(kx * ky) * fac * rpow(r2, 2.0 + sx + sy) * qf;
+        const double vs = -lnr * val;
+        const double lx[3] = {1.0 - xa0, xa0 - xa1, xa1};
+        const double ly[3] = {1.0 - yb0, yb0 - yb1, yb1};
+        const double hx = 0.5 * val / kx, hy = 0.5 * val / ky;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            acc[a] += vs * lx[a];
+            acc[3 + a] += vs * ly[a];
+            acc[6 + a] += hx * lx[a];
+            acc[9 + a] += hy * ly[a];
+        }
+    }
+    double pre = kind == 0 ? det0 * det0 / ((2.0 - sb) * (2.0 - 2.0 * sb)) : det0 * det1 * inv4;
+    if (kind != 0) pre *= 2.0;   // both orderings of a distinct touching pair
+    double* o = A.out + ((int64_t)f * A.np + pid) * 12;
+    for (int e = 0; e < 12; ++e) {
+        const double v = wave_sum(acc[e]);
+        if (lane == 0) o[e] = v * pre;
+    }
+}
+
+FPDE_KERNEL void k_adj_singular1d(SingArgs A, AdjVecs V, int f) {
+    const int lane = threadIdx.x & 63;
+    const int64_t pid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pid >= A.np) return;
+    const int32_t* P = A.pairs + pid * 8;
+    const int kind = P[0];
+    const double* s = A.s + (int64_t)f * A.M;
+    const double* kp = A.kap + (int64_t)f * A.M;
+    const int nq = A.nq;
+    const double sb = A.s_bar;
+    auto val_of = [&](const double* x, int node, int r) -> double {
+        return node < V.N ? x[((int64_t)f * V.N + node) * V.R + r] : 0.0;
+    };
+    double acc[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) acc[e] = 0.0;
+    double pre;
+    if (kind == 0) {
+        const int v0 = P[1], v1 = P[2];
+        double cq = 0.0;   // sum_r (w1 - w0)(u1 - u0): the local matrix is sigma sigma^T
+        for (int r = 0; r < V.R; ++r)
+            cq += (val_of(V.w, v1, r) - val_of(V.w, v0, r)) * (val_of(V.u, v1, r) - val_of(V.u, v0, r));
+        const double J = A.X[v1] - A.X[v0];
+        const double aJ = fabs(J);
+        const double inv = 1.0 / (2.0 - 2.0 * sb);
+        for (int idx = lane; idx < nq * nq; idx += 64) {
+            const int i0 = idx / nq, i1 = idx % nq;
+            const double z = A.g[i0], u = A.g[i1];
+            const double wt = A.w[i0] * A.w[i1];
+            const double t = exp(inv * log(z));
+            const double yh = (1.0 - t) * u;
+            const double xh = yh + t;
+            const double sx = (1.0 - xh) * s[v0] + xh * s[v1];
+            const double sy = (1.0 - yh) * s[v0] + yh * s[v1];
+            const double kx = (1.0 - xh) * kp[v0] + xh * kp[v1];
+            const double ky = (1.0 - yh) * kp[v0] + yh * kp[v1];
+            const double ss = sx + sy;
+            const double val = cq * wt * A.a_scale * sqrt(kx * ky) * exp((1.0 - ss) * log(aJ)) *
+                               exp((2.0 * sb - ss) * inv * log(z)) * (1.0 - t);
+            const double vs = -(inv * log(z) + log(aJ)) * val;   // |x - y| = t |J|
+            acc[0] += vs * (1.0 - xh); acc[1] += vs * xh;
+            acc[3] += vs * (1.0 - yh); acc[4] += vs * yh;
+            acc[6] += 0.5 * val / kx * (1.0 - xh); acc[7] += 0.5 * val / kx * xh;
+            acc[9] += 0.5 * val / ky * (1.0 - yh); acc[10] += 0.5 * val / ky * yh;
+        }
+        pre = 2.0 * inv;
+    } else {
+        // vertex pair: cell0 = (P, A), cell1 = (P, B); local dofs (P, A, B)
+        const int vp = P[1], va = P[2], vb = P[5];
+        double C[3][3];
+        const int loc[3] = {vp, va, vb};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double v = 0.0;
+                for (int r = 0; r < V.R; ++r) v += val_of(V.w, loc[a], r) * val_of(V.u, loc[b], r);
+                C[a][b] = v;
+            }
+        const double h1 = fabs(A.X[va] - A.X[vp]);
+        const double h2 = fabs(A.X[vb] - A.X[vp]);
+        const double inv = 1.0 / (3.0 - 2.0 * sb);
+        for (int idx = lane; idx < 2 * nq * nq; idx += 64) {
+            const int r = idx / (nq * nq);
+            const int q = idx % (nq * nq);
+            const int i0 = q / nq, i1 = q % nq;
+            const double z = A.g[i0], u = A.g[i1];
+            const double wt = A.w[i0] * A.w[i1];
+            const double xi = exp(inv * log(z));
+            const double at = r == 0 ? 1.0 : u;
+            const double bt = r == 0 ? u : 1.0;
+            const double al = xi * at, be = xi * bt;
+            const double sx = (1.0 - al) * s[vp] + al * s[va];
+            const double sy = (1.0 - be) * s[vp] + be * s[vb];
+            const double kx = (1.0 - al) * kp[vp] + al * kp[va];
+            const double ky = (1.0 - be) * kp[vp] + be * kp[vb];
+            const double D = h1 * at + h2 * bt;
+            const double phi[3] = {bt - at, at, -bt};
+            double qf = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) qf += phi[a] * C[a][b] * phi[b];
+            const double val = qf * wt * A.a_scale * sqrt(kx * ky) * exp((2.0 * sb - (sx + sy)) * inv * log(z)) *
+                               exp(-(1.0 + sx + sy) * log(D));
+            const double vs = -(inv * log(z) + log(D)) * val;   // |x - y| = xi D
+            acc[0] += vs * (1.0 - al); acc[1] += vs * al;
+            acc[3] += vs * (1.0 - be); acc[4] += vs * be;
+            acc[6] += 0.5 * val / kx * (1.0 - al); acc[7] += 0.5 * val / kx * al;
+            acc[9] += 0.5 * val / ky * (1.0 - be); acc[10] += 0.5 * val / ky * be;
+        }
+        pre = 2.0 * h1 * h2 * inv;
+    }
+    double* o = A.out + ((int64_t)f * A.np + pid) * 12;
+    for (int e = 0; e < 12; ++e) {
+        const double v = wave_sum(acc[e]);
+        if (lane == 0) o[e] = v * pre;
+    }
+}
+
+hipError_t launch_adj_singular(int dim, int64_t np, const int32_t* pairs, const double* coords, int64_t n_nodes,
+                               int F, const double* s, const double* kappa, double a_scale, double s_bar, int nq,
+                               const double* g01, const double* w01, const double* w, const double* u, int64_t N,
+                               int R, double* out, hipStream_t st) {
+    if (np == 0) return hipSuccess;
+    SingArgs A{np, pairs, coords, n_nodes, s, kappa, a_scale, s_bar, nq, g01, w01, out};
+    AdjVecs V{w, u, N, R};
+    for (int f = 0; f < F; ++f) {
+        if (dim == 2)
+            hipLaunchKernelGGL(k_adj_singular2d, dim3(grid1(np, 4)), dim3(256), 0, st, A, V, f);
+        else
+            hipLaunchKernelGGL(k_adj_singular1d, dim3(grid1(np, 4)), dim3(256), 0, st, A, V, f);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_singular(int dim, int64_t np, const int32_t* pairs, const double* coords,

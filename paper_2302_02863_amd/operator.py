@@ -44,7 +44,7 @@ def _stream_handle(stream):
 
 
 class Operator:
-    """fpde_build / fpde_apply / fpde_solve / fpde_load_vector / fpde_export / fpde_stats."""
+    """fpde_build / fpde_apply / fpde_solve / fpde_apply_adjoint / fpde_load_vector / fpde_export / fpde_stats."""
 
     def __init__(self, mesh, s, kappa, opts: dict | None = None, plan_only: bool = False):
         self._h = C.c_void_p()
@@ -113,6 +113,27 @@ class Operator:
         if st != _abi.FPDE_OK and (raise_on_noconv or st != _abi.FPDE_ENOCONV):
             check(st, "fpde_solve")
         return u, out
+
+    def apply_adjoint(self, w, u, stream=None):
+        """(grad_s, grad_kappa) [F, n_nodes] of sum_r w_r^T A(s, kappa) u_r for device float64 [F, N, R]."""
+        import torch
+        if w.dim() == 2:
+            w = w.unsqueeze(-1)
+        if u.dim() == 2:
+            u = u.unsqueeze(-1)
+        for v in (w, u):
+            if tuple(v.shape[:2]) != (self.n_fields, self.n_dofs) or not v.is_cuda or v.dtype != torch.float64:
+                raise ValueError(f"w, u must be float64 device tensors [F={self.n_fields}, N={self.n_dofs}, R]")
+        if w.shape != u.shape:
+            raise ValueError("w and u must have the same shape")
+        w = w.contiguous()
+        u = u.contiguous()
+        gs = torch.empty((self.n_fields, self.n_nodes), dtype=torch.float64, device=w.device)
+        gk = torch.empty_like(gs)
+        check(lib().fpde_apply_adjoint(self._h, C.c_void_p(w.data_ptr()), C.c_void_p(u.data_ptr()), w.shape[2],
+                                       C.c_void_p(gs.data_ptr()), C.c_void_p(gk.data_ptr()), _stream_handle(stream)),
+              "fpde_apply_adjoint")
+        return gs, gk
 
     # ------------------------------------------------------------------ inspection
     def export(self, what: str, field: int = 0) -> np.ndarray:

@@ -1,0 +1,86 @@
+"""GPU adjoint (fpde_apply_adjoint) against the oracle's complex-step derivatives.
+
+The library returns the full gradient of J = w^T A_h(s, kappa) u over all mesh
+nodes; the oracle differentiates its dense H2-consistent assembly by complex
+step (exact to rounding, pinned in tests/test_oracle_adjoint.py).  Directional
+derivatives along random directions are compared on cases that span several
+leaves, far blocks, an analytic exterior and the 1D rules; on a tiny mesh the
+whole gradient is compared node by node.  Tolerance 1e-10, relative to the
+absolute sum sum_j |g_j d_j| of the terms of the directional derivative.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from fpde_inputs import configs  # noqa: E402
+from oracle.adjoint import directional  # noqa: E402
+
+TOL = 1e-10
+
+CASES = {
+    "square": lambda: configs.square(12, 6, leaf_size=16, leaf_size_rho=32, cheb_p=4),
+    "interval": lambda: configs.interval(n_int=64, n_ext=16, leaf_size=8, leaf_size_rho=16, cheb_p=5),
+    "disk": lambda: configs.disk(8, leaf_size=16, leaf_size_rho=32, cheb_p=4),
+}
+
+
+def _grad(P, w, u):
+    import paper_2302_02863_amd as fp
+    op = fp.Operator(P.mesh, P.s, P.kappa, P.opts)
+    gs, gk = op.apply_adjoint(torch.tensor(w, device="cuda"), torch.tensor(u, device="cuda"))
+    torch.cuda.synchronize()
+    return gs.cpu().numpy()[0], gk.cpu().numpy()[0], op
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_directional_derivatives(name):
+    P = CASES[name]()
+    m = P.mesh
+    rng = np.random.default_rng(12)
+    w = rng.standard_normal((1, m.n_dofs, 1))
+    u = rng.standard_normal((1, m.n_dofs, 1))
+    print(f"[adjoint] {name}: N={m.n_dofs} M={m.n_nodes}", flush=True)
+    gs, gk, op = _grad(P, w, u)
+    for trial in range(3):
+        ds = rng.uniform(-1, 1, m.n_nodes)
+        dk = rng.uniform(-1, 1, m.n_nodes)
+        for dsv, dkv in ((ds, None), (None, dk)):
+            ref = directional(m, P.s[0], P.kappa[0], P.opts, w[0, :, 0], u[0, :, 0], ds=dsv, dk=dkv)
+            g, d = (gs, dsv) if dsv is not None else (gk, dkv)
+            got = float(g @ d)
+            scale = float(np.abs(g * d).sum())
+            print(f"[adjoint] {name} trial {trial} {'s' if dsv is not None else 'kappa'}: "
+                  f"{got:.15e} vs {ref:.15e}", flush=True)
+            assert abs(got - ref) <= TOL * scale, (got, ref, scale)
+    op.close()
+
+
+def test_gradient_node_by_node_and_several_rhs():
+    """Single entries of the gradient (interior, boundary and exterior nodes) with two
+    right-hand sides, each against the oracle's derivative along that node alone."""
+    P = configs.square(4, 2, leaf_size=6, leaf_size_rho=12, cheb_p=3)
+    m = P.mesh
+    rng = np.random.default_rng(13)
+    R = 2
+    w = rng.standard_normal((1, m.n_dofs, R))
+    u = rng.standard_normal((1, m.n_dofs, R))
+    gs, gk, op = _grad(P, w, u)
+    nodes = np.concatenate([rng.choice(m.n_dofs, 5, replace=False),
+                            rng.choice(np.arange(m.n_dofs, m.n_nodes), 5, replace=False)])
+    scale_s, scale_k = np.abs(gs).max(), np.abs(gk).max()
+    for j in nodes:
+        e = np.zeros(m.n_nodes)
+        e[j] = 1.0
+        rs = directional(m, P.s[0], P.kappa[0], P.opts, w[0], u[0], ds=e)
+        rk = directional(m, P.s[0], P.kappa[0], P.opts, w[0], u[0], dk=e)
+        print(f"[adjoint] node {j}: ds {gs[j]:.15e} vs {rs:.15e}; dkappa {gk[j]:.15e} vs {rk:.15e}", flush=True)
+        assert abs(gs[j] - rs) <= TOL * scale_s, (j, gs[j], rs)
+        assert abs(gk[j] - rk) <= TOL * scale_k, (j, gk[j], rk)
+    # bitwise reproducible
+    gs2, gk2 = op.apply_adjoint(torch.tensor(w, device="cuda"), torch.tensor(u, device="cuda"))
+    torch.cuda.synchronize()
+    assert np.array_equal(gs2.cpu().numpy()[0], gs) and np.array_equal(gk2.cpu().numpy()[0], gk)
+    op.close()
