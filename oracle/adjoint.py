@@ -19,6 +19,9 @@ is therefore exact to rounding (no difference of nearby values is taken).
 * ``directional``  the complex-step directional derivative above.
 * ``gradient``     the full gradient over all nodes, one complex assembly per
                    node and field (small meshes only).
+* ``objective_directional``  derivative of J(s) = 1/2 ||u(s) - u_obs||^2 with
+                   u(s) = A_h(s, kappa)^{-1} F, by the same complex step through a
+                   dense LU solve (the complex-symmetric A_h is not Hermitian).
 
 Pinned by tests/test_oracle_adjoint.py: central finite differences of the real
 assembly, the exact scaling laws A_h(2T) = 2^{d-2s} A_h(T) (constant s,
@@ -48,6 +51,18 @@ def directional(mesh, s, kappa, opts, w, u, ds=None, dk=None, h=STEP):
     sc = s + 1j * h * (np.zeros_like(s) if ds is None else np.asarray(ds, dtype=np.float64))
     kc = kappa + 1j * h * (np.zeros_like(kappa) if dk is None else np.asarray(dk, dtype=np.float64))
     return float(np.imag(bilinear(mesh, sc, kc, opts, w, u)) / h)
+
+
+def objective_directional(mesh, s, kappa, opts, F, u_obs, ds=None, dk=None, h=STEP):
+    s = np.asarray(s, dtype=np.float64).reshape(-1)
+    kappa = np.asarray(kappa, dtype=np.float64).reshape(-1)
+    sc = s + 1j * h * (np.zeros_like(s) if ds is None else np.asarray(ds, dtype=np.float64))
+    kc = kappa + 1j * h * (np.zeros_like(kappa) if dk is None else np.asarray(dk, dtype=np.float64))
+    ref = assemble_h2(mesh, sc, kc, opts)
+    A = ref["B"] + ref["K"] + ref["M"]
+    u = np.linalg.solve(A, np.asarray(F, dtype=np.complex128))
+    J = 0.5 * np.sum((u - u_obs) ** 2)
+    return float(np.imag(J) / h)
 
 
 def gradient(mesh, s, kappa, opts, w, u):

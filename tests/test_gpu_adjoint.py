@@ -84,3 +84,33 @@ def test_gradient_node_by_node_and_several_rhs():
     torch.cuda.synchronize()
     assert np.array_equal(gs2.cpu().numpy()[0], gs) and np.array_equal(gk2.cpu().numpy()[0], gk)
     op.close()
+
+
+def test_autograd_solve_gradient():
+    """J(s, kappa) = 1/2 ||u - u_obs||^2 with u = A_h^{-1} F through FracSolve: the
+    autograd gradient (adjoint CG + fpde_apply_adjoint) against the oracle's complex
+    step through a dense solve, along random directions."""
+    from paper_2302_02863_amd.autograd import frac_solve
+    from oracle.adjoint import objective_directional
+    from oracle.assembly import load_vector
+    P = configs.square(8, 4, leaf_size=12, leaf_size_rho=24, cheb_p=3)
+    m = P.mesh
+    F = load_vector(m, P.f, P.opts)
+    rng = np.random.default_rng(17)
+    u_obs = 0.3 * rng.standard_normal(m.n_dofs)
+    s = torch.tensor(P.s, requires_grad=True)
+    k = torch.tensor(P.kappa, requires_grad=True)
+    Fd = torch.tensor(F, device="cuda").reshape(1, -1, 1)
+    u = frac_solve(s, k, Fd, m, P.opts, 1e-13)
+    J = 0.5 * ((u[0, :, 0] - torch.tensor(u_obs, device="cuda")) ** 2).sum()
+    J.backward()
+    gs = s.grad.numpy()[0]
+    gk = k.grad.numpy()[0]
+    for trial in range(2):
+        d = rng.uniform(-1, 1, m.n_nodes)
+        for which, g in (("s", gs), ("kappa", gk)):
+            kw = {"ds": d} if which == "s" else {"dk": d}
+            ref = objective_directional(m, P.s[0], P.kappa[0], P.opts, F, u_obs, **kw)
+            got = float(g @ d)
+            print(f"[autograd] {which} trial {trial}: {got:.15e} vs {ref:.15e}", flush=True)
+            assert abs(got - ref) <= 1e-8 * float(np.abs(g * d).sum()), (which, got, ref)

@@ -83,3 +83,26 @@ def test_kappa_homogeneity_and_symmetry():
     d_wu = directional(P.mesh, s, k, P.opts, w, u, ds=ds)
     d_uw = directional(P.mesh, s, k, P.opts, u, w, ds=ds)
     assert abs(d_wu - d_uw) <= 1e-12 * abs(d_wu)
+
+
+def test_objective_through_the_solve():
+    """d/dt J(s + t ds) with J = 1/2 ||A_h^{-1} F - u_obs||^2: complex step through the
+    dense solve against central differences."""
+    from oracle.adjoint import objective_directional
+    from oracle.assembly import load_vector
+    from oracle.h2 import assemble_h2
+    from oracle.solve import solve_dense
+    P = configs.square(4, 2, leaf_size=8, leaf_size_rho=16, cheb_p=3)
+    m = P.mesh
+    F = load_vector(m, P.f, P.opts)
+    u_obs = 0.5 * solve_dense(*(lambda r: (r["B"] + r["K"] + r["M"], F))(assemble_h2(m, P.s[0], P.kappa[0], P.opts)))
+    ds = np.random.default_rng(7).uniform(-1, 1, m.n_nodes) * 0.05
+
+    def J(s):
+        r = assemble_h2(m, s, P.kappa[0], P.opts)
+        u = solve_dense(r["B"] + r["K"] + r["M"], F)
+        return 0.5 * np.sum((u - u_obs) ** 2)
+    cs = objective_directional(m, P.s[0], P.kappa[0], P.opts, F, u_obs, ds=ds)
+    eps = 1e-5
+    fd = (J(P.s[0] + eps * ds) - J(P.s[0] - eps * ds)) / (2 * eps)
+    assert abs(cs - fd) <= 1e-7 * abs(cs), (cs, fd)
