@@ -142,7 +142,7 @@ struct fpde_op {
     int64_t* d_leaf_beg = nullptr;
     int64_t* d_near_ptr = nullptr;
     int64_t* d_near_src = nullptr;
-    double* d_near = nullptr;
+    double* d_near = nullptr;       // near leaf blocks [F][pairs][cap][cap] (build only; repacked as panels)
     double* d_U = nullptr;
     double* d_St = nullptr;         // [F][nfar][k][k] coupling matrices (transposed)
     int64_t cap = 0;
@@ -839,6 +839,8 @@ void build_device(fpde_op& op) {
                                      op.d_poff, op.d_pstride, op.d_pcols_ptr, op.d_near, F, op.d_panel, st), "pack");
             hipck(hipStreamSynchronize(st), "pack sync");
             A.release(d_pcol_off);
+            A.release(op.d_near);   // every apply reads the panels
+            op.d_near = nullptr;
         }
         for (void* q : {(void*)np.tgt, (void*)np.src, (void*)np.row_ptr, (void*)np.row_lcell, (void*)np.row_slot})
             A.release(q);
@@ -1003,8 +1005,7 @@ ApplyPlan make_apply_plan(const fpde_op& op, const H2Tree& h) {
 hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void* y, int64_t R, hipStream_t s0,
                          hipStream_t s1, hipEvent_t fk, hipEvent_t jn, hipEvent_t* ev) {
     const int F = op.F, p = op.opts.cheb_p;
-    const Tree& kt = op.kt;
-    H2Tree h = make_h2(kt, op.kdev, p);
+    const H2Tree h = make_h2(op.kt, op.kdev, p);
     const ApplyPlan a = make_apply_plan(op, h);
     const double* cv = nullptr;
     if ((parts & FPDE_PART_B) && (parts & FPDE_PART_M)) cv = op.d_BM;
@@ -1014,8 +1015,8 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
     const bool f32 = op.mixed && !(parts & FPDE_PART_FP64);
     const int pr = f32 ? 1 : 0;
     const size_t esz = f32 ? sizeof(float) : sizeof(double);
+    const PanelPlan pp{op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr, op.panel_max_stride, op.d_csr_col_dof};
     if (R == 1 && op.up[pr].ok && op.panel_max_stride * (int64_t)esz <= 64 * 1024) {
-        PanelPlan pp{op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr, op.panel_max_stride, op.d_csr_col_dof};
         if (f32) {
             OpData<float> od{op.f32.U, op.f32.E, op.f32.St, op.f32.panel, op.f32.xh, op.f32.tmp};
             return launch_apply_single(a, h, pp, op.up[1], parts, F, cv, nfar, od, dtype, x, y, op.d_tickets, s0, s1,
@@ -1025,22 +1026,14 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
         return launch_apply_single(a, h, pp, op.up[0], parts, F, cv, nfar, od, dtype, x, y, op.d_tickets, s0, s1, fk,
                                    jn, ev);
     }
-    // several right-hand sides (FP64 data): LDS-resident subtrees and top tree
+    // several right-hand sides: near panels as MFMA GEMMs (FP32 data for a mixed
+    // operator), far field in FP64 with LDS-resident subtrees, or per-level sweeps
+    const void* panel = f32 ? (const void*)op.f32.panel : (const void*)op.d_panel;
     if (multi_fits(h, op.ls2, (int)R))
-        return launch_apply_multi(a, h, op.ls2, op.d_csr_col_dof, parts, F, (int)R, cv, op.d_St, nfar, dtype, x,
+        return launch_apply_multi(a, h, op.ls2, pp, panel, f32 ? 1 : 0, parts, F, (int)R, cv, op.d_St, nfar, dtype, x,
                                   op.d_xh, op.d_tmp, y, s0, s1, fk, jn, ev);
-    // wide R: per-level sweeps, one stream
-    hipError_t e = launch_gather(a, F, (int)R, dtype, x, op.d_xt, s0);
-    if (e != hipSuccess) return e;
-    if (parts & FPDE_PART_KFAR) {
-        if ((e = launch_leaf_up(a, h, F, (int)R, op.d_xt, op.d_xh, s0)) != hipSuccess) return e;
-        for (int lev = kt.L - 1; lev >= 0; --lev)
-            if ((e = launch_up_level(h, lev, F, (int)R, op.d_xh, s0)) != hipSuccess) return e;
-        if ((e = launch_coupling_apply(h, F, (int)R, op.d_St, op.d_xh, op.d_yh, s0)) != hipSuccess) return e;
-        for (int lev = 0; lev < kt.L; ++lev)
-            if ((e = launch_down_level(h, lev, F, (int)R, op.d_yh, s0)) != hipSuccess) return e;
-    }
-    return launch_leaf_out(a, h, parts, F, (int)R, cv, op.d_xt, op.d_yh, dtype, y, s0);
+    return launch_apply_wide(a, h, pp, panel, f32 ? 1 : 0, parts, F, (int)R, cv, op.d_St, dtype, x, op.d_xt, op.d_xh,
+                             op.d_yh, y, s0, s1, fk, jn, ev);
 }
 
 void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64_t R, hipStream_t st) {

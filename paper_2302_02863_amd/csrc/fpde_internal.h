@@ -143,10 +143,10 @@ hipError_t launch_gather(const ApplyPlan& a, int F, int R, int dtype, const void
 // xh[f][leaf][alpha][r] = sum_{t in leaf} U[t][alpha] xt[f][t][r]
 hipError_t launch_leaf_up(const ApplyPlan& a, const H2Tree& t, int F, int R, const double* xt,
                           double* xh, hipStream_t st);
-// y[f][perm[t]][r] = (B+M) xt + K_near xt + U yh     (parts select terms)
+// y[f][perm[t]][r] (=, or += with accumulate) (B+M) xt + K_near xt + U yh   (parts select terms)
 hipError_t launch_leaf_out(const ApplyPlan& a, const H2Tree& t, int parts, int F, int R,
                            const double* csr_val_override, const double* xt, const double* yh,
-                           int dtype, void* y, hipStream_t st);
+                           int dtype, void* y, hipStream_t st, int accumulate = 0);
 
 hipError_t launch_coupling_store(const H2Tree& t, int64_t nfar, const int64_t* far_tgt, int F, double fac,
                                  double a_scale, double* St, hipStream_t st);
@@ -163,10 +163,15 @@ bool multi_fits(const H2Tree& t, int ls, int R);
 // coupling products; join; per-leaf downsweep fused with the output (FP64).
 // ev (optional, 5 events, side == st): start, far chain end, near kernel
 // start/stop, end.
-hipError_t launch_apply_multi(const ApplyPlan& a, const H2Tree& t, int ls, const int32_t* csr_col_dof, int parts,
-                              int F, int R, const double* csr_val, const double* St, int64_t nfar, int dtype,
-                              const void* x, double* xh, double* tmp, void* y, hipStream_t st, hipStream_t side,
-                              hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+struct PanelPlan;
+hipError_t launch_apply_multi(const ApplyPlan& a, const H2Tree& t, int ls, const PanelPlan& pp, const void* panel,
+                              int panel_f32, int parts, int F, int R, const double* csr_val, const double* St,
+                              int64_t nfar, int dtype, const void* x, double* xh, double* tmp, void* y,
+                              hipStream_t st, hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+hipError_t launch_apply_wide(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const void* panel, int panel_f32,
+                             int parts, int F, int R, const double* csr_val, const double* St, int dtype,
+                             const void* x, double* xt, double* xh, double* yh, void* y, hipStream_t st,
+                             hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
 
 // ---------------------------------------------------------------- apply, one right-hand side (fpde_apply.hip)
 
@@ -206,6 +211,13 @@ hipError_t launch_near_panel(const ApplyPlan& a, const PanelPlan& pp, const doub
 hipError_t launch_near_panel(const ApplyPlan& a, const PanelPlan& pp, const float* panel, int use_near,
                              const double* csr_val, int F, int dtype, const void* x, void* y, hipStream_t st,
                              hipEvent_t e0, hipEvent_t e1);
+// several right-hand sides: Y = Panel X (MFMA) + (B+M) X per (leaf, 64 rows, 64 rhs, field); x, y [F][N][R]
+hipError_t launch_near_mm(const ApplyPlan& a, const PanelPlan& pp, const double* panel, int use_near,
+                          const double* csr_val, int F, int R, int dtype, const void* x, void* y, hipStream_t st,
+                          hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_near_mm(const ApplyPlan& a, const PanelPlan& pp, const float* panel, int use_near,
+                          const double* csr_val, int F, int R, int dtype, const void* x, void* y, hipStream_t st,
+                          hipEvent_t e0, hipEvent_t e1);
 // tickets: [F][ncl] zero-initialised counters (left at zero by every launch).
 // ev (optional, 5 events, side == st): start, far chain end, near kernel start/stop, end.
 hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up, int parts,

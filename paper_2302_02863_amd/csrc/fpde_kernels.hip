@@ -1131,7 +1131,7 @@ hipError_t launch_leaf_up(const ApplyPlan& a, const H2Tree& t, int F, int R, con
 // Output per tree row: one 16-lane group per (row, rhs); lanes split the columns
 // of the near blocks (row-major [cap][cap]) and the CSR row, then reduce.
 FPDE_KERNEL void k_leaf_out(ApplyPlan a, H2Tree t, int parts, int F, int R, const double* csr_val,
-                            const double* xt, const double* yh, int dtype, void* y) {
+                            const double* xt, const double* yh, int dtype, void* y, int accumulate) {
     const int g = threadIdx.x & 15;
     const int64_t item = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
     if (item >= (int64_t)F * a.N * R) return;
@@ -1170,17 +1170,17 @@ FPDE_KERNEL void k_leaf_out(ApplyPlan a, H2Tree t, int parts, int F, int R, cons
     for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
     if (g == 0) {
         const int64_t dst = ((int64_t)f * a.N + a.perm[row]) * R + r;
-        if (dtype == 0) ((double*)y)[dst] = acc;
-        else ((float*)y)[dst] = (float)acc;
+        if (dtype == 0) ((double*)y)[dst] = accumulate ? ((double*)y)[dst] + acc : acc;
+        else ((float*)y)[dst] = (float)(accumulate ? (double)((float*)y)[dst] + acc : acc);
     }
 }
 
 hipError_t launch_leaf_out(const ApplyPlan& a, const H2Tree& t, int parts, int F, int R,
                            const double* csr_val_override, const double* xt, const double* yh,
-                           int dtype, void* y, hipStream_t st) {
+                           int dtype, void* y, hipStream_t st, int accumulate) {
     const int64_t items = (int64_t)F * a.N * R;
     hipLaunchKernelGGL(k_leaf_out, dim3(grid1(items, 16)), dim3(256), 0, st, a, t, parts, F, R,
-                       csr_val_override, xt, yh, dtype, y);
+                       csr_val_override, xt, yh, dtype, y, accumulate);
     return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
-// Operator apply for several right-hand sides per field (R > 1) in FP64:
-// main stream: CSR rows of B + M and the near leaf blocks read in place
-// (k_near_out_m); side stream: subtree upsweep, top levels, coupling products
-// per far pair; join: per-leaf downsweep walk fused with the output.
+// Operator apply for several right-hand sides per field (R > 1): main stream:
+// near panels as MFMA GEMMs with the CSR rows of B + M (k_near_mm, fpde_near.hip,
+// FP64 or FP32 operator data); side stream: the far field in FP64 (subtree
+// upsweep, top levels, coupling products per far pair, or per-level sweeps
+// when R is too wide for LDS); join: the far output added per leaf.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -57,90 +58,6 @@ FPDE_KERNEL void k_coupling_pairs_m(H2Tree t, int64_t nfar, int F, int R, const 
 #pragma unroll
     for (int b = 0; b < K; ++b) acc += S[b * K] * xs[(int64_t)b * R];
     tmp[i] = acc;
-}
-
-// Near field + CSR reading the caller's x: CSR columns are dof indices (csr_col_dof),
-// near-block columns map through perm.  One 16-lane group per row, 16 rows per block.
-FPDE_KERNEL void k_near_out_m(ApplyPlan a, const int32_t* csr_col_dof, int parts, int F, int R,
-                               const double* csr_val, int dtype, const void* x, void* y) {
-    const int f = blockIdx.y;
-    const int64_t nrb = (a.cap + 15) / 16;
-    const int64_t li = blockIdx.x / nrb;
-    const int rb = (int)(blockIdx.x % nrb);
-    const int g = threadIdx.x & 15;
-    const int64_t it = (int64_t)rb * 16 + (threadIdx.x >> 4);
-    const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
-    if (it >= nt) return;
-    const int64_t row = lb + it;
-    const int64_t xo = (int64_t)f * a.N * R;
-    const int64_t cap = a.cap;
-    const int64_t e0 = a.near_ptr[li], e1 = a.near_ptr[li + 1];
-    const int64_t c0 = 4 * g;
-    for (int r = 0; r < R; ++r) {
-        double acc = 0.0;
-        if (csr_val) {
-            const double* v = csr_val + (int64_t)f * a.nnz;
-            for (int64_t e = a.csr_ptr[row] + g; e < a.csr_ptr[row + 1]; e += 16)
-                acc += v[e] * ldx(x, xo + (int64_t)csr_col_dof[e] * R + r, dtype);
-        }
-        if (parts & 4) {
-            if ((cap & 3) == 0) {
-                int64_t e = e0;
-                for (; e + 4 <= e1; e += 4) {
-                    double2 b0[4], b1[4];
-                    int64_t sb[4], ns[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int64_t ls_ = a.near_src[e + u];
-                        sb[u] = a.leaf_beg[ls_];
-                        ns[u] = a.leaf_beg[ls_ + 1] - sb[u];
-                        const double* blk = a.near_blk + (((int64_t)f * a.npairs + e + u) * cap + it) * cap + c0;
-                        if (c0 < ns[u]) {
-                            b0[u] = *(const double2*)(blk);
-                            b1[u] = *(const double2*)(blk + 2);
-                        } else {
-                            b0[u] = make_double2(0.0, 0.0);
-                            b1[u] = make_double2(0.0, 0.0);
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int64_t m = ns[u] - c0;
-                        const double v4[4] = {b0[u].x, b0[u].y, b1[u].x, b1[u].y};
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            if (j < m) acc += v4[j] * ldx(x, xo + a.perm[sb[u] + c0 + j] * R + r, dtype);
-                    }
-                }
-                for (; e < e1; ++e) {
-                    const int64_t ls_ = a.near_src[e];
-                    const int64_t sb = a.leaf_beg[ls_], ns = a.leaf_beg[ls_ + 1] - sb;
-                    const double* blk = a.near_blk + (((int64_t)f * a.npairs + e) * cap + it) * cap;
-                    for (int64_t jc = c0; jc < c0 + 4 && jc < ns; ++jc)
-                        acc += blk[jc] * ldx(x, xo + a.perm[sb + jc] * R + r, dtype);
-                }
-                for (e = e0; e < e1 && cap > 64; ++e) {
-                    const int64_t ls_ = a.near_src[e];
-                    const int64_t sb = a.leaf_beg[ls_], ns = a.leaf_beg[ls_ + 1] - sb;
-                    const double* blk = a.near_blk + (((int64_t)f * a.npairs + e) * cap + it) * cap;
-                    for (int64_t jc = 64 + g; jc < ns; jc += 16) acc += blk[jc] * ldx(x, xo + a.perm[sb + jc] * R + r, dtype);
-                }
-            } else {
-                for (int64_t e = e0; e < e1; ++e) {
-                    const int64_t ls_ = a.near_src[e];
-                    const int64_t sb = a.leaf_beg[ls_], ns = a.leaf_beg[ls_ + 1] - sb;
-                    const double* blk = a.near_blk + (((int64_t)f * a.npairs + e) * cap + it) * cap;
-                    for (int64_t jc = g; jc < ns; jc += 16) acc += blk[jc] * ldx(x, xo + a.perm[sb + jc] * R + r, dtype);
-                }
-            }
-        }
-        for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-        if (g == 0) {
-            const int64_t dst = ((int64_t)f * a.N + a.perm[row]) * R + r;
-            if (dtype == 0) ((double*)y)[dst] = acc;
-            else ((float*)y)[dst] = (float)acc;
-        }
-    }
 }
 
 // LDS needed by the v2 far chain; false when the per-level path must be used
@@ -325,10 +242,13 @@ static void far_out_m_t(const ApplyPlan& a, const H2Tree& t, int F, int R, const
                        dtype, y);
 }
 
-hipError_t launch_apply_multi(const ApplyPlan& a, const H2Tree& t, int ls, const int32_t* csr_col_dof, int parts, int F,
-                           int R, const double* csr_val, const double* St, int64_t nfar, int dtype, const void* x,
-                           double* xh, double* tmp, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
-                           hipEvent_t join, hipEvent_t* ev) {
+// main stream: near panels (MFMA GEMMs) and the CSR rows of B + M; side stream:
+// subtree upsweep, top levels and coupling products; join; per-leaf downsweep
+// walk fused with the output.
+hipError_t launch_apply_multi(const ApplyPlan& a, const H2Tree& t, int ls, const PanelPlan& pp, const void* panel,
+                              int panel_f32, int parts, int F, int R, const double* csr_val, const double* St,
+                              int64_t nfar, int dtype, const void* x, double* xh, double* tmp, void* y,
+                              hipStream_t st, hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev) {
     const bool far = (parts & 8) != 0;
     if (ev) hipEventRecord(ev[0], st);
     hipStream_t fs = st;
@@ -339,19 +259,58 @@ hipError_t launch_apply_multi(const ApplyPlan& a, const H2Tree& t, int ls, const
     }
     if (far) FPDE_DISPATCH_DP(t.dim, t.p, far_m_t, a, t, ls, F, R, St, nfar, dtype, x, xh, tmp, fs);
     if (ev) hipEventRecord(ev[1], fs);
-    const int64_t nrb = (a.cap + 15) / 16;
-    if (ev)   // start/stop timestamps of exactly this kernel
-        hipExtLaunchKernelGGL(k_near_out_m, dim3((unsigned)(a.nleaf * nrb), F), dim3(256), 0, st, ev[2], ev[3], 0, a,
-                              csr_col_dof, parts, F, R, csr_val, dtype, x, y);
-    else
-        hipLaunchKernelGGL(k_near_out_m, dim3((unsigned)(a.nleaf * nrb), F), dim3(256), 0, st, a, csr_col_dof, parts,
-                           F, R, csr_val, dtype, x, y);
+    hipError_t e = panel_f32 ? launch_near_mm(a, pp, (const float*)panel, (parts & 4) != 0, csr_val, F, R, dtype, x, y,
+                                              st, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr)
+                             : launch_near_mm(a, pp, (const double*)panel, (parts & 4) != 0, csr_val, F, R, dtype, x,
+                                              y, st, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+    if (e != hipSuccess) return e;
     if (far) {
         if (fs != st) {
             hipEventRecord(join, fs);
             hipStreamWaitEvent(st, join, 0);
         }
         FPDE_DISPATCH_DP(t.dim, t.p, far_out_m_t, a, t, F, R, tmp, dtype, y, st);
+    }
+    if (ev) hipEventRecord(ev[4], st);
+    return hipGetLastError();
+}
+
+// Wide R (subtrees do not fit LDS): the far field by per-level sweeps on the side
+// stream, near panels on the main stream, then y += U y^ per leaf.
+hipError_t launch_apply_wide(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const void* panel, int panel_f32,
+                             int parts, int F, int R, const double* csr_val, const double* St, int dtype,
+                             const void* x, double* xt, double* xh, double* yh, void* y, hipStream_t st,
+                             hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev) {
+    const bool far = (parts & 8) != 0;
+    if (ev) hipEventRecord(ev[0], st);
+    hipStream_t fs = st;
+    if (far && side != st) {
+        hipEventRecord(fork, st);
+        hipStreamWaitEvent(side, fork, 0);
+        fs = side;
+    }
+    hipError_t e = hipSuccess;
+    if (far) {
+        if ((e = launch_gather(a, F, R, dtype, x, xt, fs)) != hipSuccess) return e;
+        if ((e = launch_leaf_up(a, t, F, R, xt, xh, fs)) != hipSuccess) return e;
+        for (int lev = t.L - 1; lev >= 0; --lev)
+            if ((e = launch_up_level(t, lev, F, R, xh, fs)) != hipSuccess) return e;
+        if ((e = launch_coupling_apply(t, F, R, St, xh, yh, fs)) != hipSuccess) return e;
+        for (int lev = 0; lev < t.L; ++lev)
+            if ((e = launch_down_level(t, lev, F, R, yh, fs)) != hipSuccess) return e;
+    }
+    if (ev) hipEventRecord(ev[1], fs);
+    e = panel_f32 ? launch_near_mm(a, pp, (const float*)panel, (parts & 4) != 0, csr_val, F, R, dtype, x, y, st,
+                                   ev ? ev[2] : nullptr, ev ? ev[3] : nullptr)
+                  : launch_near_mm(a, pp, (const double*)panel, (parts & 4) != 0, csr_val, F, R, dtype, x, y, st,
+                                   ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+    if (e != hipSuccess) return e;
+    if (far) {
+        if (fs != st) {
+            hipEventRecord(join, fs);
+            hipStreamWaitEvent(st, join, 0);
+        }
+        if ((e = launch_leaf_out(a, t, 8, F, R, nullptr, xt, yh, dtype, y, st, 1)) != hipSuccess) return e;
     }
     if (ev) hipEventRecord(ev[4], st);
     return hipGetLastError();

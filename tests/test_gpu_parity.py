@@ -228,3 +228,27 @@ def test_load_vector():
     torch.cuda.synchronize()
     Fr = load_vector(P.mesh, f, P.opts)
     assert _rel(F.cpu().numpy(), Fr) < 1e-13
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_fields_and_rhs(precision):
+    """Several order fields x 64 right-hand sides (the batched workload's shape at a
+    small mesh): near panels as MFMA GEMMs, FP64 (1e-10) and FP32 operator data (1e-6)."""
+    import paper_2302_02863_amd as fp
+    P = configs.batched(16, n_fields=3, nrhs=64, leaf_size=16, leaf_size_rho=32, cheb_p=4)
+    m = P.mesh
+    o = dict(P.opts)
+    o["precision"] = precision
+    op = fp.Operator(m, P.s, P.kappa, o)
+    tol = TOL if precision == "fp64" else MIXED_TOL
+    for dt in (torch.float64, torch.float32):
+        x = torch.tensor(P.x, device="cuda", dtype=dt)
+        y = op.apply(x).double().cpu().numpy()
+        for f in range(P.s.shape[0]):
+            ref = assemble_h2(m, P.s[f], P.kappa[f], P.opts)
+            A = ref["B"] + ref["K"] + ref["M"]
+            yr = A @ x[f].double().cpu().numpy()
+            err = np.linalg.norm(y[f] - yr, axis=0) / np.linalg.norm(yr, axis=0)
+            lim = tol if dt == torch.float64 else max(tol, 1e-6)
+            assert err.max() < lim, (precision, dt, f, err.max())
+    op.close()
