@@ -29,6 +29,7 @@ SOURCES = [
     ("fpde_near.hip", HIP_FLAGS),
     ("fpde_apply.hip", HIP_FLAGS),
     ("fpde_multi.hip", HIP_FLAGS),
+    ("fpde_batched.hip", HIP_FLAGS),
     ("fpde_solve.hip", HIP_FLAGS),
     ("fpde_adjoint.hip", HIP_FLAGS),
     ("fpde_host.cpp", HOST_FLAGS),

@@ -157,7 +157,8 @@ struct fpde_op {
     UpPlan up[2]{};                        // one-launch upsweep plan per precision (0 FP64, 1 FP32)
     struct {                               // FP32 operator data of a mixed-precision operator
         float *U = nullptr, *E = nullptr, *St = nullptr, *panel = nullptr;
-        float *xh = nullptr, *tmp = nullptr;   // workspace
+        float *xh = nullptr, *tmp = nullptr;   // workspace, one right-hand side
+        float *xhR = nullptr, *yhR = nullptr;  // workspace [F][ncl][K][R]
     } f32;
     // captured apply graphs keyed by (parts, dtype, x, y, R)
     std::map<std::tuple<int, int, const void*, void*, int64_t>, hipGraphExec_t> graphs;
@@ -971,9 +972,17 @@ void ensure_ws(fpde_op& op, int64_t R) {
     op.d_xt = op.arena.alloc<double>((int64_t)op.F * (op.mesh.N + op.cap) * R);
     op.d_xh = op.arena.alloc<double>((int64_t)op.F * op.kt.ncl * k * R);
     op.d_yh = op.arena.alloc<double>((int64_t)op.F * op.kt.ncl * k * R);
-    if (op.mixed && !op.f32.xh) {   // single-vector FP32 workspace
-        op.f32.xh = op.arena.alloc<float>((int64_t)op.F * op.kt.ncl * k);
-        op.f32.tmp = op.arena.alloc<float>((int64_t)op.F * std::max<size_t>(1, op.kfar.size()) * k);
+    if (op.mixed) {   // FP32 workspace
+        if (!op.f32.xh) {
+            op.f32.xh = op.arena.alloc<float>((int64_t)op.F * op.kt.ncl * k);
+            op.f32.tmp = op.arena.alloc<float>((int64_t)op.F * std::max<size_t>(1, op.kfar.size()) * k);
+        }
+        if (op.f32.xhR) {
+            op.arena.release(op.f32.xhR);
+            op.arena.release(op.f32.yhR);
+        }
+        op.f32.xhR = op.arena.alloc<float>((int64_t)op.F * op.kt.ncl * k * R);
+        op.f32.yhR = op.arena.alloc<float>((int64_t)op.F * op.kt.ncl * k * R);
     }
     op.ws_R = R;
 }
@@ -1026,8 +1035,19 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
         return launch_apply_single(a, h, pp, op.up[0], parts, F, cv, nfar, od, dtype, x, y, op.d_tickets, s0, s1, fk,
                                    jn, ev);
     }
-    // several right-hand sides: near panels as MFMA GEMMs (FP32 data for a mixed
-    // operator), far field in FP64 with LDS-resident subtrees, or per-level sweeps
+    // several right-hand sides: near panels as MFMA GEMMs and the far field as
+    // batched products in the operator's precision (FP32 data for a mixed operator)
+    if (batched_fits(h, op.cap, pr)) {
+        if (f32) {
+            OpData<float> od{op.f32.U, op.f32.E, op.f32.St, op.f32.panel, nullptr, nullptr};
+            return launch_apply_batched(a, h, pp, parts, F, (int)R, cv, od, op.f32.xhR, op.f32.yhR, dtype, x, y, s0,
+                                        s1, fk, jn, ev);
+        }
+        OpData<double> od{op.d_U, op.kdev.E, op.d_St, op.d_panel, nullptr, nullptr};
+        return launch_apply_batched(a, h, pp, parts, F, (int)R, cv, od, op.d_xh, op.d_yh, dtype, x, y, s0, s1, fk, jn,
+                                    ev);
+    }
+    // otherwise (K > 32): FP64 far field with LDS-resident subtrees, or per-level sweeps
     const void* panel = f32 ? (const void*)op.f32.panel : (const void*)op.d_panel;
     if (multi_fits(h, op.ls2, (int)R))
         return launch_apply_multi(a, h, op.ls2, pp, panel, f32 ? 1 : 0, parts, F, (int)R, cv, op.d_St, nfar, dtype, x,

@@ -229,6 +229,22 @@ hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelP
                                const void* x, void* y, unsigned int* tickets, hipStream_t st, hipStream_t side,
                                hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
 
+// ---------------------------------------------------------------- apply, many right-hand sides (fpde_batched.hip)
+
+// K <= 32 and the leaf stages fit LDS (prec 0 double, 1 float)
+bool batched_fits(const H2Tree& t, int64_t cap, int prec);
+// near panels (MFMA) + CSR on st; far field in the operator precision on side:
+// leaf upsweep, level transfers, MFMA coupling per target cluster, downsweep;
+// join; y += U Y^ per leaf.  xh, yh: [F][ncl][K][R] workspaces of that precision.
+hipError_t launch_apply_batched(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, int parts, int F, int R,
+                                const double* csr_val, const OpData<double>& od, double* xh, double* yh, int dtype,
+                                const void* x, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
+                                hipEvent_t join, hipEvent_t* ev);
+hipError_t launch_apply_batched(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, int parts, int F, int R,
+                                const double* csr_val, const OpData<float>& od, float* xh, float* yh, int dtype,
+                                const void* x, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
+                                hipEvent_t join, hipEvent_t* ev);
+
 // ---------------------------------------------------------------- adjoint (fpde_adjoint.hip, singular pairs in
 // fpde_kernels.hip): d/ds_j and d/dkappa_j of sum_r w_r^T A_h u_r
 
