@@ -2,9 +2,9 @@
 // with the operator data in FP64 or FP32.  Coefficients are [F][cluster][K][R]
 // (right-hand sides fastest).  Each stage is a batch of small dense products:
 //   k_bup_leaf     X^_leaf = U_leaf^T X_leaf            (per leaf, 64 rhs)
-//   k_bup_level    X^_parent = sum_c E_c^T X^_c          (per level)
+//   k_blevel       X^_parent = sum_c E_c^T X^_c          (per level)
 //   k_bcoupling    Y^_S = sum_{S' far S} S_(S,S') X^_S'  (MFMA, per target cluster)
-//   k_bdown_level  Y^_c += E_c Y^_parent                 (per level)
+//   k_blevel       Y^_c += E_c Y^_parent                 (per level)
 //   k_bout_leaf    y_leaf += U_leaf Y^_leaf              (per leaf, added to y)
 // The coupling products, 2 K^2 R flops per far pair and field, are the bulk
 // of the work: FP32 operator data uses v_mfma_f32_32x32x2f32, FP64 uses
@@ -23,65 +23,141 @@ typedef double bf64x4 __attribute__((ext_vector_type(4)));
 constexpr int kRC = 64;   // right-hand sides per block
 }  // namespace
 
-// X^_leaf[alpha][r] = sum_j U[j][alpha] x[perm[j]][r]; one block per (leaf, rhs chunk, field)
+// X^_leaf[alpha][r] = sum_j U[j][alpha] x[perm[j]][r]: a (K <= 32) x 64 x n GEMM per
+// (leaf, rhs chunk, field) on MFMA, two waves of 32 right-hand sides, leaf rows
+// staged in LDS 64 at a time (alpha and the row count padded with zeros).
 template <typename T>
-__global__ __launch_bounds__(256) void k_bup_leaf(ApplyPlan a, H2Tree t, int F, int R, const T* U, int dtype,
+__global__ __launch_bounds__(128) void k_bup_leaf(ApplyPlan a, H2Tree t, int F, int R, const T* U, int dtype,
                                                   const void* x, T* xh) {
-    extern __shared__ __align__(16) unsigned char sraw[];
+    constexpr int JC = 64, US = 33, XS = kRC + 1;
+    __shared__ T sU[JC * US];    // [row][alpha]
+    __shared__ T sX[JC * XS];    // [row][r]
     const int K = t.k;
     const int64_t nrc = (R + kRC - 1) / kRC;
     const int64_t li = blockIdx.x / nrc;
     const int r0 = (int)(blockIdx.x % nrc) * kRC;
     const int f = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t lb = a.leaf_beg[li], n = a.leaf_beg[li + 1] - lb;
-    T* sU = (T*)sraw;          // [n][K]
-    T* sX = sU + n * K;        // [n][kRC]
-    for (int64_t i = threadIdx.x; i < n * K; i += blockDim.x) sU[i] = U[lb * K + i];
-    for (int64_t i = threadIdx.x; i < n * kRC; i += blockDim.x) {
-        const int64_t j = i / kRC;
-        const int r = r0 + (int)(i % kRC);
-        sX[i] = r < R ? (T)ldx(x, ((int64_t)f * a.N + a.perm[lb + j]) * R + r, dtype) : T(0);
+    bf32x16 c32 = {0};
+    bf64x4 c64[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+    for (int64_t j0 = 0; j0 < n; j0 += JC) {
+        __syncthreads();
+        for (int i = tid; i < JC * 32; i += blockDim.x) {
+            const int j = i / 32, al = i % 32;
+            sU[j * US + al] = (j0 + j < n && al < K) ? U[(lb + j0 + j) * K + al] : T(0);
+        }
+        for (int i = tid; i < JC * kRC; i += blockDim.x) {
+            const int j = i / kRC, rr = i % kRC;
+            sX[j * XS + rr] = (j0 + j < n && r0 + rr < R)
+                                  ? (T)ldx(x, ((int64_t)f * a.N + a.perm[lb + j0 + j]) * R + r0 + rr, dtype)
+                                  : T(0);
+        }
+        __syncthreads();
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll 8
+            for (int k = 0; k < JC; k += 2) {
+                const float av = sU[(k + (lane >> 5)) * US + (lane & 31)];
+                const float bv = sX[(k + (lane >> 5)) * XS + wv * 32 + (lane & 31)];
+                c32 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, c32, 0, 0, 0);
+            }
+        } else {
+#pragma unroll 4
+            for (int k = 0; k < JC; k += 4) {
+                double av[2], bv[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    av[i] = sU[(k + (lane >> 4)) * US + 16 * i + (lane & 15)];
+                    bv[i] = sX[(k + (lane >> 4)) * XS + wv * 32 + 16 * i + (lane & 15)];
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        c64[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c64[i][j], 0, 0, 0);
+            }
+        }
+    }
+    T* Xo = xh + (((int64_t)f * t.ncl + t.first_leaf + li) * K) * R;
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int al = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const int r = r0 + wv * 32 + (lane & 31);
+            if (al < K && r < R) Xo[(int64_t)al * R + r] = c32[v];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int al = 16 * i + (lane >> 4) + 4 * v;
+                    const int r = r0 + wv * 32 + 16 * j + (lane & 15);
+                    if (al < K && r < R) Xo[(int64_t)al * R + r] = c64[i][j][v];
+                }
+    }
+}
+
+// One level of the nested transfers, per (parent cluster, rhs chunk, field), with the
+// Kronecker transfer applied one dimension at a time in LDS:
+//   up:   X^_p[a0 + P a1] = sum_c sum_b1 E_c1[b1][a1] sum_b0 E_c0[b0][a0] X^_c[b0 + P b1]
+//   down: Y^_c[b0 + P b1] += sum_a1 E_c1[b1][a1] sum_a0 E_c0[b0][a0] Y^_p[a0 + P a1]
+template <int D, int P, typename T, bool UP>
+__global__ __launch_bounds__(256) void k_blevel(H2Tree t, int64_t c0, int F, int R, const T* E, T* xh) {
+    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
+    __shared__ T sE[2 * EP];
+    __shared__ T sA[2 * K * kRC];   // up: both children; down: the parent (first K * kRC)
+    __shared__ T sT[2 * K * kRC];   // after the first dimension
+    const int64_t nrc = (R + kRC - 1) / kRC;
+    const int64_t c = c0 + blockIdx.x / nrc;
+    const int r0 = (int)(blockIdx.x % nrc) * kRC;
+    const int f = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int64_t ch[2] = {2 * c + 1, 2 * c + 2};
+    T* xf = xh + (int64_t)f * t.ncl * K * R;
+    for (int i = tid; i < 2 * EP; i += blockDim.x) sE[i] = E[ch[i / EP] * EP + i % EP];
+    const int nin = UP ? 2 : 1;
+    for (int i = tid; i < nin * K * kRC; i += blockDim.x) {
+        const int s = i / (K * kRC), al = (i / kRC) % K, rr = i % kRC;
+        const int64_t src = UP ? ch[s] : c;
+        sA[i] = r0 + rr < R ? xf[(src * K + al) * R + r0 + rr] : T(0);
     }
     __syncthreads();
-    const int64_t c = t.first_leaf + li;
-    for (int i = threadIdx.x; i < K * kRC; i += blockDim.x) {
-        const int al = i / kRC, rr = i % kRC;
-        if (r0 + rr >= R) continue;
+    // first dimension (dim 0: index % P): sT[s][i0][i1][r], both children
+    for (int i = tid; i < 2 * K * kRC; i += blockDim.x) {
+        const int s = i / (K * kRC), q = (i / kRC) % K, rr = i % kRC;
+        const int i0 = q % P, i1 = q / P;
+        const T* Ed = sE + s * EP;   // dim-0 factor [b][a]
+        const T* src = sA + (UP ? s : 0) * K * kRC;
         T acc = 0;
-        for (int64_t j = 0; j < n; ++j) acc += sU[j * K + al] * sX[j * kRC + rr];
-        xh[(((int64_t)f * t.ncl + c) * K + al) * R + r0 + rr] = acc;
+#pragma unroll
+        for (int m = 0; m < P; ++m)   // up: sum_b0 E[b0][a0 = i0] X[b0 + P i1];  down: sum_a0 E[b0 = i0][a0] Y[a0 + P i1]
+            acc += (UP ? Ed[m * P + i0] : Ed[i0 * P + m]) * src[(m + P * i1) * kRC + rr];
+        sT[i] = acc;
     }
-}
-
-// one level of the upsweep: parent coefficients from both children
-template <int D, int P, typename T>
-FPDE_KERNEL void k_bup_level(H2Tree t, int64_t c0, int64_t nlev, int F, int R, const T* E, T* xh) {
-    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)F * nlev * K * R) return;
-    const int r = (int)(i % R);
-    const int al = (int)((i / R) % K);
-    const int64_t cl = (i / ((int64_t)R * K)) % nlev;
-    const int f = (int)(i / ((int64_t)R * K * nlev));
-    const int64_t c = c0 + cl, ch1 = 2 * c + 1, ch2 = 2 * c + 2;
-    const T* xf = xh + (int64_t)f * t.ncl * K * R;
-    xh[(((int64_t)f * t.ncl + c) * K + al) * R + r] =
-        up_t<D, P, T>(E + ch1 * EP, E + ch2 * EP, xf + ch1 * K * R + r, xf + ch2 * K * R + r, al, R);
-}
-
-// one level of the downsweep: children += E_c parent
-template <int D, int P, typename T>
-FPDE_KERNEL void k_bdown_level(H2Tree t, int64_t c0, int64_t nlev, int F, int R, const T* E, T* yh) {
-    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)F * nlev * K * R) return;
-    const int r = (int)(i % R);
-    const int be = (int)((i / R) % K);
-    const int64_t cl = (i / ((int64_t)R * K)) % nlev;
-    const int f = (int)(i / ((int64_t)R * K * nlev));
-    const int64_t c = c0 + cl, par = (c - 1) / 2;
-    T* yf = yh + (int64_t)f * t.ncl * K * R;
-    yf[(c * K + be) * R + r] += down_t<D, P, T>(E + c * EP, yf + par * K * R + r, be, R);
+    __syncthreads();
+    // second dimension (2D), then store
+    for (int i = tid; i < (UP ? 1 : 2) * K * kRC; i += blockDim.x) {
+        const int s = i / (K * kRC), q = (i / kRC) % K, rr = i % kRC;
+        if (r0 + rr >= R) continue;
+        const int i0 = q % P, i1 = q / P;
+        T acc = 0;
+        for (int s2 = 0; s2 < 2; ++s2) {
+            if (!UP && s2 != s) continue;
+            if (D == 1) {
+                acc += sT[(s2 * K + q) * kRC + rr];
+            } else {
+                const T* Ed = sE + s2 * EP + P * P;   // dim-1 factor [b][a]
+#pragma unroll
+                for (int m = 0; m < P; ++m)
+                    acc += (UP ? Ed[m * P + i1] : Ed[i1 * P + m]) * sT[(s2 * K + i0 + P * m) * kRC + rr];
+            }
+        }
+        if (UP) xf[(c * K + q) * R + r0 + rr] = acc;
+        else xf[(ch[s] * K + q) * R + r0 + rr] += acc;
+    }
 }
 
 // Y^_S[alpha][r] = sum_{e in far(S)} sum_beta S_e[alpha][beta] X^_src(e)[beta][r],
@@ -200,18 +276,20 @@ template <typename T>
 struct Batched {
     template <int D, int P>
     static void up(const H2Tree& t, int F, int R, const T* E, T* xh, hipStream_t st) {
+        const int64_t nrc = (R + kRC - 1) / kRC;
         for (int lev = t.L - 1; lev >= 0; --lev) {
             const int64_t c0 = (int64_t(1) << lev) - 1, n = int64_t(1) << lev;
-            hipLaunchKernelGGL((k_bup_level<D, P, T>), dim3(grid1((int64_t)F * n * t.k * R)), dim3(256), 0, st, t, c0,
-                               n, F, R, E, xh);
+            hipLaunchKernelGGL((k_blevel<D, P, T, true>), dim3((unsigned)(n * nrc), F), dim3(256), 0, st, t, c0, F, R,
+                               E, xh);
         }
     }
     template <int D, int P>
     static void down(const H2Tree& t, int F, int R, const T* E, T* yh, hipStream_t st) {
-        for (int lev = 1; lev <= t.L; ++lev) {
+        const int64_t nrc = (R + kRC - 1) / kRC;
+        for (int lev = 0; lev < t.L; ++lev) {   // parents at lev -> children at lev + 1
             const int64_t c0 = (int64_t(1) << lev) - 1, n = int64_t(1) << lev;
-            hipLaunchKernelGGL((k_bdown_level<D, P, T>), dim3(grid1((int64_t)F * n * t.k * R)), dim3(256), 0, st, t,
-                               c0, n, F, R, E, yh);
+            hipLaunchKernelGGL((k_blevel<D, P, T, false>), dim3((unsigned)(n * nrc), F), dim3(256), 0, st, t, c0, F,
+                               R, E, yh);
         }
     }
 };
@@ -220,9 +298,8 @@ template <typename T>
 hipError_t far_batched_t(const ApplyPlan& a, const H2Tree& t, int F, int R, const OpData<T>& od, int dtype,
                          const void* x, T* xh, T* yh, hipStream_t st) {
     const int64_t nrc = (R + kRC - 1) / kRC;
-    const size_t lds_up = sizeof(T) * (size_t)(a.cap * t.k + a.cap * kRC);
-    hipLaunchKernelGGL(k_bup_leaf<T>, dim3((unsigned)(a.nleaf * nrc), F), dim3(256), lds_up, st, a, t, F, R, od.U,
-                       dtype, x, xh);
+    hipLaunchKernelGGL(k_bup_leaf<T>, dim3((unsigned)(a.nleaf * nrc), F), dim3(128), 0, st, a, t, F, R, od.U, dtype, x,
+                       xh);
     FPDE_DISPATCH_DP(t.dim, t.p, Batched<T>::template up, t, F, R, od.E, xh, st);
     hipLaunchKernelGGL(k_bcoupling<T>, dim3((unsigned)(t.ncl * nrc), F), dim3(128), 0, st, t, F, R, od.St, xh, yh);
     FPDE_DISPATCH_DP(t.dim, t.p, Batched<T>::template down, t, F, R, od.E, yh, st);
@@ -271,9 +348,9 @@ hipError_t apply_batched_t(const ApplyPlan& a, const H2Tree& t, const PanelPlan&
 }  // namespace
 
 bool batched_fits(const H2Tree& t, int64_t cap, int prec) {
-    const size_t es = prec == 0 ? 8 : 4;
-    const size_t lds = es * (size_t)(cap * t.k + cap * kRC);
-    return t.k <= 32 && lds <= 64 * 1024;
+    (void)cap;
+    (void)prec;
+    return t.k <= 32;
 }
 
 hipError_t launch_apply_batched(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, int parts, int F, int R,

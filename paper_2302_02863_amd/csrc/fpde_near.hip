@@ -201,28 +201,37 @@ __global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, cons
         const int64_t ps = pp.pstride[li];
         const int64_t cb = pp.pcols_ptr[li], ncols = pp.pcols_ptr[li + 1] - cb;
         const T* pl = panel + (int64_t)f * pp.poff[a.nleaf] + pp.poff[li];
+        // this thread's share of a chunk: panel row tid/4, columns (tid%4)*8..+8;
+        // X row for column tid/8, right-hand sides (tid%8)*8..+8
+        const int pr_ = tid >> 2, pc_ = (tid & 3) * 8;
+        const int xk_ = tid >> 3, xr_ = (tid & 7) * 8;
+        const int64_t prow = row0 + pr_;
+        T pa[8], xa[8];
+        auto fetch = [&](int64_t k0) {   // global -> registers (next chunk, in flight during the MFMAs)
+            const int64_t col = k0 + pc_;
+            if (prow < a.cap && col + 8 <= ps) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) pa[j] = pl[prow * ps + col + j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) pa[j] = (prow < a.cap && col + j < ps) ? pl[prow * ps + col + j] : T(0);
+            }
+            const int64_t xc = k0 + xk_;
+            const int64_t dof = xc < ncols ? pp.pcols[cb + xc] : -1;
+            const int64_t xi = xo + dof * R + r0 + xr_;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) xa[j] = (dof >= 0 && r0 + xr_ + j < R) ? ldt<T>(x, xi + j, dtype) : T(0);
+        };
+        fetch(0);
         for (int64_t k0 = 0; k0 < ps; k0 += kKC) {
-            __syncthreads();
-            {   // panel chunk: thread -> row tid/4, 8 consecutive columns
-                const int rr = tid >> 2, cc = (tid & 3) * 8;
-                const int64_t prow = row0 + rr;
+            __syncthreads();   // the previous chunk's MFMAs are done with the LDS tiles
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int64_t col = k0 + cc + j;
-                    Ap[rr * kApS + cc + j] = (prow < a.cap && col < ps) ? pl[prow * ps + col] : T(0);
-                }
-            }
-            {   // rows of X for the chunk's columns: thread -> column tid/8, 8 consecutive rhs
-                const int kk = tid >> 3, rc = (tid & 7) * 8;
-                const int64_t col = k0 + kk;
-                const int64_t dof = col < ncols ? pp.pcols[cb + col] : -1;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int r = r0 + rc + j;
-                    Bx[kk * kBxS + rc + j] = (dof >= 0 && r < R) ? ldt<T>(x, xo + dof * R + r, dtype) : T(0);
-                }
+            for (int j = 0; j < 8; ++j) {
+                Ap[pr_ * kApS + pc_ + j] = pa[j];
+                Bx[xk_ * kBxS + xr_ + j] = xa[j];
             }
             __syncthreads();
+            if (k0 + kKC < ps) fetch(k0 + kKC);
             if constexpr (sizeof(T) == 4) {
 #pragma unroll
                 for (int k = 0; k < kKC; k += 2) {
