@@ -42,17 +42,30 @@ __global__ __launch_bounds__(128) void k_bup_leaf(ApplyPlan a, H2Tree t, int F, 
     bf32x16 c32 = {0};
     bf64x4 c64[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
     for (int64_t j0 = 0; j0 < n; j0 += JC) {
+        // all of this thread's loads in flight before the first wait: U rows (alpha = tid % 32,
+        // rows tid / 32 + 4m), the permutation, then x (rhs = tid % 64, rows tid / 64 + 2m)
+        T uv[JC * 32 / 128], xv[JC * kRC / 128];
+        int64_t pv[JC * kRC / 128];
+#pragma unroll
+        for (int m = 0; m < JC * 32 / 128; ++m) {
+            const int j = (tid >> 5) + 4 * m, al = tid & 31;
+            uv[m] = (j0 + j < n && al < K) ? U[(lb + j0 + j) * K + al] : T(0);
+        }
+#pragma unroll
+        for (int m = 0; m < JC * kRC / 128; ++m) {
+            const int j = (tid >> 6) + 2 * m;
+            pv[m] = j0 + j < n ? a.perm[lb + j0 + j] : -1;
+        }
+#pragma unroll
+        for (int m = 0; m < JC * kRC / 128; ++m) {
+            const int rr = tid & 63;
+            xv[m] = (pv[m] >= 0 && r0 + rr < R) ? (T)ldx(x, ((int64_t)f * a.N + pv[m]) * R + r0 + rr, dtype) : T(0);
+        }
         __syncthreads();
-        for (int i = tid; i < JC * 32; i += blockDim.x) {
-            const int j = i / 32, al = i % 32;
-            sU[j * US + al] = (j0 + j < n && al < K) ? U[(lb + j0 + j) * K + al] : T(0);
-        }
-        for (int i = tid; i < JC * kRC; i += blockDim.x) {
-            const int j = i / kRC, rr = i % kRC;
-            sX[j * XS + rr] = (j0 + j < n && r0 + rr < R)
-                                  ? (T)ldx(x, ((int64_t)f * a.N + a.perm[lb + j0 + j]) * R + r0 + rr, dtype)
-                                  : T(0);
-        }
+#pragma unroll
+        for (int m = 0; m < JC * 32 / 128; ++m) sU[((tid >> 5) + 4 * m) * US + (tid & 31)] = uv[m];
+#pragma unroll
+        for (int m = 0; m < JC * kRC / 128; ++m) sX[((tid >> 6) + 2 * m) * XS + (tid & 63)] = xv[m];
         __syncthreads();
         if constexpr (sizeof(T) == 4) {
 #pragma unroll 8
@@ -117,13 +130,26 @@ __global__ __launch_bounds__(256) void k_blevel(H2Tree t, int64_t c0, int F, int
     const int tid = threadIdx.x;
     const int64_t ch[2] = {2 * c + 1, 2 * c + 2};
     T* xf = xh + (int64_t)f * t.ncl * K * R;
-    for (int i = tid; i < 2 * EP; i += blockDim.x) sE[i] = E[ch[i / EP] * EP + i % EP];
-    const int nin = UP ? 2 : 1;
-    for (int i = tid; i < nin * K * kRC; i += blockDim.x) {
-        const int s = i / (K * kRC), al = (i / kRC) % K, rr = i % kRC;
-        const int64_t src = UP ? ch[s] : c;
-        sA[i] = r0 + rr < R ? xf[(src * K + al) * R + r0 + rr] : T(0);
+    constexpr int nin = UP ? 2 : 1, NE = (2 * EP + 255) / 256, NA = (nin * K * kRC + 255) / 256;
+    T ve[NE], va[NA];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        const int i = tid + 256 * m;
+        ve[m] = i < 2 * EP ? E[ch[i / EP] * EP + i % EP] : T(0);
     }
+#pragma unroll
+    for (int m = 0; m < NA; ++m) {
+        const int i = tid + 256 * m;
+        const int s = i / (K * kRC), al = (i / kRC) % K, rr = i % kRC;
+        const int64_t src = UP ? ch[s < 2 ? s : 1] : c;
+        va[m] = (i < nin * K * kRC && r0 + rr < R) ? xf[(src * K + al) * R + r0 + rr] : T(0);
+    }
+#pragma unroll
+    for (int m = 0; m < NE; ++m)
+        if (tid + 256 * m < 2 * EP) sE[tid + 256 * m] = ve[m];
+#pragma unroll
+    for (int m = 0; m < NA; ++m)
+        if (tid + 256 * m < nin * K * kRC) sA[tid + 256 * m] = va[m];
     __syncthreads();
     // first dimension (dim 0: index % P): sT[s][i0][i1][r], both children
     for (int i = tid; i < 2 * K * kRC; i += blockDim.x) {
@@ -178,20 +204,36 @@ __global__ __launch_bounds__(128) void k_bcoupling(H2Tree t, int F, int R, const
     const int64_t nfar = t.far_ptr[t.ncl];
     bf32x16 c32 = {0};
     bf64x4 c64[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
-    for (int64_t e = t.far_ptr[S]; e < t.far_ptr[S + 1]; ++e) {
+    // operands of a pair: S_e (thread -> alpha = tid % 32, beta = tid / 32 + 4m) and
+    // X^ of its source (rhs = tid % 64, beta = tid / 64 + 2m), fetched into registers
+    // one pair ahead so that the loads overlap the MFMAs
+    constexpr int NS = KP * KP / 128, NX = KP * kRC / 128;
+    T rs[NS], rx[NX];
+    auto fetch = [&](int64_t e) {
         const int64_t src = t.far_src[e];
         const T* Se = St + ((int64_t)f * nfar + e) * K * K;
         const T* Xe = xh + (((int64_t)f * t.ncl + src) * K) * R;
-        __syncthreads();
-        for (int i = tid; i < KP * KP; i += blockDim.x) {
-            const int be = i / KP, al = i % KP;
-            sS[be * SS + al] = (be < K && al < K) ? Se[be * K + al] : T(0);
+#pragma unroll
+        for (int m = 0; m < NS; ++m) {
+            const int be = (tid >> 5) + 4 * m, al = tid & 31;
+            rs[m] = (be < K && al < K) ? Se[be * K + al] : T(0);
         }
-        for (int i = tid; i < KP * kRC; i += blockDim.x) {
-            const int be = i / kRC, rr = i % kRC;
-            sX[be * XS + rr] = (be < K && r0 + rr < R) ? Xe[(int64_t)be * R + r0 + rr] : T(0);
+#pragma unroll
+        for (int m = 0; m < NX; ++m) {
+            const int be = (tid >> 6) + 2 * m, rr = tid & 63;
+            rx[m] = (be < K && r0 + rr < R) ? Xe[(int64_t)be * R + r0 + rr] : T(0);
         }
+    };
+    const int64_t e0 = t.far_ptr[S], e1 = t.far_ptr[S + 1];
+    if (e0 < e1) fetch(e0);
+    for (int64_t e = e0; e < e1; ++e) {
         __syncthreads();
+#pragma unroll
+        for (int m = 0; m < NS; ++m) sS[((tid >> 5) + 4 * m) * SS + (tid & 31)] = rs[m];
+#pragma unroll
+        for (int m = 0; m < NX; ++m) sX[((tid >> 6) + 2 * m) * XS + (tid & 63)] = rx[m];
+        __syncthreads();
+        if (e + 1 < e1) fetch(e + 1);
         if constexpr (sizeof(T) == 4) {
 #pragma unroll
             for (int k = 0; k < KP; k += 2) {
@@ -252,10 +294,33 @@ __global__ __launch_bounds__(256) void k_bout_leaf(ApplyPlan a, H2Tree t, int F,
     const int64_t c = t.first_leaf + li;
     T* sU = (T*)sraw;          // [n][K]
     T* sY = sU + n * K;        // [K][kRC]
-    for (int64_t i = threadIdx.x; i < n * K; i += blockDim.x) sU[i] = U[lb * K + i];
-    for (int i = threadIdx.x; i < K * kRC; i += blockDim.x) {
-        const int al = i / kRC, rr = i % kRC;
-        sY[i] = r0 + rr < R ? yh[(((int64_t)f * t.ncl + c) * K + al) * R + r0 + rr] : T(0);
+    {   // staging with every load of a thread in flight before the first wait (K <= 32, 64 rows a pass)
+        constexpr int NU = 64 * 32 / 256, NY = 32 * kRC / 256;
+        for (int64_t b0 = 0; b0 < n * K; b0 += 64 * 32) {
+            T vu[NU];
+#pragma unroll
+            for (int m = 0; m < NU; ++m) {
+                const int64_t i = b0 + threadIdx.x + 256 * m;
+                vu[m] = i < n * K ? U[lb * K + i] : T(0);
+            }
+#pragma unroll
+            for (int m = 0; m < NU; ++m) {
+                const int64_t i = b0 + threadIdx.x + 256 * m;
+                if (i < n * K) sU[i] = vu[m];
+            }
+        }
+        T vy[NY];
+#pragma unroll
+        for (int m = 0; m < NY; ++m) {
+            const int i = threadIdx.x + 256 * m;
+            const int al = i / kRC, rr = i % kRC;
+            vy[m] = (al < K && r0 + rr < R) ? yh[(((int64_t)f * t.ncl + c) * K + al) * R + r0 + rr] : T(0);
+        }
+#pragma unroll
+        for (int m = 0; m < NY; ++m) {
+            const int i = threadIdx.x + 256 * m;
+            if (i / kRC < K) sY[i] = vy[m];
+        }
     }
     __syncthreads();
     for (int64_t i = threadIdx.x; i < n * kRC; i += blockDim.x) {

@@ -273,7 +273,8 @@ __global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, cons
                     Cs[(wr + 16 * i + (lane >> 4) + 4 * v) * kCS + wc + 16 * j + (lane & 15)] = c64[i][j][v];
     }
     __syncthreads();
-    // CSR rows of B + M and the output: thread -> one rhs, rows strided by 4
+    // CSR rows of B + M and the output: thread -> one rhs, rows strided by 4 (a wave
+    // shares each row, so the column and value loads are uniform across it)
     const int rc = tid & 63;
     const int r = r0 + rc;
     if (r >= R) return;
@@ -284,8 +285,17 @@ __global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, cons
         double acc = (double)Cs[rr * kCS + rc];
         if (csr_val) {
             const double* v = csr_val + (int64_t)f * a.nnz;
-            for (int64_t e = a.csr_ptr[row]; e < a.csr_ptr[row + 1]; ++e)
+            const int64_t e1 = a.csr_ptr[row + 1];
+            int64_t e = a.csr_ptr[row];
+            double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            for (; e + 4 <= e1; e += 4) {   // four independent gathers in flight
                 acc += v[e] * ldx(x, xo + (int64_t)pp.csr_col_dof[e] * R + r, dtype);
+                s1 += v[e + 1] * ldx(x, xo + (int64_t)pp.csr_col_dof[e + 1] * R + r, dtype);
+                s2 += v[e + 2] * ldx(x, xo + (int64_t)pp.csr_col_dof[e + 2] * R + r, dtype);
+                s3 += v[e + 3] * ldx(x, xo + (int64_t)pp.csr_col_dof[e + 3] * R + r, dtype);
+            }
+            for (; e < e1; ++e) acc += v[e] * ldx(x, xo + (int64_t)pp.csr_col_dof[e] * R + r, dtype);
+            acc += (s1 + s2) + s3;
         }
         const int64_t dst = xo + (int64_t)a.perm[row] * R + r;
         if (dtype == 0) ((double*)y)[dst] = acc;
