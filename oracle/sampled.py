@@ -139,6 +139,7 @@ class SampledOracle:
             self.leaf_of_q[rt.members[c]] = c
         self.hmax = m.h_max()
         self._xhat = {}
+        self._xhat_of = None      # the vector the cached coefficients belong to
         self._mom = {}
         self._nodes = {}
 
@@ -185,7 +186,10 @@ class SampledOracle:
         return lagrange(axes, self.Q["x"][:, q]) @ wpsi
 
     def _xhat_cluster(self, c, x):
-        """U_c^T x_c with the basis of cluster c computed directly."""
+        """U_c^T x_c with the basis of cluster c computed directly (cached for the current x)."""
+        if self._xhat_of is None or self._xhat_of.shape != x.shape or not np.array_equal(self._xhat_of, x):
+            self._xhat = {}
+            self._xhat_of = np.array(x, copy=True)
         if c not in self._xhat:
             nodes, axes, sn, kn = self._cluster_nodes(("k", c), self.klo[c], self.khi[c])
             acc = np.zeros(nodes.shape[1])

@@ -1,6 +1,8 @@
-"""Full-size parity: the 128 x 128 square workload (16129 dofs, 131072 cells) in the
-launch configuration the benchmark times, checked on sampled rows that the oracle
-computes one by one (oracle.sampled), at 1e-10 of the output's max norm."""
+"""Full-size parity on sampled rows that the oracle computes one by one
+(oracle.sampled): the 128 x 128 square workload (16129 dofs, 131072 cells) in the
+launch configuration the benchmark times, and the batched 256 x 256 workload
+(16 fields x 64 right-hand sides), at 1e-10 of the output's max norm (1e-6 for the
+mixed-precision operator)."""
 import numpy as np
 import pytest
 
@@ -43,3 +45,38 @@ def test_square128_sampled_rows():
     err = np.abs(y[rows] - out["total"]).max() / scale
     print(f"[fullsize] total: {err:.2e}", flush=True)
     assert err < TOL
+
+
+def test_batched256_sampled_rows():
+    """The batched workload at full size (256 x 256 squares, 65025 dofs, 16 order fields
+    x 64 right-hand sides, values rounded to FP32): FP64 operator at 1e-10 and the
+    mixed-precision operator at 1e-6 of the output's max norm on sampled (field, rhs,
+    row) entries, with FP64 vectors; FP32 vectors agree with them to FP32 rounding."""
+    import paper_2302_02863_amd as fp
+    P = configs.batched(256, n_fields=16, nrhs=64)
+    m = P.mesh
+    x64 = torch.tensor(P.x, device="cuda", dtype=torch.float64)
+    x32 = x64.float()
+    ys = {}
+    for precision in ("fp64", "mixed"):
+        o = dict(P.opts)
+        o["precision"] = precision
+        print(f"[fullsize] batched build {precision} N={m.n_dofs} F=16", flush=True)
+        op = fp.Operator(m, P.s, P.kappa, o)
+        ys[precision] = op.apply(x64).cpu().numpy()
+        y32 = op.apply(x32).double().cpu().numpy()
+        d = np.abs(y32 - ys[precision]).max() / np.abs(ys[precision]).max()
+        print(f"[fullsize] batched {precision} FP32 vectors vs FP64 vectors: {d:.2e}", flush=True)
+        assert d < 1e-6
+        op.close()
+    rng = np.random.default_rng(23)
+    for f in (0, 15):
+        so = SampledOracle(m, P.s[f], P.kappa[f], P.opts)
+        rows = list(rng.choice(m.n_dofs, size=2, replace=False))
+        for r in rng.choice(64, size=2, replace=False):
+            out = so.row_apply(rows, P.x[f, :, r])
+            for precision, tol in (("fp64", TOL), ("mixed", 1e-6)):
+                y = ys[precision][f, :, r]
+                err = np.abs(y[rows] - out["total"]).max() / np.abs(y).max()
+                print(f"[fullsize] batched {precision} field {f} rhs {r}: {err:.2e}", flush=True)
+                assert err < tol, (precision, f, r, err)
