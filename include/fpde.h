@@ -204,11 +204,14 @@ fpde_status fpde_apply_adjoint(fpde_op *op, const double *w, const double *u, in
 
 /* Device-time profile of fpde_apply.  While profiling is on, each apply runs
  * the same kernels as its captured graph, serialised on the apply's stream,
- * with HIP events: far = the H2 chain (upsweep, top levels, coupling), out =
- * start-to-stop timestamps of the near-field kernel (CSR + near leaf blocks,
- * the dominant kernel, launched with hipExtLaunchKernelGGL events), far_out =
- * downsweep walk and U yh added to y, total = whole apply.  ms_gather is 0
- * (the vectors are read in place).  fpde_profile(op, 1, NULL) resets and
+ * with HIP events: out = start-to-stop timestamps of the near-field kernel
+ * (the dominant kernel, launched with hipExtLaunchKernelGGL events: CSR +
+ * near leaf blocks, and for one right-hand side the far-field upsweep in the
+ * same launch), far = far-field work enqueued before it (the H2 upsweep and
+ * coupling of several right-hand sides; 0 for one), far_out = from the end
+ * of the near-field kernel to the end of the apply (coupling, downsweep and
+ * U yh added to y), total = whole apply.  ms_gather is 0 (the vectors are
+ * read in place).  fpde_profile(op, 1, NULL) resets and
  * starts recording; fpde_profile(op, 0, out) stops, waits for the recorded
  * events and returns the sums. */
 typedef struct {

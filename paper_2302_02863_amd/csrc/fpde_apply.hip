@@ -3,11 +3,21 @@
 // B + M stays FP64, the near leaf blocks, bases, transfers and coupling
 // matrices are FP32 and their products accumulate in FP32).
 //
-// One apply is a fork/join of five kernels:
-//   main stream:  k_near_panel   CSR row of B + M and the packed near panel row
-//   side stream:  k_up_tree      leaf coefficients and the whole upsweep
-//                 k_coupling1    S x^ for every far pair
-//   after join:   k_far_out1     per-leaf downsweep walk fused with the output
+// One apply is three launches on one stream:
+//   k_near_up    blocks [0, nup): the upsweep (leaf coefficients, then the
+//                nested transfers up to the shallowest level a far pair reads);
+//                blocks [nup, ...): the near rows (CSR row of B + M and the
+//                packed near panel row).  The subtree roots that one upsweep
+//                block hands to another are stored and loaded as agent-scope
+//                atomics, which bypass the per-XCD L2 copies; every wave waits
+//                for its stores to be acknowledged before the block's barrier
+//                and its one ticket increment, so no cache writeback or
+//                invalidate is needed, and no block ever waits for another
+//                (the last arrival goes on), so the launch always drains.
+//   k_couple     z^(c) = sum over the far pairs (c, s) of S x^(s), one block
+//                per far target cluster.
+//   k_far_out    per leaf: the walk down its root path (y^ of a child is its
+//                z^ plus the transfer of its parent's y^), U y^ added to y.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -17,51 +27,83 @@
 
 namespace fpde {
 
-// Upsweep of the whole tree in one launch (nested bases, Sec. 5.3).
-// Stage 0: block b owns the subtree of depth d0 rooted at level L - d0: leaf
-// coefficients x^_leaf = U_leaf^T x_leaf (one wave per leaf, the leaf's x rows
-// staged in LDS), then the subtree's levels in LDS.  Upper stages: every group
-// of subtrees under one ancestor ds levels up counts its finished blocks with a
-// ticket (agent-scope release fence of every thread, block barrier, one atomic
-// per block, agent-scope acquire fence in the last block); the last block of the group
-// computes the ancestor's subtree levels from the published coefficients,
-// resets the ticket and goes on to the next group.  No block ever waits for
-// another, so the launch always drains.  Loads that do not depend on other
-// blocks (U rows, transfers) are issued before the dependent ones.
+constexpr int kApplyThreads = 256;
+
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+
+// heap id -> level
+__device__ __forceinline__ int heap_level(int64_t c) {
+    int lev = 0;
+    while (((int64_t(2) << lev) - 1) <= c) ++lev;
+    return lev;
+}
+
+// Stores and loads of values that another block of the same launch reads:
+// agent-scope atomics, coherent across the XCDs' L2 caches.
+template <typename T>
+__device__ __forceinline__ void put(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T get(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Upsweep (nested bases, Sec. 5.3) from the leaves up to level lmin.
+// Stage 0: upsweep block b owns the subtree of depth d0 rooted at level L - d0
+// (2^d0 leaves, at most one per wave): leaf coefficients x^_leaf = U_leaf^T
+// x_leaf, the leaf's rows split over the waves of the leaf (x rows staged in
+// LDS, partial sums combined in a fixed order), then the subtree's levels in
+// LDS.  Upper stages: every
+// group of subtrees under one ancestor ds levels up counts its finished blocks
+// with a ticket; the last block of the group computes the ancestor's subtree
+// levels from the other blocks' subtree roots, resets the ticket and goes on to
+// the next group.  Loads that do not depend on other blocks (U rows,
+// transfers) are issued before the dependent ones.
 template <int D, int P, typename T>
-__global__ __launch_bounds__(512) void k_up_tree(ApplyPlan a, H2Tree t, UpPlan up, int F, int dtype, const void* x,
-                                                 const T* U, const T* E, T* xh, unsigned int* tickets) {
+__device__ __forceinline__ void up_tree(const ApplyPlan& a, const H2Tree& t, const UpPlan& up, int dtype,
+                                        const void* x, const T* U, const T* E, T* xh, unsigned int* tickets, int f,
+                                        int64_t bid, T* sm) {
     constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
-    constexpr int kRows = 32;   // rows per half-wave held in registers (leaves of up to 64 rows)
-    extern __shared__ __align__(16) unsigned char sraw[];
-    T* sm = (T*)sraw;
+    constexpr int kRows = 16;   // rows per half-wave held in registers (32 rows per wave)
     __shared__ unsigned int s_ticket;
-    const int f = blockIdx.y;
     const int L = t.L;
-    int lc = L - up.d0;                                 // root level of the current subtree
-    int64_t c = ((int64_t(1) << lc) - 1) + blockIdx.x;  // its heap id
+    int lc = L - up.d0;                          // root level of the current subtree
+    int64_t c = ((int64_t(1) << lc) - 1) + bid;  // its heap id
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     T* xf = xh + (int64_t)f * t.ncl * K;
     // local heap index l of a subtree rooted at r -> global heap id
     auto gid = [](int64_t r, int64_t l) -> int64_t {
-        int lev = 0;
-        while (((int64_t(2) << lev) - 1) <= l) ++lev;
+        const int lev = heap_level(l);
         const int64_t w = int64_t(1) << lev;
         return (r + 1) * w - 1 + (l - (w - 1));
     };
     {
-        const int depth = up.d0;
+        const int depth = up.d0;                     // 2^depth leaves, at most one per wave
         const int64_t ncs = (int64_t(2) << depth) - 1;
+        const int nl = 1 << depth, wpl = nw / nl;    // waves per leaf
         T* sc = sm;                          // [ncs][K]
         T* sE = sc + ncs * K;                // [ncs][EP]
-        T* sx = sE + ncs * EP;               // [waves][cap]
+        T* sp = sE + ncs * EP;               // [waves][K] partial sums
+        T* sx = sp + nw * K;                 // [waves][cap]
         for (int64_t i = threadIdx.x + EP; i < ncs * EP; i += blockDim.x) sE[i] = E[gid(c, i / EP) * EP + i % EP];
-        const int64_t nl = int64_t(1) << depth;
         const int64_t l0 = ((c + 1) << depth) - 1;
         T* sxw = sx + (int64_t)wv * a.cap;
-        for (int64_t li = wv; li < nl; li += nw) {
-            const int64_t cc = l0 + li;
-            const int64_t rb = t.beg[cc], n = t.end[cc] - rb;
+        {
+            const int64_t cc = l0 + wv / wpl;
+            const int wi = wv % wpl;
+            const int64_t rl = t.beg[cc], nll = t.end[cc] - rl;
+            // this wave's share of the leaf's rows
+            const int64_t rb = rl + nll * wi / wpl, n = rl + nll * (wi + 1) / wpl - rb;
             // lanes (half, alpha): with K <= 32 the two half-waves split the rows
             const int half = K <= 32 ? (lane >> 5) : 0;
             const int al = K <= 32 ? (lane & 31) : lane;
@@ -95,13 +137,15 @@ __global__ __launch_bounds__(512) void k_up_tree(ApplyPlan a, H2Tree t, UpPlan u
                 v = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
             }
             if (K <= 32) v += __shfl_xor(v, 32, 64);
-            if (lane < K) {
-                sc[(nl - 1 + li) * K + lane] = v;
-                xf[cc * K + lane] = v;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (lane < K) sp[wv * K + lane] = v;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nl * K; i += blockDim.x) {   // the waves of a leaf, in a fixed order
+            const int l = i / K, al = i % K;
+            T s = 0;
+            for (int w = 0; w < wpl; ++w) s += sp[(l * wpl + w) * K + al];
+            sc[(nl - 1 + l) * K + al] = s;
+            put(&xf[(l0 + l) * K + al], s);
         }
         __syncthreads();
         for (int lev = depth - 1; lev >= 0; --lev) {
@@ -112,13 +156,13 @@ __global__ __launch_bounds__(512) void k_up_tree(ApplyPlan a, H2Tree t, UpPlan u
                 const int64_t l1 = 2 * lcl + 1, l2 = 2 * lcl + 2;
                 const T v = up_t<D, P, T>(sE + l1 * EP, sE + l2 * EP, sc + l1 * K, sc + l2 * K, al, 1);
                 sc[lcl * K + al] = v;
-                xf[gid(c, lcl) * K + al] = v;
+                put(&xf[gid(c, lcl) * K + al], v);
             }
             __syncthreads();
         }
     }
-    while (lc > 0) {
-        const int ln = lc - up.ds > 0 ? lc - up.ds : 0;
+    while (lc > up.lmin) {
+        const int ln = lc - up.ds > up.lmin ? lc - up.ds : up.lmin;
         const int depth = lc - ln;
         const int64_t g = ((c + 1) >> depth) - 1;     // ancestor at level ln
         const int64_t ncs = (int64_t(2) << depth) - 1, w0 = int64_t(1) << depth;
@@ -126,20 +170,19 @@ __global__ __launch_bounds__(512) void k_up_tree(ApplyPlan a, H2Tree t, UpPlan u
         T* sE = sc + ncs * K;
         // transfers of the group's subtree do not depend on other blocks: load them first
         for (int64_t i = threadIdx.x + EP; i < ncs * EP; i += blockDim.x) sE[i] = E[gid(g, i / EP) * EP + i % EP];
-        // publish: every thread's coefficient stores are released at agent scope before
-        // the barrier; one ticket per block; the last block acquires the others' stores
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // publish: the root's agent-scope stores of every wave are acknowledged
+        // before the barrier, then one ticket per block
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0)
             s_ticket = __hip_atomic_fetch_add(&tickets[(int64_t)f * t.ncl + g], 1u, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
         if (s_ticket != (unsigned int)((1u << depth) - 1)) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (threadIdx.x == 0)   // every group's blocks have arrived: reset for the next launch
             __hip_atomic_store(&tickets[(int64_t)f * t.ncl + g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (int64_t i = threadIdx.x; i < w0 * K; i += blockDim.x)
-            sc[(w0 - 1) * K + i] = __builtin_nontemporal_load(&xf[(((g + 1) << depth) - 1) * K + i]);
+            sc[(w0 - 1) * K + i] = get(&xf[(((g + 1) << depth) - 1) * K + i]);
         __syncthreads();
         for (int lev = depth - 1; lev >= 0; --lev) {
             const int64_t w = int64_t(1) << lev, lfirst = w - 1;
@@ -149,7 +192,7 @@ __global__ __launch_bounds__(512) void k_up_tree(ApplyPlan a, H2Tree t, UpPlan u
                 const int64_t l1 = 2 * lcl + 1, l2 = 2 * lcl + 2;
                 const T v = up_t<D, P, T>(sE + l1 * EP, sE + l2 * EP, sc + l1 * K, sc + l2 * K, al, 1);
                 sc[lcl * K + al] = v;
-                xf[gid(g, lcl) * K + al] = v;
+                put(&xf[gid(g, lcl) * K + al], v);
             }
             __syncthreads();
         }
@@ -158,42 +201,146 @@ __global__ __launch_bounds__(512) void k_up_tree(ApplyPlan a, H2Tree t, UpPlan u
     }
 }
 
-// tmp[f][e][alpha] = sum_beta S_e[alpha][beta] x^[f][src(e)][beta]; St holds S_e transposed
-// ([beta][alpha]) so that consecutive threads (alpha) read consecutive entries.
+// Coupling of far target cluster c (Sec. 5.2): z^(c) = sum over the far pairs
+// (c, s) of S x^(s).  Pair slots of G lanes (lane alpha) each take every NS-th
+// pair of c and accumulate S[alpha][beta] x^(s)[beta]; St holds S transposed
+// ([beta][alpha]) so that the lanes read consecutive entries, and x^(s)[beta]
+// is broadcast from lane beta of the slot.  The slots are summed in a fixed
+// order.  z^ of clusters that are not targets stays zero.
 template <int D, int P, typename T>
-FPDE_KERNEL void k_coupling1(H2Tree t, int64_t nfar, int F, const T* St, const T* xh, T* tmp) {
+__device__ __forceinline__ void couple(const H2Tree& t, int64_t c, int f, const T* St, const T* xh, T* zh, T* sred) {
     constexpr int K = KR<D, P>::K;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)F * nfar * K) return;
-    const int64_t fe = i / K;
-    const int al = (int)(i % K);
-    const int f = (int)(fe / nfar);
-    const int64_t e = fe - (int64_t)f * nfar;
-    const T* S = St + fe * K * K + al;
-    const T* xs = xh + ((int64_t)f * t.ncl + t.far_src[e]) * K;
+    constexpr int G = K <= 32 ? 32 : 64;   // lanes of a pair slot
+    constexpr int NS = kApplyThreads / G;  // pair slots
+    const int64_t nfar = t.far_ptr[t.ncl];
+    const int64_t e0 = t.far_ptr[c], e1 = t.far_ptr[c + 1];
+    const int sl = threadIdx.x / G, al = threadIdx.x % G;
+    const int base = (threadIdx.x & 63) & ~(G - 1);   // first lane of the slot within the wave
+    const T* xf = xh + (int64_t)f * t.ncl * K;
     T acc = 0;
+    for (int64_t e = e0 + sl; e < e1; e += NS) {   // the lanes of a slot share e
+        const T* S = St + ((int64_t)f * nfar + e) * K * K + (al < K ? al : 0);
+        T sv[K];
 #pragma unroll
-    for (int b = 0; b < K; ++b) acc += S[b * K] * xs[b];
-    tmp[i] = acc;
+        for (int b = 0; b < K; ++b) sv[b] = S[b * K];
+        const T xv = al < K ? xf[t.far_src[e] * K + al] : T(0);
+#pragma unroll
+        for (int b = 0; b < K; ++b) acc += sv[b] * __shfl(xv, base + b, 64);
+    }
+    sred[sl * G + al] = acc;
+    __syncthreads();
+    if (threadIdx.x < K) {
+        T z = 0;
+        for (int s = 0; s < NS; ++s) z += sred[s * G + threadIdx.x];
+        zh[((int64_t)f * t.ncl + c) * K + threadIdx.x] = z;
+    }
 }
 
-// y[perm[row]] += U[row] . y^_leaf, where y^_leaf accumulates, from the root
-// down, y^(c) = sum_{e in far(c)} tmp[e] plus the transfer of the parent's.
-// One block per (leaf, 64 rows, field); the root-to-leaf walk is redone per block.
+// Near rows: y[f][perm[row]] = (B+M)_row . x + panel_row . x_near for the 16
+// rows of block rb of leaf li, 16 lanes per row.  The x entries of the leaf's
+// near columns are staged in LDS once per block.  Each lane keeps 8 vector
+// loads of its panel row in flight; the first 8 are issued before the x
+// staging and the CSR row, so their latency overlaps those gathers.
+template <typename T>
+__device__ __forceinline__ void near_rows(const ApplyPlan& a, const PanelPlan& pp, const T* panel, int use_near,
+                                          const double* csr_val, int dtype, const void* x, void* y, int f,
+                                          int64_t bid, T* xs) {
+    using V2 = typename Vec2<T>::type;
+    constexpr int NB = 8;   // vector loads in flight per lane (32 columns apart)
+    const int64_t nrb = (a.cap + 15) / 16;
+    const int64_t li = bid / nrb;
+    const int rb = (int)(bid % nrb);
+    const int64_t xo = (int64_t)f * a.N;
+    const int g = threadIdx.x & 15;
+    const int64_t it = (int64_t)rb * 16 + (threadIdx.x >> 4);
+    const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
+    const bool ok = it < nt;
+    const int64_t row = lb + it;
+    const int64_t ps = use_near ? pp.pstride[li] : 0;
+    const T* pr = panel + (int64_t)f * pp.poff[a.nleaf] + pp.poff[li] + it * ps + 2 * g;
+    V2 q[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        if (ok && 2 * g + 32 * k + 2 <= ps) q[k] = *(const V2*)(pr + 32 * k);
+    if (use_near) {   // padding columns of the row stride hold 0 in the panel and in xs
+        const int64_t c0 = pp.pcols_ptr[li], ncols = pp.pcols_ptr[li + 1] - c0;
+        for (int64_t c = threadIdx.x; c < ps; c += blockDim.x)
+            xs[c] = c < ncols ? (T)ldx(x, xo + pp.pcols[c0 + c], dtype) : T(0);
+    }
+    double acc = 0.0;
+    if (ok && csr_val) {
+        const double* v = csr_val + (int64_t)f * a.nnz;
+        for (int64_t e = a.csr_ptr[row] + g; e < a.csr_ptr[row + 1]; e += 16)
+            acc += v[e] * ldx(x, xo + pp.csr_col_dof[e], dtype);
+    }
+    __syncthreads();
+    if (!ok) return;
+    if (use_near) {
+        T s[4] = {0, 0, 0, 0};
+        const T* xl = xs + 2 * g;
+        int64_t c = 0;   // column offset of q[0] relative to 2g
+        for (;;) {
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+                if (2 * g + c + 32 * k + 2 <= ps)
+                    s[k & 3] += q[k].x * xl[c + 32 * k] + q[k].y * xl[c + 32 * k + 1];
+            c += 32 * NB;
+            if (2 * g + c + 2 > ps) break;
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+                if (2 * g + c + 32 * k + 2 <= ps) q[k] = *(const V2*)(pr + c + 32 * k);
+        }
+        acc += (double)((s[0] + s[1]) + (s[2] + s[3]));
+    }
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    if (g == 0) {
+        const int64_t dst = xo + a.perm[row];
+        if (dtype == 0) ((double*)y)[dst] = acc;
+        else ((float*)y)[dst] = (float)acc;
+    }
+}
+
+// Upsweep blocks first, then the near rows.  The upsweep blocks are
+// dispatched first, so their dependent chain starts at once beside the near
+// rows' HBM stream.
 template <int D, int P, typename T>
-FPDE_KERNEL void k_far_out1(ApplyPlan a, H2Tree t, int F, const T* tmp, const T* U, const T* E, int dtype, void* y) {
+__global__ __launch_bounds__(kApplyThreads) void k_near_up(ApplyPlan a, H2Tree t, PanelPlan pp, UpPlan up, int nup,
+                                                           const T* panel, int use_near, const double* csr_val,
+                                                           int dtype, const void* x, void* y, const T* U, const T* E,
+                                                           T* xh, unsigned int* tickets) {
+    extern __shared__ __align__(16) unsigned char sraw[];
+    const int f = blockIdx.y;
+    if ((int)blockIdx.x < nup)
+        up_tree<D, P, T>(a, t, up, dtype, x, U, E, xh, tickets, f, blockIdx.x, (T*)sraw);
+    else
+        near_rows<T>(a, pp, panel, use_near, csr_val, dtype, x, y, f, (int64_t)blockIdx.x - nup, (T*)sraw);
+}
+
+// One block per far target cluster tgt[b].
+template <int D, int P, typename T>
+__global__ __launch_bounds__(kApplyThreads) void k_couple(H2Tree t, FarPlan fp, const T* St, const T* xh, T* zh) {
+    __shared__ T sred[kApplyThreads];
+    couple<D, P, T>(t, fp.tgt[blockIdx.x], blockIdx.y, St, xh, zh, sred);
+}
+
+// Downsweep and output (Sec. 5.3): y[perm[row]] += U[row] . y^_leaf, where
+// y^ of a cluster is its z^ plus the transfer of its parent's y^, from level
+// ltop (the shallowest target) down.  One block per (leaf, 64 rows, field),
+// 4 lanes per row; the basis rows, output indices, old y values, transfers
+// and z^ of the root path are all fetched before the walk.
+template <int D, int P, typename T>
+__global__ __launch_bounds__(kApplyThreads) void k_far_out(ApplyPlan a, H2Tree t, int ltop, const T* zh, const T* U,
+                                                           const T* E, int dtype, void* y) {
     constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
     extern __shared__ __align__(16) unsigned char sraw[];
-    T* sy = (T*)sraw;
+    const int L = t.L, nlev = L + 1 - ltop;
+    T* sy = (T*)sraw;                       // [nlev][K]
+    T* sE = sy + (int64_t)nlev * K;         // [nlev][EP]
     const int f = blockIdx.y;
     const int64_t nrb = (a.cap + 63) / 64;
     const int64_t li = blockIdx.x / nrb;
     const int rb = (int)(blockIdx.x % nrb);
     const int64_t leafc = t.first_leaf + li;
-    const int L = t.L;
-    const int64_t nfar = t.far_ptr[t.ncl];
-    T* sE = sy + (int64_t)(L + 1) * K;
-    // output row of this thread (4 lanes per row) and its basis row, fetched before the walk
     const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
     const int g = threadIdx.x & 3;
     const int64_t it = (int64_t)rb * 64 + (threadIdx.x >> 2);
@@ -201,34 +348,28 @@ FPDE_KERNEL void k_far_out1(ApplyPlan a, H2Tree t, int F, const T* tmp, const T*
     T u[(K + 3) / 4];
 #pragma unroll
     for (int q = 0; q < (K + 3) / 4; ++q) u[q] = (ok && 4 * q + g < K) ? U[(lb + it) * K + 4 * q + g] : T(0);
-    for (int64_t i = threadIdx.x; i < (int64_t)(L + 1) * K; i += blockDim.x) {
-        const int lev = (int)(i / K);
-        const int64_t cc = ((leafc + 1) >> (L - lev)) - 1;
-        const int w = (int)(i % K);
-        const int64_t e0 = t.far_ptr[cc], e1 = t.far_ptr[cc + 1];
-        const T* tp = tmp + ((int64_t)f * nfar) * K + w;
-        T s[4] = {0, 0, 0, 0};
-        for (int64_t e = e0; e < e1; e += 16) {   // sixteen independent loads in flight
-            T v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = e + q < e1 ? tp[(e + q) * K] : T(0);
-#pragma unroll
-            for (int q = 0; q < 16; ++q) s[q & 3] += v[q];
-        }
-        sy[i] = (s[0] + s[1]) + (s[2] + s[3]);
+    int64_t dst = 0;
+    double yold = 0.0;
+    if (ok && g == 0) {
+        dst = (int64_t)f * a.N + a.perm[lb + it];
+        yold = ldx(y, dst, dtype);
     }
-    for (int64_t i = threadIdx.x; i < (int64_t)(L + 1) * EP; i += blockDim.x) {
-        const int lev = (int)(i / EP);
-        const int64_t cc = ((leafc + 1) >> (L - lev)) - 1;
-        sE[i] = lev == 0 ? T(0) : E[cc * EP + i % EP];
+    const T* zf = zh + (int64_t)f * t.ncl * K;
+    for (int i = threadIdx.x; i < nlev * K; i += blockDim.x) {
+        const int lev = ltop + i / K;
+        sy[i] = zf[(((leafc + 1) >> (L - lev)) - 1) * K + i % K];
+    }
+    for (int i = threadIdx.x; i < nlev * EP; i += blockDim.x) {
+        const int lev = ltop + i / EP;
+        sE[i] = E[(((leafc + 1) >> (L - lev)) - 1) * EP + i % EP];
     }
     __syncthreads();
-    for (int lev = 1; lev <= L; ++lev) {
+    for (int l = 1; l < nlev; ++l) {
         for (int i = threadIdx.x; i < K; i += blockDim.x)
-            sy[lev * K + i] += down_t<D, P, T>(sE + lev * EP, sy + (lev - 1) * K, i, 1);
+            sy[l * K + i] += down_t<D, P, T>(sE + l * EP, sy + (l - 1) * K, i, 1);
         __syncthreads();
     }
-    const T* cur = sy + L * K;
+    const T* cur = sy + (int64_t)(nlev - 1) * K;
     T acc = 0;
 #pragma unroll
     for (int q = 0; q < (K + 3) / 4; ++q)
@@ -236,123 +377,115 @@ FPDE_KERNEL void k_far_out1(ApplyPlan a, H2Tree t, int F, const T* tmp, const T*
     acc += __shfl_xor(acc, 1, 4);
     acc += __shfl_xor(acc, 2, 4);
     if (ok && g == 0) {
-        const int64_t dst = (int64_t)f * a.N + a.perm[lb + it];
-        if (dtype == 0) ((double*)y)[dst] += (double)acc;
-        else ((float*)y)[dst] = (float)((double)((float*)y)[dst] + (double)acc);
+        if (dtype == 0) ((double*)y)[dst] = yold + (double)acc;
+        else ((float*)y)[dst] = (float)(yold + (double)acc);
     }
 }
 
 template <int D, int P, typename T>
-static size_t up_tree_lds(const H2Tree& t, int64_t cap, int d0, int ds) {
+static size_t up_tree_lds(int64_t cap, int d0, int ds) {
     constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
-    (void)t;
-    const int64_t nl = int64_t(1) << d0;
-    const int64_t waves = nl < 8 ? nl : 8;
-    const int64_t s0 = ((int64_t(2) << d0) - 1) * (K + EP) + waves * cap;
+    constexpr int64_t waves = kApplyThreads / 64;
+    const int64_t s0 = ((int64_t(2) << d0) - 1) * (K + EP) + waves * (K + cap);
     const int64_t s1 = ((int64_t(2) << ds) - 1) * (K + EP);
     return sizeof(T) * (size_t)(s0 > s1 ? s0 : s1);
 }
 
+// far-field part of a near block: y^ and transfers of the root path from ltop
 template <int D, int P, typename T>
-static void far_chain1(const ApplyPlan& a, const H2Tree& t, const UpPlan& up, int F, int64_t nfar, int dtype,
-                       const void* x, const OpData<T>& od, unsigned int* tickets, hipStream_t fs) {
-    constexpr int K = KR<D, P>::K;
-    const int64_t nl = int64_t(1) << up.d0;
-    const int waves = (int)(nl < 8 ? nl : 8);
-    const size_t lds = up_tree_lds<D, P, T>(t, a.cap, up.d0, up.ds);
-    hipLaunchKernelGGL((k_up_tree<D, P, T>), dim3((unsigned)(int64_t(1) << (t.L - up.d0)), F), dim3(64 * waves), lds,
-                       fs, a, t, up, F, dtype, x, od.U, od.E, od.xh, tickets);
-    if (nfar > 0)
-        hipLaunchKernelGGL((k_coupling1<D, P, T>), dim3(grid1((int64_t)F * nfar * K)), dim3(256), 0, fs, t, nfar, F,
-                           od.St, od.xh, od.tmp);
-}
-
-template <int D, int P, typename T>
-static void far_out1(const ApplyPlan& a, const H2Tree& t, int F, const OpData<T>& od, int dtype, void* y,
-                     hipStream_t st) {
+static size_t path_lds(const H2Tree& t, int ltop) {
     constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
-    const int64_t nrb = (a.cap + 63) / 64;
-    const size_t lds = sizeof(T) * ((int64_t)(t.L + 1) * (K + EP));
-    hipLaunchKernelGGL((k_far_out1<D, P, T>), dim3((unsigned)(a.nleaf * nrb), F), dim3(256), lds, st, a, t, F, od.tmp,
-                       od.U, od.E, dtype, y);
+    return sizeof(T) * (size_t)((int64_t)(t.L + 1 - ltop) * (K + EP));
 }
 
 // (dim, points) dispatch of the templates above for one operator precision T
 template <typename T>
 struct Single {
     template <int D, int P>
-    static void chain(const ApplyPlan& a, const H2Tree& t, const UpPlan& up, int F, int64_t nfar, int dtype,
-                      const void* x, const OpData<T>& od, unsigned int* tickets, hipStream_t fs) {
-        far_chain1<D, P, T>(a, t, up, F, nfar, dtype, x, od, tickets, fs);
+    static void near_up(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up, bool far,
+                        int use_near, const double* csr_val, int F, int dtype, const void* x, void* y,
+                        const OpData<T>& od, unsigned int* tickets, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+        const int nup = far ? (int)(int64_t(1) << (t.L - up.d0)) : 0;
+        const int64_t nrb = (a.cap + 15) / 16;
+        size_t lds = sizeof(T) * (pp.max_stride > 0 ? pp.max_stride : 1);
+        if (far) {
+            const size_t lu = up_tree_lds<D, P, T>(a.cap, up.d0, up.ds);
+            if (lu > lds) lds = lu;
+        }
+        const dim3 grid((unsigned)(nup + a.nleaf * nrb), F);
+        if (e0)   // start/stop timestamps of exactly this kernel
+            hipExtLaunchKernelGGL((k_near_up<D, P, T>), grid, dim3(kApplyThreads), lds, st, e0, e1, 0, a, t, pp, up,
+                                  nup, od.panel, use_near, csr_val, dtype, x, y, od.U, od.E, od.xh, tickets);
+        else
+            hipLaunchKernelGGL((k_near_up<D, P, T>), grid, dim3(kApplyThreads), lds, st, a, t, pp, up, nup, od.panel,
+                               use_near, csr_val, dtype, x, y, od.U, od.E, od.xh, tickets);
     }
     template <int D, int P>
-    static void out(const ApplyPlan& a, const H2Tree& t, int F, const OpData<T>& od, int dtype, void* y,
-                    hipStream_t st) {
-        far_out1<D, P, T>(a, t, F, od, dtype, y, st);
+    static void far_out(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<T>& od, int dtype,
+                        void* y, hipStream_t st) {
+        hipLaunchKernelGGL((k_couple<D, P, T>), dim3((unsigned)fp.ntgt, F), dim3(kApplyThreads), 0, st, t, fp, od.St,
+                           od.xh, od.zh);
+        const int64_t nrb = (a.cap + 63) / 64;
+        const size_t lds = path_lds<D, P, T>(t, fp.ltop);
+        hipLaunchKernelGGL((k_far_out<D, P, T>), dim3((unsigned)(a.nleaf * nrb), F), dim3(kApplyThreads), lds, st, a,
+                           t, fp.ltop, od.zh, od.U, od.E, dtype, y);
     }
-    // leaf-stage depth d0 (at most 3: 8 leaves, one wave each) and the deepest
-    // upper-stage depth ds whose subtree fits 64 KB of LDS
+    // leaf-stage depth d0 (1: two leaves, two waves each; at most 2, one leaf
+    // per wave) and the upper-stage depth ds: the levels above the stage-0
+    // roots up to lmin in one stage if they fit 64 KB of LDS
     template <int D, int P>
-    static void plan(const H2Tree& t, int64_t cap, UpPlan* up) {
+    static void plan(const H2Tree& t, int64_t cap, int lmin, UpPlan* up) {
         const size_t lim = 64 * 1024;
-        up->d0 = t.L < 3 ? t.L : 3;
-        while (up->d0 > 0 && up_tree_lds<D, P, T>(t, cap, up->d0, 1) > lim) --up->d0;
+        up->lmin = lmin;
+        up->d0 = t.L < 1 ? t.L : 1;
+        while (up->d0 > 0 && up_tree_lds<D, P, T>(cap, up->d0, 1) > lim) --up->d0;
+        const int need = t.L - up->d0 - lmin > 1 ? t.L - up->d0 - lmin : 1;
         up->ds = 1;
-        while (up->ds < 16 && up_tree_lds<D, P, T>(t, cap, up->d0, up->ds + 1) <= lim) ++up->ds;
-        up->ok = up_tree_lds<D, P, T>(t, cap, up->d0, up->ds) <= lim && KR<D, P>::K <= 64 && cap <= 256;
+        while (up->ds < need && up_tree_lds<D, P, T>(cap, up->d0, up->ds + 1) <= lim) ++up->ds;
+        up->path_lds = path_lds<D, P, T>(t, 0);
+        up->ok = up_tree_lds<D, P, T>(cap, up->d0, up->ds) <= lim && up->path_lds <= lim &&
+                 KR<D, P>::K <= 64 && cap <= 256;
     }
 };
 
-UpPlan plan_up_tree(const H2Tree& t, int64_t cap, int prec) {
+UpPlan plan_up_tree(const H2Tree& t, int64_t cap, int lmin, int prec) {
     UpPlan up{};
-    if (prec == 0) FPDE_DISPATCH_DP(t.dim, t.p, Single<double>::template plan, t, cap, &up);
-    else FPDE_DISPATCH_DP(t.dim, t.p, Single<float>::template plan, t, cap, &up);
+    if (prec == 0) FPDE_DISPATCH_DP(t.dim, t.p, Single<double>::template plan, t, cap, lmin, &up);
+    else FPDE_DISPATCH_DP(t.dim, t.p, Single<float>::template plan, t, cap, lmin, &up);
     return up;
 }
 
 template <typename T>
-static hipError_t apply_single_t(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up, int parts,
-                                 int F, const double* csr_val, int64_t nfar, const OpData<T>& od, int dtype,
-                                 const void* x, void* y, unsigned int* tickets, hipStream_t st, hipStream_t side,
-                                 hipEvent_t fork, hipEvent_t join, hipEvent_t* ev) {
-    const bool far = (parts & 8) != 0;
-    if (ev) hipEventRecord(ev[0], st);
-    hipStream_t fs = st;
-    if (far && side != st) {
-        hipEventRecord(fork, st);
-        hipStreamWaitEvent(side, fork, 0);
-        fs = side;
+static hipError_t apply_single_t(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up,
+                                 const FarPlan& fp, int parts, int F, const double* csr_val, const OpData<T>& od,
+                                 int dtype, const void* x, void* y, unsigned int* tickets, hipStream_t st,
+                                 hipEvent_t* ev) {
+    const bool far = (parts & 8) != 0 && fp.ntgt > 0;
+    if (ev) {
+        (void)hipEventRecord(ev[0], st);
+        (void)hipEventRecord(ev[1], st);
     }
-    if (far) FPDE_DISPATCH_DP(t.dim, t.p, Single<T>::template chain, a, t, up, F, nfar, dtype, x, od, tickets, fs);
-    if (ev) hipEventRecord(ev[1], fs);
-    hipError_t e = launch_near_panel(a, pp, od.panel, (parts & 4) != 0, csr_val, F, dtype, x, y, st,
-                                     ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+    FPDE_DISPATCH_DP(t.dim, t.p, Single<T>::template near_up, a, t, pp, up, far, (parts & 4) != 0, csr_val, F, dtype,
+                     x, y, od, tickets, st, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (far) {
-        if (fs != st) {
-            hipEventRecord(join, fs);
-            hipStreamWaitEvent(st, join, 0);
-        }
-        FPDE_DISPATCH_DP(t.dim, t.p, Single<T>::template out, a, t, F, od, dtype, y, st);
-    }
-    if (ev) hipEventRecord(ev[4], st);
+    if (far) FPDE_DISPATCH_DP(t.dim, t.p, Single<T>::template far_out, a, t, fp, F, od, dtype, y, st);
+    if (ev) (void)hipEventRecord(ev[4], st);
     return hipGetLastError();
 }
 
-hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up, int parts,
-                               int F, const double* csr_val, int64_t nfar, const OpData<double>& od, int dtype,
-                               const void* x, void* y, unsigned int* tickets, hipStream_t st, hipStream_t side,
-                               hipEvent_t fork, hipEvent_t join, hipEvent_t* ev) {
-    return apply_single_t<double>(a, t, pp, up, parts, F, csr_val, nfar, od, dtype, x, y, tickets, st, side, fork,
-                                  join, ev);
+hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up,
+                               const FarPlan& fp, int parts, int F, const double* csr_val, const OpData<double>& od,
+                               int dtype, const void* x, void* y, unsigned int* tickets, hipStream_t st,
+                               hipEvent_t* ev) {
+    return apply_single_t<double>(a, t, pp, up, fp, parts, F, csr_val, od, dtype, x, y, tickets, st, ev);
 }
 
-hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up, int parts,
-                               int F, const double* csr_val, int64_t nfar, const OpData<float>& od, int dtype,
-                               const void* x, void* y, unsigned int* tickets, hipStream_t st, hipStream_t side,
-                               hipEvent_t fork, hipEvent_t join, hipEvent_t* ev) {
-    return apply_single_t<float>(a, t, pp, up, parts, F, csr_val, nfar, od, dtype, x, y, tickets, st, side, fork,
-                                 join, ev);
+hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up,
+                               const FarPlan& fp, int parts, int F, const double* csr_val, const OpData<float>& od,
+                               int dtype, const void* x, void* y, unsigned int* tickets, hipStream_t st,
+                               hipEvent_t* ev) {
+    return apply_single_t<float>(a, t, pp, up, fp, parts, F, csr_val, od, dtype, x, y, tickets, st, ev);
 }
 
 }  // namespace fpde

@@ -153,11 +153,13 @@ struct fpde_op {
     int64_t *d_poff = nullptr, *d_pstride = nullptr, *d_pcols_ptr = nullptr;
     int32_t* d_pcols = nullptr;
     int64_t panel_max_stride = 0, panel_total = 0;
-    unsigned int* d_tickets = nullptr;     // [F][ncl] ticket counters of the one-launch upsweep (self-resetting)
+    unsigned int* d_tickets = nullptr;     // [F][ncl] ticket counters of the one-vector upsweep (self-resetting)
+    double* d_zh = nullptr;                // [F][ncl][k] coupling sums of the one-vector apply
     UpPlan up[2]{};                        // one-launch upsweep plan per precision (0 FP64, 1 FP32)
+    FarPlan far_plan{};                    // far targets of the one-vector output kernel
     struct {                               // FP32 operator data of a mixed-precision operator
         float *U = nullptr, *E = nullptr, *St = nullptr, *panel = nullptr;
-        float *xh = nullptr, *tmp = nullptr;   // workspace, one right-hand side
+        float *xh = nullptr, *zh = nullptr;    // workspace, one right-hand side
         float *xhR = nullptr, *yhR = nullptr;  // workspace [F][ncl][K][R]
     } f32;
     // captured apply graphs keyed by (parts, dtype, x, y, R)
@@ -897,8 +899,34 @@ void build_device(fpde_op& op) {
         int max_depth = kt.L;
         if (const char* env = std::getenv("FPDE_MAX_SUBTREE_DEPTH"))
             max_depth = std::max(0, std::min(max_depth, std::atoi(env)));
+        // heap id c sits on level floor(log2(c + 1))
+        auto level_of = [](int64_t c) {
+            int lev = 0;
+            while ((int64_t(2) << lev) - 1 <= c) ++lev;
+            return lev;
+        };
+        int lmin = kt.L;   // shallowest far source
+        for (auto& pr : op.kfar) lmin = std::min(lmin, level_of(pr.second));
+        {   // far targets in heap order; per leaf, the targets on its root path
+            std::vector<char> is_tgt(kt.ncl, 0);
+            for (auto& pr : op.kfar) is_tgt[pr.first] = 1;
+            std::vector<int64_t> tg;
+            int ltop = kt.L;
+            for (int64_t c = 0; c < kt.ncl; ++c)
+                if (is_tgt[c]) {
+                    tg.push_back(c);
+                    ltop = std::min(ltop, level_of(c));
+                }
+            op.far_plan.ntgt = (int64_t)tg.size();
+            op.far_plan.ltop = ltop;
+            op.far_plan.tgt = tg.empty() ? nullptr : A.upload(tg, st);
+            hipck(hipStreamSynchronize(st), "far plan upload");   // tg ends here
+            // z^ of the one-vector apply: only targets are ever written, the rest stays zero
+            op.d_zh = A.alloc<double>((int64_t)F * kt.ncl * k);
+            hipck(hipMemsetAsync(op.d_zh, 0, sizeof(double) * F * kt.ncl * k, st), "zh");
+        }
         for (int pr = 0; pr < 2; ++pr) {
-            UpPlan u = plan_up_tree(h, op.cap, pr);
+            UpPlan u = plan_up_tree(h, op.cap, lmin, pr);
             u.d0 = std::min(u.d0, max_depth);
             u.ds = std::max(1, std::min(u.ds, max_depth));
             op.up[pr] = u;
@@ -975,7 +1003,8 @@ void ensure_ws(fpde_op& op, int64_t R) {
     if (op.mixed) {   // FP32 workspace
         if (!op.f32.xh) {
             op.f32.xh = op.arena.alloc<float>((int64_t)op.F * op.kt.ncl * k);
-            op.f32.tmp = op.arena.alloc<float>((int64_t)op.F * std::max<size_t>(1, op.kfar.size()) * k);
+            op.f32.zh = op.arena.alloc<float>((int64_t)op.F * op.kt.ncl * k);
+            hipck(hipMemset(op.f32.zh, 0, sizeof(float) * op.F * op.kt.ncl * k), "zh");
         }
         if (op.f32.xhR) {
             op.arena.release(op.f32.xhR);
@@ -1027,13 +1056,13 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
     const PanelPlan pp{op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr, op.panel_max_stride, op.d_csr_col_dof};
     if (R == 1 && op.up[pr].ok && op.panel_max_stride * (int64_t)esz <= 64 * 1024) {
         if (f32) {
-            OpData<float> od{op.f32.U, op.f32.E, op.f32.St, op.f32.panel, op.f32.xh, op.f32.tmp};
-            return launch_apply_single(a, h, pp, op.up[1], parts, F, cv, nfar, od, dtype, x, y, op.d_tickets, s0, s1,
-                                       fk, jn, ev);
+            OpData<float> od{op.f32.U, op.f32.E, op.f32.St, op.f32.panel, op.f32.xh, op.f32.zh};
+            return launch_apply_single(a, h, pp, op.up[1], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets,
+                                       s0, ev);
         }
-        OpData<double> od{op.d_U, op.kdev.E, op.d_St, op.d_panel, op.d_xh, op.d_tmp};
-        return launch_apply_single(a, h, pp, op.up[0], parts, F, cv, nfar, od, dtype, x, y, op.d_tickets, s0, s1, fk,
-                                   jn, ev);
+        OpData<double> od{op.d_U, op.kdev.E, op.d_St, op.d_panel, op.d_xh, op.d_zh};
+        return launch_apply_single(a, h, pp, op.up[0], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets, s0,
+                                   ev);
     }
     // several right-hand sides: near panels as MFMA GEMMs and the far field as
     // batched products in the operator's precision (FP32 data for a mixed operator)
@@ -1507,7 +1536,7 @@ fpde_status fpde_profile(fpde_op* op, int32_t enable, fpde_profile_t* out) {
         fpde_profile_t acc{};
         for (auto& ev : op->prof_ev) {
             hipck(hipEventSynchronize(ev[4]), "event sync");
-            // ev0 start, ev1 end of the far chain, ev2/ev3 start/stop of the near-field kernel, ev4 end
+            // ev0 start, ev1 end of the far work before the near-field kernel, ev2/ev3 start/stop of that kernel, ev4 end
             float b = 0, c = 0, d = 0, e = 0;
             hipEventElapsedTime(&b, ev[0], ev[1]);
             hipEventElapsedTime(&c, ev[2], ev[3]);

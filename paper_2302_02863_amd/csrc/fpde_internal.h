@@ -192,25 +192,27 @@ struct OpData {
     const T* E;       // [ncl][D][P][P] transfers
     const T* St;      // [F][nfar][K][K] coupling matrices, transposed
     const T* panel;   // [F][panel_total]
-    T* xh;            // [F][ncl][K] workspace
-    T* tmp;           // [F][nfar][K] workspace
+    T* xh;            // [F][ncl][K] workspace: upsweep coefficients x^
+    T* zh;            // [F][ncl][K] coupling sums z^ per target cluster, zero for the others
 };
 // One-launch upsweep: leaf-stage subtree depth d0, upper-stage depth ds
 struct UpPlan {
     int d0, ds;
+    int lmin;          // shallowest level whose coefficients a far pair reads; the upsweep stops there
+    size_t path_lds;   // LDS of the output kernel's root-path walk (bytes, whole depth)
     bool ok;
 };
-UpPlan plan_up_tree(const H2Tree& t, int64_t cap, int prec /*0 double, 1 float*/);
+// Far targets of the single-vector output kernel
+struct FarPlan {
+    const int64_t* tgt;    // [ntgt] clusters with incoming far pairs, in heap order
+    int64_t ntgt;
+    int ltop;              // level of the shallowest target
+};
+UpPlan plan_up_tree(const H2Tree& t, int64_t cap, int lmin, int prec /*0 double, 1 float*/);
 hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const int64_t* near_ptr,
                               const int64_t* near_src, const int64_t* leaf_beg, const int64_t* pcol_off,
                               const int64_t* poff, const int64_t* pstride, const int64_t* pcols_ptr, const double* nb,
                               int F, double* panel, hipStream_t st);
-hipError_t launch_near_panel(const ApplyPlan& a, const PanelPlan& pp, const double* panel, int use_near,
-                             const double* csr_val, int F, int dtype, const void* x, void* y, hipStream_t st,
-                             hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_near_panel(const ApplyPlan& a, const PanelPlan& pp, const float* panel, int use_near,
-                             const double* csr_val, int F, int dtype, const void* x, void* y, hipStream_t st,
-                             hipEvent_t e0, hipEvent_t e1);
 // several right-hand sides: Y = Panel X (MFMA) + (B+M) X per (leaf, 64 rows, 64 rhs, field); x, y [F][N][R]
 hipError_t launch_near_mm(const ApplyPlan& a, const PanelPlan& pp, const double* panel, int use_near,
                           const double* csr_val, int F, int R, int dtype, const void* x, void* y, hipStream_t st,
@@ -218,16 +220,16 @@ hipError_t launch_near_mm(const ApplyPlan& a, const PanelPlan& pp, const double*
 hipError_t launch_near_mm(const ApplyPlan& a, const PanelPlan& pp, const float* panel, int use_near,
                           const double* csr_val, int F, int R, int dtype, const void* x, void* y, hipStream_t st,
                           hipEvent_t e0, hipEvent_t e1);
-// tickets: [F][ncl] zero-initialised counters (left at zero by every launch).
-// ev (optional, 5 events, side == st): start, far chain end, near kernel start/stop, end.
-hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up, int parts,
-                               int F, const double* csr_val, int64_t nfar, const OpData<double>& od, int dtype,
-                               const void* x, void* y, unsigned int* tickets, hipStream_t st, hipStream_t side,
-                               hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
-hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up, int parts,
-                               int F, const double* csr_val, int64_t nfar, const OpData<float>& od, int dtype,
-                               const void* x, void* y, unsigned int* tickets, hipStream_t st, hipStream_t side,
-                               hipEvent_t fork, hipEvent_t join, hipEvent_t* ev);
+// tickets: [F][ncl] zero-initialised counters of the upsweep (left at zero by every launch).
+// ev (optional, 5 events): start, start, near/upsweep kernel start/stop, end.
+hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up,
+                               const FarPlan& fp, int parts, int F, const double* csr_val, const OpData<double>& od,
+                               int dtype, const void* x, void* y, unsigned int* tickets, hipStream_t st,
+                               hipEvent_t* ev);
+hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up,
+                               const FarPlan& fp, int parts, int F, const double* csr_val, const OpData<float>& od,
+                               int dtype, const void* x, void* y, unsigned int* tickets, hipStream_t st,
+                               hipEvent_t* ev);
 
 // ---------------------------------------------------------------- apply, many right-hand sides (fpde_batched.hip)
 

@@ -1,7 +1,7 @@
 // Near field of the apply: dense near leaf blocks of K~ packed per target leaf
-// into row-major panels, streamed together with the CSR rows of B + M.
-// This is the HBM-bound kernel of the apply (one right-hand side).  Panels are
-// stored in FP64, and additionally in FP32 for a mixed-precision operator.
+// into row-major panels (FP64, and additionally FP32 for a mixed-precision
+// operator), and the MFMA near-field kernel for several right-hand sides.  The
+// one-vector near rows run inside the fused near/upsweep launch of the apply.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -47,106 +47,6 @@ hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const 
     hipLaunchKernelGGL(k_pack_panels, dim3((unsigned)nleaf, F), dim3(256), 0, st, nleaf, cap, npairs, near_ptr, near_src,
                        leaf_beg, pcol_off, poff, pstride, pcols_ptr, nb, F, panel);
     return hipGetLastError();
-}
-
-template <typename T>
-struct Vec2;
-template <>
-struct Vec2<double> {
-    using type = double2;
-};
-template <>
-struct Vec2<float> {
-    using type = float2;
-};
-
-// y[f][perm[row]] = (B+M)_row . x + panel_row . x[cols]; one block per (leaf,
-// 16-row block, field), 16 lanes per row, one right-hand side, x read from the
-// caller's vector through dof-indexed columns.  The leaf's panel columns of x
-// are staged in LDS (in the panel's precision) once per block; panel products
-// accumulate in T, the CSR row and the final sum in FP64.
-template <typename T>
-FPDE_KERNEL void k_near_panel(ApplyPlan a, PanelPlan pp, const T* panel, int use_near, const double* csr_val, int F,
-                              int dtype, const void* x, void* y) {
-    using V2 = typename Vec2<T>::type;
-    extern __shared__ __align__(16) unsigned char sraw[];
-    T* xs = (T*)sraw;
-    const int f = blockIdx.y;
-    const int64_t nrb = (a.cap + 15) / 16;
-    const int64_t li = blockIdx.x / nrb;
-    const int rb = (int)(blockIdx.x % nrb);
-    const int64_t xo = (int64_t)f * a.N;
-    const int64_t c0 = pp.pcols_ptr[li], ncols = pp.pcols_ptr[li + 1] - c0;
-    if (use_near)   // padding columns of the row stride hold 0 in the panel and in xs
-        for (int64_t c = threadIdx.x; c < pp.pstride[li]; c += blockDim.x)
-            xs[c] = c < ncols ? (T)ldx(x, xo + pp.pcols[c0 + c], dtype) : T(0);
-    __syncthreads();
-    const int g = threadIdx.x & 15;
-    const int64_t it = (int64_t)rb * 16 + (threadIdx.x >> 4);
-    const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
-    if (it >= nt) return;
-    const int64_t row = lb + it;
-    double acc = 0.0;
-    if (csr_val) {
-        const double* v = csr_val + (int64_t)f * a.nnz;
-        for (int64_t e = a.csr_ptr[row] + g; e < a.csr_ptr[row + 1]; e += 16)
-            acc += v[e] * ldx(x, xo + pp.csr_col_dof[e], dtype);
-    }
-    if (use_near) {
-        const int64_t ps = pp.pstride[li];
-        const T* pr = panel + (int64_t)f * pp.poff[a.nleaf] + pp.poff[li] + it * ps;
-        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        int64_t c = 2 * g;
-        // 4 vector loads per lane in flight
-        for (; c + 96 + 2 <= ps; c += 128) {
-            const V2 p0 = *(const V2*)(pr + c);
-            const V2 p1 = *(const V2*)(pr + c + 32);
-            const V2 p2 = *(const V2*)(pr + c + 64);
-            const V2 p3 = *(const V2*)(pr + c + 96);
-            a0 += p0.x * xs[c] + p0.y * xs[c + 1];
-            a1 += p1.x * xs[c + 32] + p1.y * xs[c + 33];
-            a2 += p2.x * xs[c + 64] + p2.y * xs[c + 65];
-            a3 += p3.x * xs[c + 96] + p3.y * xs[c + 97];
-        }
-        for (; c + 2 <= ps; c += 32) {
-            const V2 p0 = *(const V2*)(pr + c);
-            a0 += p0.x * xs[c] + p0.y * xs[c + 1];
-        }
-        acc += (double)((a0 + a1) + (a2 + a3));
-    }
-    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-    if (g == 0) {
-        const int64_t dst = xo + a.perm[row];
-        if (dtype == 0) ((double*)y)[dst] = acc;
-        else ((float*)y)[dst] = (float)acc;
-    }
-}
-
-template <typename T>
-static hipError_t near_panel_t(const ApplyPlan& a, const PanelPlan& pp, const T* panel, int use_near,
-                               const double* csr_val, int F, int dtype, const void* x, void* y, hipStream_t st,
-                               hipEvent_t e0, hipEvent_t e1) {
-    const int64_t nrb = (a.cap + 15) / 16;
-    const size_t lds = sizeof(T) * (pp.max_stride > 0 ? pp.max_stride : 1);
-    const dim3 grid((unsigned)(a.nleaf * nrb), F);
-    if (e0)   // start/stop timestamps of exactly this kernel
-        hipExtLaunchKernelGGL(k_near_panel<T>, grid, dim3(256), lds, st, e0, e1, 0, a, pp, panel, use_near, csr_val, F,
-                              dtype, x, y);
-    else
-        hipLaunchKernelGGL(k_near_panel<T>, grid, dim3(256), lds, st, a, pp, panel, use_near, csr_val, F, dtype, x, y);
-    return hipGetLastError();
-}
-
-hipError_t launch_near_panel(const ApplyPlan& a, const PanelPlan& pp, const double* panel, int use_near,
-                             const double* csr_val, int F, int dtype, const void* x, void* y, hipStream_t st,
-                             hipEvent_t e0, hipEvent_t e1) {
-    return near_panel_t<double>(a, pp, panel, use_near, csr_val, F, dtype, x, y, st, e0, e1);
-}
-
-hipError_t launch_near_panel(const ApplyPlan& a, const PanelPlan& pp, const float* panel, int use_near,
-                             const double* csr_val, int F, int dtype, const void* x, void* y, hipStream_t st,
-                             hipEvent_t e0, hipEvent_t e1) {
-    return near_panel_t<float>(a, pp, panel, use_near, csr_val, F, dtype, x, y, st, e0, e1);
 }
 
 // ------------------------------------------------------------ several right-hand sides: MFMA panels
