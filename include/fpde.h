@@ -148,7 +148,11 @@ fpde_status fpde_build(const fpde_mesh *mesh, int32_t n_fields, const double *s,
 /* y = A x for F fields and nrhs right-hand sides (Sec. 3: y = (B+M)x + K~x).
  *   dtype     FPDE_F64: x, y are double; FPDE_F32: float
  *   x, y      device [F][N][nrhs], must not alias
- * Asynchronous on hip_stream.  Errors: FPDE_EINVAL, FPDE_ESTATE, FPDE_EDEVICE. */
+ * Asynchronous on hip_stream: kernel launches on that stream (with several
+ * right-hand sides the far field runs on the operator's side stream, forked
+ * from and joined back to hip_stream with events).  Calls on one operator
+ * must not run concurrently from several host threads.
+ * Errors: FPDE_EINVAL, FPDE_ESTATE, FPDE_EDEVICE. */
 fpde_status fpde_apply(fpde_op *op, int32_t dtype, const void *x, void *y, int64_t nrhs,
                        void *hip_stream);
 
@@ -203,7 +207,7 @@ fpde_status fpde_apply_adjoint(fpde_op *op, const double *w, const double *u, in
                                double *grad_s, double *grad_kappa, void *hip_stream);
 
 /* Device-time profile of fpde_apply.  While profiling is on, each apply runs
- * the same kernels as its captured graph, serialised on the apply's stream,
+ * the same kernels as without profiling, serialised on the apply's stream,
  * with HIP events: out = start-to-stop timestamps of the near-field kernel
  * (the dominant kernel, launched with hipExtLaunchKernelGGL events: CSR +
  * near leaf blocks, and for one right-hand side the far-field upsweep in the

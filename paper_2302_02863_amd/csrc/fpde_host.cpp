@@ -162,8 +162,6 @@ struct fpde_op {
         float *xh = nullptr, *zh = nullptr;    // workspace, one right-hand side
         float *xhR = nullptr, *yhR = nullptr;  // workspace [F][ncl][K][R]
     } f32;
-    // captured apply graphs keyed by (parts, dtype, x, y, R)
-    std::map<std::tuple<int, int, const void*, void*, int64_t>, hipGraphExec_t> graphs;
     bool mixed = false;                    // built with FPDE_PREC_MIXED
     // apply workspace
     int64_t ws_R = 0;
@@ -991,8 +989,6 @@ void ensure_ws(fpde_op& op, int64_t R) {
     const int d = op.mesh.dim, p = op.opts.cheb_p, k = d == 2 ? p * p : p;
     if (op.d_xt) {
         op.arena.release(op.d_xt); op.arena.release(op.d_xh); op.arena.release(op.d_yh); op.arena.release(op.d_tmp);
-        for (auto& kv : op.graphs) hipGraphExecDestroy(kv.second);
-        op.graphs.clear();
         for (auto& kv : op.cg_graphs) hipGraphExecDestroy(kv.second);
         op.cg_graphs.clear();
     }
@@ -1090,33 +1086,16 @@ void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64
     if (dtype != FPDE_F64 && dtype != FPDE_F32) fail(FPDE_EINVAL, "dtype must be FPDE_F64 or FPDE_F32");
     if (R < 1 || !x || !y) fail(FPDE_EINVAL, "bad vectors");
     ensure_ws(op, R);
-    if (op.profiling) {   // same kernels as the graph, serialised, with events between the phases
+    if (op.profiling) {   // the same kernels, serialised on st, with events between the phases
         std::array<hipEvent_t, 5> ev{};
         for (auto& e : ev) hipck(hipEventCreate(&e), "event");
         hipck(enqueue_apply(op, parts, dtype, x, y, R, st, st, nullptr, nullptr, ev.data()), "apply");
         op.prof_ev.push_back(ev);
         return;
     }
-    auto key = std::make_tuple(parts, dtype, x, y, R);
-    auto it = op.graphs.find(key);
-    if (it == op.graphs.end()) {
-        hipStream_t cs = op.stream;
-        hipGraph_t g = nullptr;
-        hipck(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
-        hipError_t le = enqueue_apply(op, parts, dtype, x, y, R, cs, op.stream2, op.ev_fork, op.ev_join, nullptr);
-        hipError_t ce = hipStreamEndCapture(cs, &g);
-        hipck(le, "apply launch");
-        hipck(ce, "end capture");
-        hipGraphExec_t ex = nullptr;
-        hipck(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate");
-        hipGraphDestroy(g);
-        if (op.graphs.size() > 64) {
-            for (auto& kv : op.graphs) hipGraphExecDestroy(kv.second);
-            op.graphs.clear();
-        }
-        it = op.graphs.emplace(key, ex).first;
-    }
-    hipck(hipGraphLaunch(it->second, st), "graph launch");
+    // launched directly: on this runtime a graph launch costs more host time
+    // than the apply's three kernel launches and leaves gaps between them
+    hipck(enqueue_apply(op, parts, dtype, x, y, R, st, op.stream2, op.ev_fork, op.ev_join, nullptr), "apply launch");
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -1651,8 +1630,6 @@ fpde_status fpde_export(const fpde_op* op, int32_t what, int32_t field, void* ds
 
 void fpde_destroy(fpde_op* op) {
     if (!op) return;
-    for (auto& kv : op->graphs) hipGraphExecDestroy(kv.second);
-    op->graphs.clear();
     for (auto& kv : op->cg_graphs) hipGraphExecDestroy(kv.second);
     op->cg_graphs.clear();
     if (op->h_nact) hipHostFree(op->h_nact);

@@ -73,16 +73,25 @@ class Operator:
         import torch
         if x.dim() == 2:
             x = x.unsqueeze(-1)
-        if tuple(x.shape[:2]) != (self.n_fields, self.n_dofs) or not x.is_cuda:
+        if x.shape[0] != self.n_fields or x.shape[1] != self.n_dofs or not x.is_cuda:
             raise ValueError(f"x must be a device tensor [F={self.n_fields}, N={self.n_dofs}, R]")
-        x = x.contiguous()
+        if not x.is_contiguous():
+            x = x.contiguous()
         if y is None:
             y = torch.empty_like(x)
-        dtype = _abi.F64 if x.dtype == torch.float64 else _abi.F32
-        if x.dtype not in (torch.float64, torch.float32) or y.dtype != x.dtype or y.shape != x.shape:
-            raise ValueError("x, y must share shape and dtype float64/float32")
-        check(lib().fpde_apply_parts(self._h, parts, dtype, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
-                                     x.shape[2], _stream_handle(stream)), "fpde_apply")
+        elif y.dtype != x.dtype or y.shape != x.shape or not y.is_contiguous():
+            raise ValueError("y must be a contiguous tensor with the shape and dtype of x")
+        if x.dtype is torch.float64:
+            dtype = _abi.F64
+        elif x.dtype is torch.float32:
+            dtype = _abi.F32
+        else:
+            raise ValueError("x must be float64 or float32")
+        st = lib().fpde_apply_parts(self._h, parts, dtype, x.data_ptr(), y.data_ptr(), x.shape[2],
+                                    torch.cuda.current_stream().cuda_stream if stream is None
+                                    else (stream if isinstance(stream, int) else stream.cuda_stream))
+        if st:
+            check(st, "fpde_apply")
         return y
 
     def load_vector(self, f_nodal, stream=None):
