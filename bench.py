@@ -65,8 +65,8 @@ def measured_traffic(kernel_name):
     """HBM traffic of the dominant kernel from the committed rocprofv3 counter record,
     valid only while the kernel source is unchanged (else None)."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "traffic_k_near_panel_square128.json")
-    src = os.path.join(ROOT, "paper_2302_02863_amd", "csrc", "fpde_near.hip")
+    rec_path = os.path.join(ROOT, "profiles", "traffic_%s_square128.json" % kernel_name)
+    src = os.path.join(ROOT, "paper_2302_02863_amd", "csrc", "fpde_apply.hip")
     try:
         rec = json.load(open(rec_path))
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()

@@ -28,6 +28,7 @@ SOURCES = [
     ("fpde_kernels.hip", HIP_FLAGS),
     ("fpde_near.hip", HIP_FLAGS),
     ("fpde_apply.hip", HIP_FLAGS),
+    ("fpde_far1.hip", HIP_FLAGS),
     ("fpde_multi.hip", HIP_FLAGS),
     ("fpde_batched.hip", HIP_FLAGS),
     ("fpde_solve.hip", HIP_FLAGS),

@@ -4,20 +4,23 @@
 // matrices are FP32 and their products accumulate in FP32).
 //
 // One apply is three launches on one stream:
-//   k_near_up    blocks [0, nup): the upsweep (leaf coefficients, then the
-//                nested transfers up to the shallowest level a far pair reads);
+//   k_near_up    blocks [0, nup): the upsweep, whole subtrees of depth d0 per
+//                block (leaf coefficients, then the nested transfers);
 //                blocks [nup, ...): the near rows (CSR row of B + M and the
-//                packed near panel row).  The subtree roots that one upsweep
-//                block hands to another are stored and loaded as agent-scope
-//                atomics, which bypass the per-XCD L2 copies; every wave waits
-//                for its stores to be acknowledged before the block's barrier
-//                and its one ticket increment, so no cache writeback or
-//                invalidate is needed, and no block ever waits for another
-//                (the last arrival goes on), so the launch always drains.
-//   k_couple     z^(c) = sum over the far pairs (c, s) of S x^(s), one block
-//                per far target cluster.
-//   k_far_out    per leaf: the walk down its root path (y^ of a child is its
-//                z^ plus the transfer of its parent's y^), U y^ added to y.
+//                packed near panel row).  The far list of this path has its
+//                sources moved down to the subtree levels at build (coupling
+//                matrices S M_r^T), so on the usual trees no block reads
+//                another's coefficients.  On deeper trees the levels still
+//                above the subtree roots are chained by tickets: the subtree
+//                roots one block hands to another are stored and loaded as
+//                agent-scope atomics, which bypass the per-XCD L2 copies;
+//                every wave waits for its stores to be acknowledged before the
+//                block's barrier and its one ticket increment, so no cache
+//                writeback or invalidate is needed, and no block ever waits
+//                for another (the last arrival goes on), so the launch always
+//                drains.
+//   k_couple, k_far_out (fpde_far1.hip): coupling sums per far target, then
+//                the downsweep walk fused with the output.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -201,41 +204,6 @@ __device__ __forceinline__ void up_tree(const ApplyPlan& a, const H2Tree& t, con
     }
 }
 
-// Coupling of far target cluster c (Sec. 5.2): z^(c) = sum over the far pairs
-// (c, s) of S x^(s).  Pair slots of G lanes (lane alpha) each take every NS-th
-// pair of c and accumulate S[alpha][beta] x^(s)[beta]; St holds S transposed
-// ([beta][alpha]) so that the lanes read consecutive entries, and x^(s)[beta]
-// is broadcast from lane beta of the slot.  The slots are summed in a fixed
-// order.  z^ of clusters that are not targets stays zero.
-template <int D, int P, typename T>
-__device__ __forceinline__ void couple(const H2Tree& t, int64_t c, int f, const T* St, const T* xh, T* zh, T* sred) {
-    constexpr int K = KR<D, P>::K;
-    constexpr int G = K <= 32 ? 32 : 64;   // lanes of a pair slot
-    constexpr int NS = kApplyThreads / G;  // pair slots
-    const int64_t nfar = t.far_ptr[t.ncl];
-    const int64_t e0 = t.far_ptr[c], e1 = t.far_ptr[c + 1];
-    const int sl = threadIdx.x / G, al = threadIdx.x % G;
-    const int base = (threadIdx.x & 63) & ~(G - 1);   // first lane of the slot within the wave
-    const T* xf = xh + (int64_t)f * t.ncl * K;
-    T acc = 0;
-    for (int64_t e = e0 + sl; e < e1; e += NS) {   // the lanes of a slot share e
-        const T* S = St + ((int64_t)f * nfar + e) * K * K + (al < K ? al : 0);
-        T sv[K];
-#pragma unroll
-        for (int b = 0; b < K; ++b) sv[b] = S[b * K];
-        const T xv = al < K ? xf[t.far_src[e] * K + al] : T(0);
-#pragma unroll
-        for (int b = 0; b < K; ++b) acc += sv[b] * __shfl(xv, base + b, 64);
-    }
-    sred[sl * G + al] = acc;
-    __syncthreads();
-    if (threadIdx.x < K) {
-        T z = 0;
-        for (int s = 0; s < NS; ++s) z += sred[s * G + threadIdx.x];
-        zh[((int64_t)f * t.ncl + c) * K + threadIdx.x] = z;
-    }
-}
-
 // Near rows: y[f][perm[row]] = (B+M)_row . x + panel_row . x_near for the 16
 // rows of block rb of leaf li, 16 lanes per row.  The x entries of the leaf's
 // near columns are staged in LDS once per block.  Each lane keeps 8 vector
@@ -316,72 +284,6 @@ __global__ __launch_bounds__(kApplyThreads) void k_near_up(ApplyPlan a, H2Tree t
         near_rows<T>(a, pp, panel, use_near, csr_val, dtype, x, y, f, (int64_t)blockIdx.x - nup, (T*)sraw);
 }
 
-// One block per far target cluster tgt[b].
-template <int D, int P, typename T>
-__global__ __launch_bounds__(kApplyThreads) void k_couple(H2Tree t, FarPlan fp, const T* St, const T* xh, T* zh) {
-    __shared__ T sred[kApplyThreads];
-    couple<D, P, T>(t, fp.tgt[blockIdx.x], blockIdx.y, St, xh, zh, sred);
-}
-
-// Downsweep and output (Sec. 5.3): y[perm[row]] += U[row] . y^_leaf, where
-// y^ of a cluster is its z^ plus the transfer of its parent's y^, from level
-// ltop (the shallowest target) down.  One block per (leaf, 64 rows, field),
-// 4 lanes per row; the basis rows, output indices, old y values, transfers
-// and z^ of the root path are all fetched before the walk.
-template <int D, int P, typename T>
-__global__ __launch_bounds__(kApplyThreads) void k_far_out(ApplyPlan a, H2Tree t, int ltop, const T* zh, const T* U,
-                                                           const T* E, int dtype, void* y) {
-    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
-    extern __shared__ __align__(16) unsigned char sraw[];
-    const int L = t.L, nlev = L + 1 - ltop;
-    T* sy = (T*)sraw;                       // [nlev][K]
-    T* sE = sy + (int64_t)nlev * K;         // [nlev][EP]
-    const int f = blockIdx.y;
-    const int64_t nrb = (a.cap + 63) / 64;
-    const int64_t li = blockIdx.x / nrb;
-    const int rb = (int)(blockIdx.x % nrb);
-    const int64_t leafc = t.first_leaf + li;
-    const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
-    const int g = threadIdx.x & 3;
-    const int64_t it = (int64_t)rb * 64 + (threadIdx.x >> 2);
-    const bool ok = it < nt;
-    T u[(K + 3) / 4];
-#pragma unroll
-    for (int q = 0; q < (K + 3) / 4; ++q) u[q] = (ok && 4 * q + g < K) ? U[(lb + it) * K + 4 * q + g] : T(0);
-    int64_t dst = 0;
-    double yold = 0.0;
-    if (ok && g == 0) {
-        dst = (int64_t)f * a.N + a.perm[lb + it];
-        yold = ldx(y, dst, dtype);
-    }
-    const T* zf = zh + (int64_t)f * t.ncl * K;
-    for (int i = threadIdx.x; i < nlev * K; i += blockDim.x) {
-        const int lev = ltop + i / K;
-        sy[i] = zf[(((leafc + 1) >> (L - lev)) - 1) * K + i % K];
-    }
-    for (int i = threadIdx.x; i < nlev * EP; i += blockDim.x) {
-        const int lev = ltop + i / EP;
-        sE[i] = E[(((leafc + 1) >> (L - lev)) - 1) * EP + i % EP];
-    }
-    __syncthreads();
-    for (int l = 1; l < nlev; ++l) {
-        for (int i = threadIdx.x; i < K; i += blockDim.x)
-            sy[l * K + i] += down_t<D, P, T>(sE + l * EP, sy + (l - 1) * K, i, 1);
-        __syncthreads();
-    }
-    const T* cur = sy + (int64_t)(nlev - 1) * K;
-    T acc = 0;
-#pragma unroll
-    for (int q = 0; q < (K + 3) / 4; ++q)
-        if (4 * q + g < K) acc += u[q] * cur[4 * q + g];
-    acc += __shfl_xor(acc, 1, 4);
-    acc += __shfl_xor(acc, 2, 4);
-    if (ok && g == 0) {
-        if (dtype == 0) ((double*)y)[dst] = yold + (double)acc;
-        else ((float*)y)[dst] = (float)(yold + (double)acc);
-    }
-}
-
 template <int D, int P, typename T>
 static size_t up_tree_lds(int64_t cap, int d0, int ds) {
     constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
@@ -389,13 +291,6 @@ static size_t up_tree_lds(int64_t cap, int d0, int ds) {
     const int64_t s0 = ((int64_t(2) << d0) - 1) * (K + EP) + waves * (K + cap);
     const int64_t s1 = ((int64_t(2) << ds) - 1) * (K + EP);
     return sizeof(T) * (size_t)(s0 > s1 ? s0 : s1);
-}
-
-// far-field part of a near block: y^ and transfers of the root path from ltop
-template <int D, int P, typename T>
-static size_t path_lds(const H2Tree& t, int ltop) {
-    constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
-    return sizeof(T) * (size_t)((int64_t)(t.L + 1 - ltop) * (K + EP));
 }
 
 // (dim, points) dispatch of the templates above for one operator precision T
@@ -420,16 +315,6 @@ struct Single {
             hipLaunchKernelGGL((k_near_up<D, P, T>), grid, dim3(kApplyThreads), lds, st, a, t, pp, up, nup, od.panel,
                                use_near, csr_val, dtype, x, y, od.U, od.E, od.xh, tickets);
     }
-    template <int D, int P>
-    static void far_out(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<T>& od, int dtype,
-                        void* y, hipStream_t st) {
-        hipLaunchKernelGGL((k_couple<D, P, T>), dim3((unsigned)fp.ntgt, F), dim3(kApplyThreads), 0, st, t, fp, od.St,
-                           od.xh, od.zh);
-        const int64_t nrb = (a.cap + 63) / 64;
-        const size_t lds = path_lds<D, P, T>(t, fp.ltop);
-        hipLaunchKernelGGL((k_far_out<D, P, T>), dim3((unsigned)(a.nleaf * nrb), F), dim3(kApplyThreads), lds, st, a,
-                           t, fp.ltop, od.zh, od.U, od.E, dtype, y);
-    }
     // leaf-stage depth d0 (1: two leaves, two waves each; at most 2, one leaf
     // per wave) and the upper-stage depth ds: the levels above the stage-0
     // roots up to lmin in one stage if they fit 64 KB of LDS
@@ -442,7 +327,7 @@ struct Single {
         const int need = t.L - up->d0 - lmin > 1 ? t.L - up->d0 - lmin : 1;
         up->ds = 1;
         while (up->ds < need && up_tree_lds<D, P, T>(cap, up->d0, up->ds + 1) <= lim) ++up->ds;
-        up->path_lds = path_lds<D, P, T>(t, 0);
+        up->path_lds = sizeof(T) * (size_t)((int64_t)(t.L + 1) * (KR<D, P>::K + KR<D, P>::EP));
         up->ok = up_tree_lds<D, P, T>(cap, up->d0, up->ds) <= lim && up->path_lds <= lim &&
                  KR<D, P>::K <= 64 && cap <= 256;
     }
@@ -469,7 +354,10 @@ static hipError_t apply_single_t(const ApplyPlan& a, const H2Tree& t, const Pane
                      x, y, od, tickets, st, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (far) FPDE_DISPATCH_DP(t.dim, t.p, Single<T>::template far_out, a, t, fp, F, od, dtype, y, st);
+    if (far) {
+        e = launch_far_single(a, t, fp, F, od, dtype, y, st);
+        if (e != hipSuccess) return e;
+    }
     if (ev) (void)hipEventRecord(ev[4], st);
     return hipGetLastError();
 }

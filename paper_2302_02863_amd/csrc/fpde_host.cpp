@@ -155,10 +155,14 @@ struct fpde_op {
     int64_t panel_max_stride = 0, panel_total = 0;
     unsigned int* d_tickets = nullptr;     // [F][ncl] ticket counters of the one-vector upsweep (self-resetting)
     double* d_zh = nullptr;                // [F][ncl][k] coupling sums of the one-vector apply
+    // far list of the one-vector apply, sources moved down to the upsweep's subtree levels
+    int64_t nfar1 = 0;
+    int64_t *d_far1_ptr = nullptr, *d_far1_src = nullptr;
+    double* d_St1 = nullptr;               // [F][nfar1][k][k], transposed like d_St
     UpPlan up[2]{};                        // one-launch upsweep plan per precision (0 FP64, 1 FP32)
     FarPlan far_plan{};                    // far targets of the one-vector output kernel
     struct {                               // FP32 operator data of a mixed-precision operator
-        float *U = nullptr, *E = nullptr, *St = nullptr, *panel = nullptr;
+        float *U = nullptr, *E = nullptr, *St = nullptr, *St1 = nullptr, *panel = nullptr;
         float *xh = nullptr, *zh = nullptr;    // workspace, one right-hand side
         float *xhR = nullptr, *yhR = nullptr;  // workspace [F][ncl][K][R]
     } f32;
@@ -923,11 +927,50 @@ void build_device(fpde_op& op) {
             op.d_zh = A.alloc<double>((int64_t)F * kt.ncl * k);
             hipck(hipMemsetAsync(op.d_zh, 0, sizeof(double) * F * kt.ncl * k, st), "zh");
         }
-        for (int pr = 0; pr < 2; ++pr) {
-            UpPlan u = plan_up_tree(h, op.cap, lmin, pr);
-            u.d0 = std::min(u.d0, max_depth);
-            u.ds = std::max(1, std::min(u.ds, max_depth));
-            op.up[pr] = u;
+        {   // far list of the one-vector apply: its upsweep computes whole subtrees of
+            // depth d0 per block, down from level lr = L - d0, without any exchange
+            // between blocks.  A far source above lr moves down at most kMoveDown
+            // levels to its descendants (coupling matrices S M_r^T, built on the
+            // device); the ticket chain of the upsweep covers what is left above.
+            constexpr int kMoveDown = 3;
+            const int d0 = std::min(plan_up_tree(h, op.cap, lmin, 0).d0, max_depth);
+            const int lr = kt.L - d0;
+            const int64_t nfar = (int64_t)op.kfar.size();
+            std::vector<int64_t> orig1, src1, fptr1(kt.ncl + 1, 0);
+            std::vector<int32_t> dep1;
+            int lstar = lr;   // the upsweep chain reaches this level
+            for (int64_t e = 0; e < nfar; ++e) {
+                const int64_t s = op.kfar[e].second;
+                const int ls = level_of(s);
+                const int lt = ls >= lr ? ls : std::min(lr, ls + kMoveDown);
+                const int dd = lt - ls;
+                lstar = std::min(lstar, lt);
+                const int64_t first = ((s + 1) << dd) - 1;
+                for (int64_t q = 0; q < (int64_t(1) << dd); ++q) {
+                    orig1.push_back(e);
+                    src1.push_back(first + q);
+                    dep1.push_back(dd);
+                }
+                fptr1[op.kfar[e].first + 1] += int64_t(1) << dd;
+            }
+            for (int64_t c = 0; c < kt.ncl; ++c) fptr1[c + 1] += fptr1[c];
+            op.nfar1 = (int64_t)src1.size();
+            op.d_far1_ptr = A.upload(fptr1, st);
+            op.d_far1_src = A.upload(src1, st);
+            int64_t* d_orig = A.upload(orig1, st);
+            int32_t* d_dep = A.upload(dep1, st);
+            op.d_St1 = A.alloc<double>((int64_t)F * op.nfar1 * k * k);
+            hipck(launch_expand_coupling(h, op.nfar1, d_orig, op.d_far1_src, d_dep, F, nfar, op.d_St, op.d_St1, st),
+                  "moved-down coupling");
+            hipck(hipStreamSynchronize(st), "moved-down coupling sync");
+            A.release(d_orig);
+            A.release(d_dep);
+            for (int pr = 0; pr < 2; ++pr) {
+                UpPlan u = plan_up_tree(h, op.cap, lstar, pr);
+                u.d0 = d0;
+                u.ds = std::max(1, std::min(u.ds, max_depth));
+                op.up[pr] = u;
+            }
         }
         op.ls2 = kt.L;
         while (op.ls2 > 0 && !multi_fits(h, op.ls2, 1)) --op.ls2;
@@ -938,10 +981,13 @@ void build_device(fpde_op& op) {
             op.f32.U = A.alloc<float>(nU);
             op.f32.E = A.alloc<float>(nE);
             op.f32.St = A.alloc<float>(nS);
+            op.f32.St1 = A.alloc<float>((int64_t)F * op.nfar1 * k * k);
             op.f32.panel = A.alloc<float>((int64_t)F * op.panel_total);
             hipck(launch_to_float(nU, op.d_U, op.f32.U, st), "to float");
             hipck(launch_to_float(nE, op.kdev.E, op.f32.E, st), "to float");
             if (nS > 0) hipck(launch_to_float(nS, op.d_St, op.f32.St, st), "to float");
+            if (op.nfar1 > 0)
+                hipck(launch_to_float((int64_t)F * op.nfar1 * k * k, op.d_St1, op.f32.St1, st), "to float");
             hipck(launch_to_float((int64_t)F * op.panel_total, op.d_panel, op.f32.panel, st), "to float");
         }
         hipck(hipStreamSynchronize(st), "tickets sync");
@@ -1051,13 +1097,16 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
     const size_t esz = f32 ? sizeof(float) : sizeof(double);
     const PanelPlan pp{op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr, op.panel_max_stride, op.d_csr_col_dof};
     if (R == 1 && op.up[pr].ok && op.panel_max_stride * (int64_t)esz <= 64 * 1024) {
+        H2Tree h1 = h;   // the far list with sources moved down
+        h1.far_ptr = op.d_far1_ptr;
+        h1.far_src = op.d_far1_src;
         if (f32) {
-            OpData<float> od{op.f32.U, op.f32.E, op.f32.St, op.f32.panel, op.f32.xh, op.f32.zh};
-            return launch_apply_single(a, h, pp, op.up[1], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets,
+            OpData<float> od{op.f32.U, op.f32.E, op.f32.St1, op.f32.panel, op.f32.xh, op.f32.zh};
+            return launch_apply_single(a, h1, pp, op.up[1], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets,
                                        s0, ev);
         }
-        OpData<double> od{op.d_U, op.kdev.E, op.d_St, op.d_panel, op.d_xh, op.d_zh};
-        return launch_apply_single(a, h, pp, op.up[0], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets, s0,
+        OpData<double> od{op.d_U, op.kdev.E, op.d_St1, op.d_panel, op.d_xh, op.d_zh};
+        return launch_apply_single(a, h1, pp, op.up[0], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets, s0,
                                    ev);
     }
     // several right-hand sides: near panels as MFMA GEMMs and the far field as

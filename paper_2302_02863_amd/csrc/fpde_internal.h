@@ -150,6 +150,11 @@ hipError_t launch_leaf_out(const ApplyPlan& a, const H2Tree& t, int parts, int F
 
 hipError_t launch_coupling_store(const H2Tree& t, int64_t nfar, const int64_t* far_tgt, int F, double fac,
                                  double a_scale, double* St, hipStream_t st);
+// St1[f][j] = S_orig[j] M_r^T for the far list with sources moved down to src1[j]
+// (depth[j] levels below the original source; St layout [f][pair][beta][alpha])
+hipError_t launch_expand_coupling(const H2Tree& t, int64_t n1, const int64_t* orig, const int64_t* src1,
+                                  const int32_t* depth, int F, int64_t nfar, const double* St, double* St1,
+                                  hipStream_t st);
 // yh[f][c] = sum_{e in far(c)} S_e xh[f][src(e)]  (per-level fallback)
 hipError_t launch_coupling_apply(const H2Tree& t, int F, int R, const double* St, const double* xh, double* yh,
                                  hipStream_t st);
@@ -230,6 +235,14 @@ hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelP
                                const FarPlan& fp, int parts, int F, const double* csr_val, const OpData<float>& od,
                                int dtype, const void* x, void* y, unsigned int* tickets, hipStream_t st,
                                hipEvent_t* ev);
+
+// far field of the one-vector apply after its upsweep (fpde_far1.hip): coupling
+// sums z^ per far target (od.St, od.xh -> od.zh), then the downsweep walk and
+// U y^ added to y
+hipError_t launch_far_single(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<double>& od,
+                             int dtype, void* y, hipStream_t st);
+hipError_t launch_far_single(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<float>& od,
+                             int dtype, void* y, hipStream_t st);
 
 // ---------------------------------------------------------------- apply, many right-hand sides (fpde_batched.hip)
 

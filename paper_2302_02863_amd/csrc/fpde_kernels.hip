@@ -1246,6 +1246,69 @@ hipError_t launch_coupling_store(const H2Tree& t, int64_t nfar, const int64_t* f
     return hipGetLastError();
 }
 
+// Coupling matrices of far pairs whose source is moved down the tree (nested
+// bases, Sec. 5.3).  x^(s) = sum over the descendants r of s at a deeper
+// level of M_r^T x^(r), M_r = E_r E_parent(r) ... (the child-to-parent
+// transfers from r up to the child of s; per dimension, Kronecker), so
+// S x^(s) = sum_r (S M_r^T) x^(r).  Entry j of the new list takes pair orig[j]
+// with source r = src1[j], dd = depth[j] levels below the original source:
+//   St1[f][j][delta][alpha] = sum_beta S[alpha][beta] M_r[delta][beta]
+// (transposed like St; M_r = I for dd = 0).
+FPDE_KERNEL void k_expand_coupling(H2Tree t, int64_t n1, const int64_t* orig, const int64_t* src1,
+                                   const int32_t* depth, int F, int64_t nfar, const double* St, double* St1) {
+    const int k = t.k, p = t.p, dim = t.dim;
+    const int64_t kk = (int64_t)k * k;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)F * n1 * kk) return;
+    const int f = (int)(i / (n1 * kk));
+    int64_t rem = i - (int64_t)f * n1 * kk;
+    const int64_t j = rem / kk;
+    rem %= kk;
+    const int delta = (int)(rem / k), alpha = (int)(rem % k);
+    const int64_t e = orig[j];
+    const double* S = St + ((int64_t)f * nfar + e) * kk;   // S[beta * k + alpha] = S_e[alpha][beta]
+    const int dd = depth[j];
+    if (dd == 0) {
+        St1[i] = S[(int64_t)delta * k + alpha];
+        return;
+    }
+    // row delta_d of the per-dimension chain E_r E_parent(r) ... (dd factors)
+    double v[2][8];
+    int64_t c = src1[j];
+    for (int d = 0; d < dim; ++d) {
+        const int dl = d == 0 ? delta % p : delta / p;
+        for (int a = 0; a < p; ++a) v[d][a] = t.E[(c * dim + d) * p * p + dl * p + a];
+    }
+    for (int s = 1; s < dd; ++s) {
+        c = (c - 1) / 2;
+        for (int d = 0; d < dim; ++d) {
+            double w[8];
+            for (int a2 = 0; a2 < p; ++a2) {
+                double acc = 0.0;
+                for (int a = 0; a < p; ++a) acc += v[d][a] * t.E[(c * dim + d) * p * p + a * p + a2];
+                w[a2] = acc;
+            }
+            for (int a2 = 0; a2 < p; ++a2) v[d][a2] = w[a2];
+        }
+    }
+    double acc = 0.0;
+    for (int beta = 0; beta < k; ++beta) {
+        const double m = dim == 2 ? v[0][beta % p] * v[1][beta / p] : v[0][beta];
+        acc += S[(int64_t)beta * k + alpha] * m;
+    }
+    St1[i] = acc;
+}
+
+hipError_t launch_expand_coupling(const H2Tree& t, int64_t n1, const int64_t* orig, const int64_t* src1,
+                                  const int32_t* depth, int F, int64_t nfar, const double* St, double* St1,
+                                  hipStream_t st) {
+    const int64_t n = (int64_t)F * n1 * t.k * t.k;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand_coupling, dim3(grid1(n)), dim3(256), 0, st, t, n1, orig, src1, depth, F, nfar, St,
+                       St1);
+    return hipGetLastError();
+}
+
 // yh[f][c][alpha][r] = sum_{e in far(c)} sum_beta St[f][e][beta][alpha] xh[f][src(e)][beta][r]
 // one block per (cluster, field); threads = (alpha lane in 0..63) x (4 pair groups), k <= 64
 FPDE_KERNEL void k_coupling_apply(H2Tree t, int F, int R, const double* St, const double* xh, double* yh) {
