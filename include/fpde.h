@@ -176,9 +176,9 @@ fpde_status fpde_load_vector(fpde_op *op, const double *f_nodal, double *F, void
  * runs unpreconditioned CG on A d = r from d = 0 and adds d to u.  An FP64
  * operator's CG runs to 0.5 rtol in one pass (a second pass only corrects
  * drift of the recursive residual); an FPDE_PREC_MIXED operator's CG uses the
- * mixed-precision apply and stops each pass at a relative reduction of 1e-4.
- * CG iterations run as captured HIP graphs; the host polls convergence every
- * few iterations.  Synchronises hip_stream.  info (host, may be NULL): total
+ * mixed-precision apply and stops each pass at a relative reduction of
+ * sqrt(rtol), clamped to [1e-7, 1e-2].  CG iterations are launched back to
+ * back on hip_stream; the host polls convergence every few iterations.  Synchronises hip_stream.  info (host, may be NULL): total
  * CG iterations of the worst system summed over passes, final worst relative
  * residual, converged flag, number of refinement passes.
  * Errors: FPDE_EINVAL, FPDE_ESTATE (plan-only), FPDE_ENOCONV (maxit reached,

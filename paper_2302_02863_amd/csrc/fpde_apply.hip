@@ -50,17 +50,6 @@ __device__ __forceinline__ int heap_level(int64_t c) {
     return lev;
 }
 
-// Stores and loads of values that another block of the same launch reads:
-// agent-scope atomics, coherent across the XCDs' L2 caches.
-template <typename T>
-__device__ __forceinline__ void put(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ T get(const T* p) {
-    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Upsweep (nested bases, Sec. 5.3) from the leaves up to level lmin.
 // Stage 0: upsweep block b owns the subtree of depth d0 rooted at level L - d0
 // (2^d0 leaves, at most one per wave): leaf coefficients x^_leaf = U_leaf^T

@@ -27,6 +27,20 @@ __device__ __forceinline__ double ldx(const void* x, int64_t i, int dtype) {
 // |d|^{-e} from |d|^2: exp(-e/2 * log(r2))
 __device__ __forceinline__ double rpow(double r2, double e) { return exp(-0.5 * e * log(r2)); }
 
+// Stores and loads of values that another block of the same launch reads:
+// agent-scope atomics, coherent across the XCDs' L2 caches.  A block hands
+// such values over by waiting for its stores (s_waitcnt 0), a barrier, then one
+// agent-scope counter increment; the block that sees the final count reads
+// them with get().
+template <typename T>
+__device__ __forceinline__ void put(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T get(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // sum over the 64 lanes of a wavefront
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

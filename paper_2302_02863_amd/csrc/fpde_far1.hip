@@ -1,5 +1,7 @@
 // Far field of the one-vector apply after its upsweep: coupling sums per far
 // target cluster, then the downsweep fused with the output (Sec. 5.2-5.3).
+// Partial coupling sums that one block hands to another are stored and loaded
+// as agent-scope atomics (put / get), coherent across the XCDs' L2 caches.
 // Both run in the operator's precision T (FP32 data of a mixed operator
 // accumulate in FP32 and are added to y in FP64).
 #include <hip/hip_runtime.h>
@@ -12,75 +14,77 @@ namespace fpde {
 
 constexpr int kFarThreads = 256;
 
-// Coupling of far target cluster c (Sec. 5.2): z^(c) = sum over the far pairs
-// (c, s) of S x^(s).  Pair slots of G lanes (lane alpha) each take every NS-th
-// pair of c and accumulate S[alpha][beta] x^(s)[beta]; St holds S transposed
-// ([beta][alpha]) so that the lanes read consecutive entries, and x^(s)[beta]
-// is broadcast from lane beta of the slot.  The source index is loaded first
-// (the x^ gather waits only for it), and the next pair's S is in flight while
-// the current one is summed.  The slots are summed in a fixed order.  z^ of
-// clusters that are not targets stays zero.
+// Coupling (Sec. 5.2): z^(c) = sum over the far pairs (c, s) of S x^(s) for
+// every far target c.  The pairs of a target are cut into chunks of at most
+// NS pairs, one block per chunk, one pair per slot of G lanes (lane alpha):
+// S[alpha][beta] x^(s)[beta] summed over beta, St holding S transposed
+// ([beta][alpha]) so that the lanes read consecutive entries, x^(s)[beta]
+// broadcast from lane beta of the slot.  The slots are summed in a fixed
+// order.  A target with one chunk writes z^ at once; otherwise each chunk
+// stores its partial at agent scope, counts itself on the target's ticket,
+// and the last one sums the partials in chunk order and resets the ticket.
+// z^ of clusters that are not targets stays zero.
 constexpr int kCoupleThreads = 512;
 template <int D, int P, typename T>
-__device__ __forceinline__ void couple(const H2Tree& t, int64_t c, int f, const T* St, const T* xh, T* zh, T* sred) {
+__global__ __launch_bounds__(kCoupleThreads) void k_couple(H2Tree t, FarPlan fp, const T* St, const T* xh, T* zh,
+                                                           T* zp) {
     constexpr int K = KR<D, P>::K;
     constexpr int G = K <= 32 ? 32 : 64;   // lanes of a pair slot
     constexpr int NS = kCoupleThreads / G; // pair slots
+    __shared__ T sred[kCoupleThreads];
+    __shared__ int s_last;
+    const int f = blockIdx.y;
+    const int64_t* ck = fp.chunks + 4 * (int64_t)blockIdx.x;
+    const int64_t c = ck[0], e0 = ck[1], e1 = ck[2];
+    const int ci = (int)(ck[3] >> 32), nch = (int)(ck[3] & 0xffffffff);
     const int64_t nfar = t.far_ptr[t.ncl];
-    const int64_t e0 = t.far_ptr[c], e1 = t.far_ptr[c + 1];
     const int sl = threadIdx.x / G, al = threadIdx.x % G;
-    const int alc = al < K ? al : 0;
     const int base = (threadIdx.x & 63) & ~(G - 1);   // first lane of the slot within the wave
-    const T* xf = xh + (int64_t)f * t.ncl * K;
-    const T* Sf = St + (int64_t)f * nfar * K * K + alc;
+    const int64_t e = e0 + sl;
     T acc = 0;
-    int64_t e = e0 + sl;
-    if (e < e1) {
-        int64_t src = t.far_src[e];
+    if (e < e1) {   // the lanes of a slot share e
+        const int64_t src = t.far_src[e];
+        const T* S = St + ((int64_t)f * nfar + e) * K * K + (al < K ? al : 0);
         T sv[K];
 #pragma unroll
-        for (int b = 0; b < K; ++b) sv[b] = Sf[(e * K + b) * K];
-        for (;;) {   // the lanes of a slot share e
-            const T xv = al < K ? xf[src * K + al] : T(0);
-            const int64_t en = e + NS;
-            const bool more = en < e1;
-            int64_t srcn = 0;
-            T svn[K];
-            if (more) {
-                srcn = t.far_src[en];
+        for (int b = 0; b < K; ++b) sv[b] = S[b * K];
+        const T xv = al < K ? xh[((int64_t)f * t.ncl + src) * K + al] : T(0);
 #pragma unroll
-                for (int b = 0; b < K; ++b) svn[b] = Sf[(en * K + b) * K];
-            }
-#pragma unroll
-            for (int b = 0; b < K; ++b) acc += sv[b] * __shfl(xv, base + b, 64);
-            if (!more) break;
-            e = en;
-            src = srcn;
-#pragma unroll
-            for (int b = 0; b < K; ++b) sv[b] = svn[b];
-        }
+        for (int b = 0; b < K; ++b) acc += sv[b] * __shfl(xv, base + b, 64);
     }
     sred[sl * G + al] = acc;
     __syncthreads();
-    if (threadIdx.x < K) {
-        T z = 0;
+    T z = 0;
+    if (threadIdx.x < K)
         for (int s = 0; s < NS; ++s) z += sred[s * G + threadIdx.x];
-        zh[((int64_t)f * t.ncl + c) * K + threadIdx.x] = z;
+    T* zc = zh + ((int64_t)f * t.ncl + c) * K;
+    if (nch == 1) {
+        if (threadIdx.x < K) zc[threadIdx.x] = z;
+        return;
     }
-}
-
-// One block per far target cluster tgt[b].
-template <int D, int P, typename T>
-__global__ __launch_bounds__(kCoupleThreads) void k_couple(H2Tree t, FarPlan fp, const T* St, const T* xh, T* zh) {
-    __shared__ T sred[kCoupleThreads];
-    couple<D, P, T>(t, fp.tgt[blockIdx.x], blockIdx.y, St, xh, zh, sred);
+    T* zpf = zp + (int64_t)f * fp.nchunks * K;
+    if (threadIdx.x < K) put(&zpf[(int64_t)blockIdx.x * K + threadIdx.x], z);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    unsigned int* tk = &fp.ctk[(int64_t)f * t.ncl + c];
+    if (threadIdx.x == 0)
+        s_last = __hip_atomic_fetch_add(tk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned int)nch - 1;
+    __syncthreads();
+    if (!s_last) return;
+    if (threadIdx.x == 0) __hip_atomic_store(tk, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < K) {
+        const int64_t first = (int64_t)blockIdx.x - ci;   // chunks of a target are consecutive
+        T s = 0;
+        for (int j = 0; j < nch; ++j) s += get(&zpf[(first + j) * K + threadIdx.x]);
+        zc[threadIdx.x] = s;
+    }
 }
 
 // Downsweep and output (Sec. 5.3): y[perm[row]] += U[row] . y^_leaf, where
 // y^ of a cluster is its z^ plus the transfer of its parent's y^, from level
 // ltop (the shallowest target) down.  One block per (leaf, 64 rows, field),
-// 4 lanes per row; the basis rows, output indices, old y values, transfers
-// and z^ of the root path are all fetched before the walk.
+// 256 threads, 4 lanes per row; the basis rows, output indices, old y values,
+// transfers and z^ of the root path are all fetched before the walk.
 template <int D, int P, typename T>
 __global__ __launch_bounds__(kFarThreads) void k_far_out(ApplyPlan a, H2Tree t, int ltop, const T* zh, const T* U,
                                                            const T* E, int dtype, void* y) {
@@ -94,28 +98,48 @@ __global__ __launch_bounds__(kFarThreads) void k_far_out(ApplyPlan a, H2Tree t, 
     const int64_t li = blockIdx.x / nrb;
     const int rb = (int)(blockIdx.x % nrb);
     const int64_t leafc = t.first_leaf + li;
+    // z^ and transfers of the root path depend on no load: fetched first, into
+    // registers, and written to LDS once the dependent loads are in flight
+    const T* zf = zh + (int64_t)f * t.ncl * K;
+    constexpr int kZR = 2, kER = 4;   // entries per thread held in registers
+    T zr[kZR], er[kER];
+#pragma unroll
+    for (int q = 0; q < kZR; ++q) {
+        const int i = threadIdx.x + q * kFarThreads;
+        zr[q] = i < nlev * K ? zf[(((leafc + 1) >> (L - (ltop + i / K))) - 1) * K + i % K] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kER; ++q) {
+        const int i = threadIdx.x + q * kFarThreads;
+        er[q] = i < nlev * EP ? E[(((leafc + 1) >> (L - (ltop + i / EP))) - 1) * EP + i % EP] : T(0);
+    }
     const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
     const int g = threadIdx.x & 3;
     const int64_t it = (int64_t)rb * 64 + (threadIdx.x >> 2);
     const bool ok = it < nt;
-    T u[(K + 3) / 4];
-#pragma unroll
-    for (int q = 0; q < (K + 3) / 4; ++q) u[q] = (ok && 4 * q + g < K) ? U[(lb + it) * K + 4 * q + g] : T(0);
     int64_t dst = 0;
     double yold = 0.0;
     if (ok && g == 0) {
         dst = (int64_t)f * a.N + a.perm[lb + it];
         yold = ldx(y, dst, dtype);
     }
-    const T* zf = zh + (int64_t)f * t.ncl * K;
-    for (int i = threadIdx.x; i < nlev * K; i += blockDim.x) {
-        const int lev = ltop + i / K;
-        sy[i] = zf[(((leafc + 1) >> (L - lev)) - 1) * K + i % K];
+    T u[(K + 3) / 4];
+#pragma unroll
+    for (int q = 0; q < (K + 3) / 4; ++q) u[q] = (ok && 4 * q + g < K) ? U[(lb + it) * K + 4 * q + g] : T(0);
+#pragma unroll
+    for (int q = 0; q < kZR; ++q) {
+        const int i = threadIdx.x + q * kFarThreads;
+        if (i < nlev * K) sy[i] = zr[q];
     }
-    for (int i = threadIdx.x; i < nlev * EP; i += blockDim.x) {
-        const int lev = ltop + i / EP;
-        sE[i] = E[(((leafc + 1) >> (L - lev)) - 1) * EP + i % EP];
+#pragma unroll
+    for (int q = 0; q < kER; ++q) {
+        const int i = threadIdx.x + q * kFarThreads;
+        if (i < nlev * EP) sE[i] = er[q];
     }
+    for (int i = threadIdx.x + kZR * kFarThreads; i < nlev * K; i += blockDim.x)   // very deep trees
+        sy[i] = zf[(((leafc + 1) >> (L - (ltop + i / K))) - 1) * K + i % K];
+    for (int i = threadIdx.x + kER * kFarThreads; i < nlev * EP; i += blockDim.x)
+        sE[i] = E[(((leafc + 1) >> (L - (ltop + i / EP))) - 1) * EP + i % EP];
     __syncthreads();
     for (int l = 1; l < nlev; ++l) {
         for (int i = threadIdx.x; i < K; i += blockDim.x)
@@ -147,8 +171,8 @@ struct Far1 {
     template <int D, int P>
     static void far_out(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<T>& od, int dtype,
                         void* y, hipStream_t st) {
-        hipLaunchKernelGGL((k_couple<D, P, T>), dim3((unsigned)fp.ntgt, F), dim3(kCoupleThreads), 0, st, t, fp, od.St,
-                           od.xh, od.zh);
+        hipLaunchKernelGGL((k_couple<D, P, T>), dim3((unsigned)fp.nchunks, F), dim3(kCoupleThreads), 0, st, t, fp,
+                           od.St, od.xh, od.zh, od.zp);
         const int64_t nrb = (a.cap + 63) / 64;
         const size_t lds = path_lds<D, P, T>(t, fp.ltop);
         hipLaunchKernelGGL((k_far_out<D, P, T>), dim3((unsigned)(a.nleaf * nrb), F), dim3(kFarThreads), lds, st, a,

@@ -159,11 +159,12 @@ struct fpde_op {
     int64_t nfar1 = 0;
     int64_t *d_far1_ptr = nullptr, *d_far1_src = nullptr;
     double* d_St1 = nullptr;               // [F][nfar1][k][k], transposed like d_St
+    double* d_zp = nullptr;                // [F][nchunks][k] partial coupling sums
     UpPlan up[2]{};                        // one-launch upsweep plan per precision (0 FP64, 1 FP32)
     FarPlan far_plan{};                    // far targets of the one-vector output kernel
     struct {                               // FP32 operator data of a mixed-precision operator
         float *U = nullptr, *E = nullptr, *St = nullptr, *St1 = nullptr, *panel = nullptr;
-        float *xh = nullptr, *zh = nullptr;    // workspace, one right-hand side
+        float *xh = nullptr, *zh = nullptr, *zp = nullptr;   // workspace, one right-hand side
         float *xhR = nullptr, *yhR = nullptr;  // workspace [F][ncl][K][R]
     } f32;
     bool mixed = false;                    // built with FPDE_PREC_MIXED
@@ -178,13 +179,11 @@ struct fpde_op {
     double *d_part1 = nullptr, *d_part2 = nullptr, *d_part3 = nullptr, *d_bb = nullptr, *d_rro = nullptr;
     CgScalars cg{};
     int* h_nact = nullptr;                    // pinned host copy of the active-system count
-    // captured CG iterations keyed by (precision, R)
-    std::map<std::pair<int, int64_t>, hipGraphExec_t> cg_graphs;
     fpde_stats_t stats{};
     // profiling: events recorded per apply (gather begin, gather end, far end, out end)
     bool profiling = false;
     std::vector<std::array<hipEvent_t, 5>> prof_ev;
-    hipStream_t stream2 = nullptr;            // side stream of the captured fork/join graph
+    hipStream_t stream2 = nullptr;            // side stream of the multi-vector far chain (fork/join)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double* d_tmp = nullptr;                  // [F][nfar][k][R] per-pair coupling products
     // ---- adjoint (fpde_apply_adjoint): build data kept on the device
@@ -955,6 +954,23 @@ void build_device(fpde_op& op) {
             }
             for (int64_t c = 0; c < kt.ncl; ++c) fptr1[c + 1] += fptr1[c];
             op.nfar1 = (int64_t)src1.size();
+            {   // coupling chunks: at most one pair per slot of a 512-thread block
+                const int64_t cs = 512 / (k <= 32 ? 32 : 64);
+                std::vector<int64_t> ck;
+                for (int64_t c = 0; c < kt.ncl; ++c) {
+                    const int64_t p0 = fptr1[c], p1 = fptr1[c + 1];
+                    if (p1 == p0) continue;
+                    const int64_t nch = (p1 - p0 + cs - 1) / cs;
+                    for (int64_t j = 0; j < nch; ++j)
+                        ck.insert(ck.end(), {c, p0 + j * cs, std::min(p1, p0 + (j + 1) * cs), (j << 32) | nch});
+                }
+                op.far_plan.nchunks = (int64_t)ck.size() / 4;
+                op.far_plan.chunks = A.upload(ck, st);
+                op.far_plan.ctk = A.alloc<unsigned int>((int64_t)F * kt.ncl);
+                hipck(hipMemsetAsync(op.far_plan.ctk, 0, sizeof(unsigned int) * F * kt.ncl, st), "coupling tickets");
+                op.d_zp = A.alloc<double>((int64_t)F * std::max<int64_t>(1, op.far_plan.nchunks) * k);
+                hipck(hipStreamSynchronize(st), "chunk upload");   // ck ends here
+            }
             op.d_far1_ptr = A.upload(fptr1, st);
             op.d_far1_src = A.upload(src1, st);
             int64_t* d_orig = A.upload(orig1, st);
@@ -1035,8 +1051,6 @@ void ensure_ws(fpde_op& op, int64_t R) {
     const int d = op.mesh.dim, p = op.opts.cheb_p, k = d == 2 ? p * p : p;
     if (op.d_xt) {
         op.arena.release(op.d_xt); op.arena.release(op.d_xh); op.arena.release(op.d_yh); op.arena.release(op.d_tmp);
-        for (auto& kv : op.cg_graphs) hipGraphExecDestroy(kv.second);
-        op.cg_graphs.clear();
     }
     op.d_tmp = op.arena.alloc<double>((int64_t)op.F * std::max<size_t>(1, op.kfar.size()) * k * R);
     op.d_xt = op.arena.alloc<double>((int64_t)op.F * (op.mesh.N + op.cap) * R);
@@ -1046,6 +1060,7 @@ void ensure_ws(fpde_op& op, int64_t R) {
         if (!op.f32.xh) {
             op.f32.xh = op.arena.alloc<float>((int64_t)op.F * op.kt.ncl * k);
             op.f32.zh = op.arena.alloc<float>((int64_t)op.F * op.kt.ncl * k);
+            op.f32.zp = op.arena.alloc<float>((int64_t)op.F * std::max<int64_t>(1, op.far_plan.nchunks) * k);
             hipck(hipMemset(op.f32.zh, 0, sizeof(float) * op.F * op.kt.ncl * k), "zh");
         }
         if (op.f32.xhR) {
@@ -1101,11 +1116,11 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
         h1.far_ptr = op.d_far1_ptr;
         h1.far_src = op.d_far1_src;
         if (f32) {
-            OpData<float> od{op.f32.U, op.f32.E, op.f32.St1, op.f32.panel, op.f32.xh, op.f32.zh};
+            OpData<float> od{op.f32.U, op.f32.E, op.f32.St1, op.f32.panel, op.f32.xh, op.f32.zh, op.f32.zp};
             return launch_apply_single(a, h1, pp, op.up[1], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets,
                                        s0, ev);
         }
-        OpData<double> od{op.d_U, op.kdev.E, op.d_St1, op.d_panel, op.d_xh, op.d_zh};
+        OpData<double> od{op.d_U, op.kdev.E, op.d_St1, op.d_panel, op.d_xh, op.d_zh, op.d_zp};
         return launch_apply_single(a, h1, pp, op.up[0], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets, s0,
                                    ev);
     }
@@ -1272,8 +1287,6 @@ void ensure_solve_ws(fpde_op& op, int64_t R) {
                     (void*)op.cg.active, (void*)op.cg.active_next, (void*)op.cg.iters, (void*)op.cg.flags,
                     (void*)op.cg.n_active})
         if (q) A.release(q);
-    for (auto& kv : op.cg_graphs) hipGraphExecDestroy(kv.second);
-    op.cg_graphs.clear();
     const int64_t n = (int64_t)op.F * op.mesh.N * R, S = (int64_t)op.F * R;
     const int64_t nb = cg_row_blocks(op.mesh.N, (int)R);
     op.d_r = A.alloc<double>(n);
@@ -1317,23 +1330,6 @@ hipError_t enqueue_cg_iteration(fpde_op& op, bool mixed, int64_t R, hipStream_t 
                               op.cg, s0);
 }
 
-hipGraphExec_t cg_graph(fpde_op& op, bool mixed, int64_t R) {
-    auto key = std::make_pair(mixed ? 1 : 0, R);
-    auto it = op.cg_graphs.find(key);
-    if (it != op.cg_graphs.end()) return it->second;
-    hipGraph_t g = nullptr;
-    hipck(hipStreamBeginCapture(op.stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    hipError_t le = enqueue_cg_iteration(op, mixed, R, op.stream, op.stream2);
-    hipError_t ce = hipStreamEndCapture(op.stream, &g);
-    hipck(le, "cg iteration launch");
-    hipck(ce, "end capture");
-    hipGraphExec_t ex = nullptr;
-    hipck(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate");
-    hipGraphDestroy(g);
-    op.cg_graphs.emplace(key, ex);
-    return ex;
-}
-
 // CG on A d = rout from d = 0 until |r_s| <= max(tau_in |rout_s|, rtol_abs_s) for every
 // system s (rtol_abs_s = rtol |b_s|, |b_s|^2 in d_bb).  Returns the largest
 // per-system iteration count; *breakdown is set if a system lost positivity.
@@ -1348,11 +1344,10 @@ int cg_run(fpde_op& op, bool mixed, int64_t R, double tau_in, double rtol, int m
     hipck(hipStreamSynchronize(st), "sync");
     *breakdown = false;
     if (*op.h_nact == 0) return 0;
-    hipGraphExec_t g = cg_graph(op, mixed, R);
     int it = 0, chunk = 4;
     while (it < maxit) {
         const int n = std::min(chunk, maxit - it);
-        for (int j = 0; j < n; ++j) hipck(hipGraphLaunch(g, st), "cg graph launch");
+        for (int j = 0; j < n; ++j) hipck(enqueue_cg_iteration(op, mixed, R, st, op.stream2), "cg iteration");
         it += n;
         hipck(hipMemcpyAsync(op.h_nact, op.cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
         hipck(hipStreamSynchronize(st), "sync");
@@ -1679,8 +1674,6 @@ fpde_status fpde_export(const fpde_op* op, int32_t what, int32_t field, void* ds
 
 void fpde_destroy(fpde_op* op) {
     if (!op) return;
-    for (auto& kv : op->cg_graphs) hipGraphExecDestroy(kv.second);
-    op->cg_graphs.clear();
     if (op->h_nact) hipHostFree(op->h_nact);
     for (auto& ev : op->prof_ev)
         for (auto& e : ev) hipEventDestroy(e);

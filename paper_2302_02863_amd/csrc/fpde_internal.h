@@ -199,6 +199,7 @@ struct OpData {
     const T* panel;   // [F][panel_total]
     T* xh;            // [F][ncl][K] workspace: upsweep coefficients x^
     T* zh;            // [F][ncl][K] coupling sums z^ per target cluster, zero for the others
+    T* zp;            // [F][nchunks][K] partial sums of targets split in several coupling chunks
 };
 // One-launch upsweep: leaf-stage subtree depth d0, upper-stage depth ds
 struct UpPlan {
@@ -212,6 +213,11 @@ struct FarPlan {
     const int64_t* tgt;    // [ntgt] clusters with incoming far pairs, in heap order
     int64_t ntgt;
     int ltop;              // level of the shallowest target
+    // coupling work: chunks of at most one pair per slot of a coupling block,
+    // 4 words each: target, first pair, end pair, (chunk of the target << 32 | chunks of the target)
+    const int64_t* chunks;
+    int64_t nchunks;
+    unsigned int* ctk;     // [F][ncl] zero-initialised tickets of targets split in several chunks
 };
 UpPlan plan_up_tree(const H2Tree& t, int64_t cap, int lmin, int prec /*0 double, 1 float*/);
 hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const int64_t* near_ptr,

@@ -7,7 +7,7 @@
 // solve is bitwise reproducible.  The per-system scalars stay on the device:
 // each block that needs alpha or beta sums the partials itself (same order,
 // same value in every block), so one CG iteration is the operator apply and
-// three row-block kernels, captured in a graph, with no host round trip.
+// three row-block kernels, launched back to back with no host round trip.
 // State that the blocks of a kernel read (|r|^2, activity) is only committed
 // by the next kernel, so no block reads a value another block of the same
 // kernel writes.
@@ -59,7 +59,8 @@ __device__ inline double sum_parts(const double* part, int64_t nb, int R, int64_
 // [blockIdx.x * rpb, ...):
 //   CG_DOT:       part1 = p . Ap                                        (a=p, b=Ap)
 //                 the first block of the field commits |r|^2 and activity of the
-//                 previous iteration (rr = rr_next, active = active_next)
+//                 previous iteration (rr = rr_next, active = active_next); the
+//                 first block of field 0 clears the active-system counter
 //   CG_UPDATE_UR: alpha = rr / p.Ap (p.Ap summed from part_in); a system with a
 //                 non-positive p.Ap takes alpha = 0 and is flagged (breakdown);
 //                 u += alpha p, r -= alpha Ap, part1 = r . r             (a=p, b=Ap)
@@ -69,9 +70,11 @@ __device__ inline double sum_parts(const double* part, int64_t nb, int R, int64_
 //   CG_RESID:     r = b - Ap, part1 = r . r, part2 = b . b              (a=Ap, b=b)
 //   CG_COPY_RP:   r = b, p = b, u = 0, part1 = b . b                    (b=b)
 template <int OP>
-__global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb, const double* a, const double* b,
-                                                  double* u, double* r, double* p, double* part1, double* part2,
-                                                  const double* part_in, CgScalars c) {
+__global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb, const double* __restrict__ a,
+                                                  const double* __restrict__ b, double* __restrict__ u,
+                                                  double* __restrict__ r, double* __restrict__ p,
+                                                  double* __restrict__ part1, double* __restrict__ part2,
+                                                  const double* __restrict__ part_in, CgScalars c) {
     __shared__ double red[kBS];
     __shared__ double coef[kBS];
     __shared__ int nact;
@@ -84,12 +87,14 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
     const int cl = t % RC, rl = t / RC, nrl = kBS / RC;
     const bool first = blockIdx.x == 0;
     constexpr bool kCoef = OP == CG_UPDATE_UR || OP == CG_UPDATE_P;
-    if (OP == CG_DOT && first)
+    if (OP == CG_DOT && first) {
         for (int col = t; col < R; col += kBS) {
             const int64_t sys = (int64_t)f * R + col;
             c.rr[sys] = c.rr_next[sys];
             c.active[sys] = c.active_next[sys];
         }
+        if (f == 0 && t == 0) c.n_active[0] = 0;   // rebuilt by this iteration's CG_UPDATE_P
+    }
     if (OP == CG_UPDATE_P && t == 0) nact = 0;
     for (int c0 = 0; c0 < R; c0 += RC) {
         const int col = c0 + cl;
@@ -192,11 +197,6 @@ __global__ __launch_bounds__(kBS) void k_cg_start(int64_t S, int64_t nb, int R, 
     if (threadIdx.x == 0) c.n_active[0] = cnt;
 }
 
-// The active-system counter is rebuilt by every CG_UPDATE_P pass.
-__global__ void k_zero_count(int* n) {
-    if (threadIdx.x == 0) n[0] = 0;
-}
-
 // |r|^2 and |b|^2 of the outer residual r = b - A u per system
 __global__ __launch_bounds__(kBS) void k_sum2(int64_t S, int64_t nb, int R, const double* part1, const double* part2,
                                                double* o1, double* o2) {
@@ -219,8 +219,9 @@ unsigned grid_of(int64_t n) {
 }  // namespace
 
 int64_t cg_row_blocks(int64_t N, int R) {
-    // about 8 elements per thread: N * R / 2048 blocks, between 1 and 1024 per field
-    int64_t nb = (N * (int64_t)R + 2047) / 2048;
+    // one element per thread: N * R / 256 blocks, between 1 and 1024 per field
+    // (the partials of a pass are summed by every block of the next one)
+    int64_t nb = (N * (int64_t)R + kBS - 1) / kBS;
     if (nb < 1) nb = 1;
     if (nb > 1024) nb = 1024;
     if (nb > N) nb = N;
@@ -239,10 +240,7 @@ hipError_t launch_cg_rowblock(int op, const CgDims& d, const double* a, const do
         case CG_UPDATE_UR: FPDE_ROWBLOCK(CG_UPDATE_UR); break;
         case CG_RESID: FPDE_ROWBLOCK(CG_RESID); break;
         case CG_COPY_RP: FPDE_ROWBLOCK(CG_COPY_RP); break;
-        case CG_UPDATE_P:
-            hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, st, c.n_active);
-            FPDE_ROWBLOCK(CG_UPDATE_P);
-            break;
+        case CG_UPDATE_P: FPDE_ROWBLOCK(CG_UPDATE_P); break;
         default: return hipErrorInvalidValue;
     }
 #undef FPDE_ROWBLOCK
