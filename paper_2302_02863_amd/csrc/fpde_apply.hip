@@ -7,20 +7,20 @@
 //   k_near_up    blocks [0, nup): the upsweep, whole subtrees of depth d0 per
 //                block (leaf coefficients, then the nested transfers);
 //                blocks [nup, ...): the near rows (CSR row of B + M and the
-//                packed near panel row).  The far list of this path has its
-//                sources moved down to the subtree levels at build (coupling
-//                matrices S M_r^T), so on the usual trees no block reads
-//                another's coefficients.  On deeper trees the levels still
-//                above the subtree roots are chained by tickets: the subtree
-//                roots one block hands to another are stored and loaded as
-//                agent-scope atomics, which bypass the per-XCD L2 copies;
-//                every wave waits for its stores to be acknowledged before the
-//                block's barrier and its one ticket increment, so no cache
-//                writeback or invalidate is needed, and no block ever waits
-//                for another (the last arrival goes on), so the launch always
-//                drains.
+//                packed near panel row).
 //   k_couple, k_far_out (fpde_far1.hip): coupling sums per far target, then
 //                the downsweep walk fused with the output.
+// The far list of this path has its sources moved down to the subtree levels
+// at build (coupling matrices S M_r^T), so on the usual trees no upsweep block
+// reads another's coefficients.  On deeper trees the levels still above the
+// subtree roots are chained by tickets: the subtree roots one block hands to
+// another are stored and loaded as agent-scope atomics, which bypass the
+// per-XCD L2 copies; every wave waits for its stores to be acknowledged before
+// the block's barrier and its one ticket increment, so no cache writeback or
+// invalidate is needed, and no block ever waits for another (the last arrival
+// goes on), so the launch always drains.  (The far chain on a second stream
+// beside the near rows was measured slower: the streams did not overlap and
+// the event fork/join added its own cost.)
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -30,7 +30,6 @@
 
 namespace fpde {
 
-constexpr int kApplyThreads = 256;
 
 template <typename T>
 struct Vec2;
@@ -193,8 +192,8 @@ __device__ __forceinline__ void up_tree(const ApplyPlan& a, const H2Tree& t, con
     }
 }
 
-// Near rows: y[f][perm[row]] = (B+M)_row . x + panel_row . x_near for the 16
-// rows of block rb of leaf li, 16 lanes per row.  The x entries of the leaf's
+// Near rows: y[f][perm[row]] = (B+M)_row . x + panel_row . x_near for the
+// rows of block rb of leaf li, 16 lanes per row (blockDim / 16 rows).  The x entries of the leaf's
 // near columns are staged in LDS once per block.  Each lane keeps 8 vector
 // loads of its panel row in flight; the first 8 are issued before the x
 // staging and the CSR row, so their latency overlaps those gathers.
@@ -204,12 +203,13 @@ __device__ __forceinline__ void near_rows(const ApplyPlan& a, const PanelPlan& p
                                           int64_t bid, T* xs) {
     using V2 = typename Vec2<T>::type;
     constexpr int NB = 8;   // vector loads in flight per lane (32 columns apart)
-    const int64_t nrb = (a.cap + 15) / 16;
+    const int rpb = blockDim.x / 16;   // rows per block
+    const int64_t nrb = (a.cap + rpb - 1) / rpb;
     const int64_t li = bid / nrb;
     const int rb = (int)(bid % nrb);
     const int64_t xo = (int64_t)f * a.N;
     const int g = threadIdx.x & 15;
-    const int64_t it = (int64_t)rb * 16 + (threadIdx.x >> 4);
+    const int64_t it = (int64_t)rb * rpb + (threadIdx.x >> 4);
     const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
     const bool ok = it < nt;
     const int64_t row = lb + it;
@@ -258,13 +258,14 @@ __device__ __forceinline__ void near_rows(const ApplyPlan& a, const PanelPlan& p
 }
 
 // Upsweep blocks first, then the near rows.  The upsweep blocks are
-// dispatched first, so their dependent chain starts at once beside the near
-// rows' HBM stream.
+// dispatched first, so their dependent chain (one subtree of depth d0 per
+// block: 2^d0 leaves, two waves each) runs beside the near rows' HBM stream.
+constexpr int kUpThreads = 512;
 template <int D, int P, typename T>
-__global__ __launch_bounds__(kApplyThreads) void k_near_up(ApplyPlan a, H2Tree t, PanelPlan pp, UpPlan up, int nup,
-                                                           const T* panel, int use_near, const double* csr_val,
-                                                           int dtype, const void* x, void* y, const T* U, const T* E,
-                                                           T* xh, unsigned int* tickets) {
+__global__ __launch_bounds__(kUpThreads) void k_near_up(ApplyPlan a, H2Tree t, PanelPlan pp, UpPlan up, int nup,
+                                                        const T* panel, int use_near, const double* csr_val,
+                                                        int dtype, const void* x, void* y, const T* U, const T* E,
+                                                        T* xh, unsigned int* tickets) {
     extern __shared__ __align__(16) unsigned char sraw[];
     const int f = blockIdx.y;
     if ((int)blockIdx.x < nup)
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_near_up(ApplyPlan a, H2Tree t
 template <int D, int P, typename T>
 static size_t up_tree_lds(int64_t cap, int d0, int ds) {
     constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
-    constexpr int64_t waves = kApplyThreads / 64;
+    constexpr int64_t waves = kUpThreads / 64;
     const int64_t s0 = ((int64_t(2) << d0) - 1) * (K + EP) + waves * (K + cap);
     const int64_t s1 = ((int64_t(2) << ds) - 1) * (K + EP);
     return sizeof(T) * (size_t)(s0 > s1 ? s0 : s1);
@@ -290,7 +291,7 @@ struct Single {
                         int use_near, const double* csr_val, int F, int dtype, const void* x, void* y,
                         const OpData<T>& od, unsigned int* tickets, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
         const int nup = far ? (int)(int64_t(1) << (t.L - up.d0)) : 0;
-        const int64_t nrb = (a.cap + 15) / 16;
+        const int64_t nrb = (a.cap + kUpThreads / 16 - 1) / (kUpThreads / 16);
         size_t lds = sizeof(T) * (pp.max_stride > 0 ? pp.max_stride : 1);
         if (far) {
             const size_t lu = up_tree_lds<D, P, T>(a.cap, up.d0, up.ds);
@@ -298,20 +299,20 @@ struct Single {
         }
         const dim3 grid((unsigned)(nup + a.nleaf * nrb), F);
         if (e0)   // start/stop timestamps of exactly this kernel
-            hipExtLaunchKernelGGL((k_near_up<D, P, T>), grid, dim3(kApplyThreads), lds, st, e0, e1, 0, a, t, pp, up,
+            hipExtLaunchKernelGGL((k_near_up<D, P, T>), grid, dim3(kUpThreads), lds, st, e0, e1, 0, a, t, pp, up,
                                   nup, od.panel, use_near, csr_val, dtype, x, y, od.U, od.E, od.xh, tickets);
         else
-            hipLaunchKernelGGL((k_near_up<D, P, T>), grid, dim3(kApplyThreads), lds, st, a, t, pp, up, nup, od.panel,
+            hipLaunchKernelGGL((k_near_up<D, P, T>), grid, dim3(kUpThreads), lds, st, a, t, pp, up, nup, od.panel,
                                use_near, csr_val, dtype, x, y, od.U, od.E, od.xh, tickets);
     }
-    // leaf-stage depth d0 (1: two leaves, two waves each; at most 2, one leaf
-    // per wave) and the upper-stage depth ds: the levels above the stage-0
-    // roots up to lmin in one stage if they fit 64 KB of LDS
+    // leaf-stage depth d0 (2: four leaves, two waves each) and the upper-stage
+    // depth ds: the levels above the stage-0 roots up to lmin in one stage if
+    // they fit 64 KB of LDS
     template <int D, int P>
     static void plan(const H2Tree& t, int64_t cap, int lmin, UpPlan* up) {
         const size_t lim = 64 * 1024;
         up->lmin = lmin;
-        up->d0 = t.L < 1 ? t.L : 1;
+        up->d0 = t.L < 2 ? t.L : 2;
         while (up->d0 > 0 && up_tree_lds<D, P, T>(cap, up->d0, 1) > lim) --up->d0;
         const int need = t.L - up->d0 - lmin > 1 ? t.L - up->d0 - lmin : 1;
         up->ds = 1;
@@ -344,8 +345,8 @@ static hipError_t apply_single_t(const ApplyPlan& a, const H2Tree& t, const Pane
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (far) {
-        e = launch_far_single(a, t, fp, F, od, dtype, y, st);
-        if (e != hipSuccess) return e;
+        if ((e = launch_couple_single(t, fp, F, od, st)) != hipSuccess) return e;
+        if ((e = launch_out_single(a, t, fp, F, od, dtype, y, st)) != hipSuccess) return e;
     }
     if (ev) (void)hipEventRecord(ev[4], st);
     return hipGetLastError();

@@ -169,10 +169,13 @@ static size_t path_lds(const H2Tree& t, int ltop) {
 template <typename T>
 struct Far1 {
     template <int D, int P>
-    static void far_out(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<T>& od, int dtype,
-                        void* y, hipStream_t st) {
+    static void couple(const H2Tree& t, const FarPlan& fp, int F, const OpData<T>& od, hipStream_t st) {
         hipLaunchKernelGGL((k_couple<D, P, T>), dim3((unsigned)fp.nchunks, F), dim3(kCoupleThreads), 0, st, t, fp,
                            od.St, od.xh, od.zh, od.zp);
+    }
+    template <int D, int P>
+    static void out(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<T>& od, int dtype,
+                    void* y, hipStream_t st) {
         const int64_t nrb = (a.cap + 63) / 64;
         const size_t lds = path_lds<D, P, T>(t, fp.ltop);
         hipLaunchKernelGGL((k_far_out<D, P, T>), dim3((unsigned)(a.nleaf * nrb), F), dim3(kFarThreads), lds, st, a,
@@ -180,21 +183,23 @@ struct Far1 {
     }
 };
 
-template <typename T>
-static hipError_t far_single_t(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<T>& od,
-                               int dtype, void* y, hipStream_t st) {
-    FPDE_DISPATCH_DP(t.dim, t.p, Far1<T>::template far_out, a, t, fp, F, od, dtype, y, st);
+hipError_t launch_couple_single(const H2Tree& t, const FarPlan& fp, int F, const OpData<double>& od, hipStream_t st) {
+    FPDE_DISPATCH_DP(t.dim, t.p, Far1<double>::template couple, t, fp, F, od, st);
     return hipGetLastError();
 }
-
-hipError_t launch_far_single(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<double>& od,
-                             int dtype, void* y, hipStream_t st) {
-    return far_single_t<double>(a, t, fp, F, od, dtype, y, st);
+hipError_t launch_couple_single(const H2Tree& t, const FarPlan& fp, int F, const OpData<float>& od, hipStream_t st) {
+    FPDE_DISPATCH_DP(t.dim, t.p, Far1<float>::template couple, t, fp, F, od, st);
+    return hipGetLastError();
 }
-
-hipError_t launch_far_single(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<float>& od,
+hipError_t launch_out_single(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<double>& od,
                              int dtype, void* y, hipStream_t st) {
-    return far_single_t<float>(a, t, fp, F, od, dtype, y, st);
+    FPDE_DISPATCH_DP(t.dim, t.p, Far1<double>::template out, a, t, fp, F, od, dtype, y, st);
+    return hipGetLastError();
+}
+hipError_t launch_out_single(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<float>& od,
+                             int dtype, void* y, hipStream_t st) {
+    FPDE_DISPATCH_DP(t.dim, t.p, Far1<float>::template out, a, t, fp, F, od, dtype, y, st);
+    return hipGetLastError();
 }
 
 }  // namespace fpde

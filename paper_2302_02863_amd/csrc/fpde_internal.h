@@ -245,9 +245,11 @@ hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelP
 // far field of the one-vector apply after its upsweep (fpde_far1.hip): coupling
 // sums z^ per far target (od.St, od.xh -> od.zh), then the downsweep walk and
 // U y^ added to y
-hipError_t launch_far_single(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<double>& od,
+hipError_t launch_couple_single(const H2Tree& t, const FarPlan& fp, int F, const OpData<double>& od, hipStream_t st);
+hipError_t launch_couple_single(const H2Tree& t, const FarPlan& fp, int F, const OpData<float>& od, hipStream_t st);
+hipError_t launch_out_single(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<double>& od,
                              int dtype, void* y, hipStream_t st);
-hipError_t launch_far_single(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<float>& od,
+hipError_t launch_out_single(const ApplyPlan& a, const H2Tree& t, const FarPlan& fp, int F, const OpData<float>& od,
                              int dtype, void* y, hipStream_t st);
 
 // ---------------------------------------------------------------- apply, many right-hand sides (fpde_batched.hip)
