@@ -100,10 +100,21 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
         const int col = c0 + cl;
         const int64_t sys = (int64_t)f * R + col;
         if (kCoef) {
+            // the partials of the previous pass, summed by the whole block: row lanes
+            // stride over the blocks, then a fixed-order tree (same value in every block)
+            double pv = 0.0;
+            if (col < R)
+                for (int64_t b = rl; b < nb; b += nrl) pv += part_in[((int64_t)f * nb + b) * R + col];
+            red[t] = pv;
+            __syncthreads();
+            for (int s = nrl / 2; s >= 1; s >>= 1) {
+                if (rl < s) red[t] += red[t + s * RC];
+                __syncthreads();
+            }
             if (rl == 0) {   // per-system coefficient, once per column
                 double cf = 0.0;
                 if (col < R) {
-                    const double v = sum_parts(part_in, nb, R, sys);
+                    const double v = red[cl];
                     const bool act = c.active[sys] != 0;
                     if (OP == CG_UPDATE_UR) {
                         const bool ok = act && v > 0.0 && v == v;
