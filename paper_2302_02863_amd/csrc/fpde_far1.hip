@@ -16,7 +16,9 @@ constexpr int kFarThreads = 256;
 
 // Coupling (Sec. 5.2): z^(c) = sum over the far pairs (c, s) of S x^(s) for
 // every far target c.  The pairs of a target are cut into chunks of at most
-// NS pairs, one block per chunk, one pair per slot of G lanes (lane alpha):
+// NS pairs (their source clusters in the chunk record, so that the x^ gather
+// goes out with the S loads), one block per chunk, one pair per slot of G
+// lanes (lane alpha):
 // S[alpha][beta] x^(s)[beta] summed over beta, St holding S transposed
 // ([beta][alpha]) so that the lanes read consecutive entries, x^(s)[beta]
 // broadcast from lane beta of the slot.  The slots are summed in a fixed
@@ -34,7 +36,7 @@ __global__ __launch_bounds__(kCoupleThreads) void k_couple(H2Tree t, FarPlan fp,
     __shared__ T sred[kCoupleThreads];
     __shared__ int s_last;
     const int f = blockIdx.y;
-    const int64_t* ck = fp.chunks + 4 * (int64_t)blockIdx.x;
+    const int64_t* ck = fp.chunks + kChunkWords * (int64_t)blockIdx.x;
     const int64_t c = ck[0], e0 = ck[1], e1 = ck[2];
     const int ci = (int)(ck[3] >> 32), nch = (int)(ck[3] & 0xffffffff);
     const int64_t nfar = t.far_ptr[t.ncl];
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(kCoupleThreads) void k_couple(H2Tree t, FarPlan fp,
     const int64_t e = e0 + sl;
     T acc = 0;
     if (e < e1) {   // the lanes of a slot share e
-        const int64_t src = t.far_src[e];
+        const int64_t src = ck[4 + sl];   // the source cluster, carried by the chunk record
         const T* S = St + ((int64_t)f * nfar + e) * K * K + (al < K ? al : 0);
         T sv[K];
 #pragma unroll
@@ -83,11 +85,15 @@ __global__ __launch_bounds__(kCoupleThreads) void k_couple(H2Tree t, FarPlan fp,
 // Downsweep and output (Sec. 5.3): y[perm[row]] += U[row] . y^_leaf, where
 // y^ of a cluster is its z^ plus the transfer of its parent's y^, from level
 // ltop (the shallowest target) down.  One block per (leaf, 64 rows, field),
-// 256 threads, 4 lanes per row; the basis rows, output indices, old y values,
-// transfers and z^ of the root path are all fetched before the walk.
+// 256 threads, 4 lanes per row.  Rows are addressed by leaf slot (leaf li,
+// row i: slot li * cap + i, padded), so the basis rows (Upad) and output
+// indices (perm_pad, -1 for padding) are loaded at once; they, the old y
+// values, the transfers and z^ of the root path are all fetched before the
+// walk.
 template <int D, int P, typename T>
-__global__ __launch_bounds__(kFarThreads) void k_far_out(ApplyPlan a, H2Tree t, int ltop, const T* zh, const T* U,
-                                                           const T* E, int dtype, void* y) {
+__global__ __launch_bounds__(kFarThreads) void k_far_out(ApplyPlan a, H2Tree t, int ltop, const T* zh,
+                                                           const T* Upad, const int64_t* perm_pad, const T* E,
+                                                           int dtype, void* y) {
     constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
     extern __shared__ __align__(16) unsigned char sraw[];
     const int L = t.L, nlev = L + 1 - ltop;
@@ -113,19 +119,22 @@ __global__ __launch_bounds__(kFarThreads) void k_far_out(ApplyPlan a, H2Tree t, 
         const int i = threadIdx.x + q * kFarThreads;
         er[q] = i < nlev * EP ? E[(((leafc + 1) >> (L - (ltop + i / EP))) - 1) * EP + i % EP] : T(0);
     }
-    const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
+    // leaf slot rows: the basis rows and output indices need no leaf range first
     const int g = threadIdx.x & 3;
     const int64_t it = (int64_t)rb * 64 + (threadIdx.x >> 2);
-    const bool ok = it < nt;
+    const int64_t slot = li * a.cap + it;
+    const bool in = it < a.cap;
+    T u[(K + 3) / 4];
+#pragma unroll
+    for (int q = 0; q < (K + 3) / 4; ++q) u[q] = (in && 4 * q + g < K) ? Upad[slot * K + 4 * q + g] : T(0);
+    const int64_t pr = in ? perm_pad[slot] : -1;
+    const bool ok = pr >= 0;
     int64_t dst = 0;
     double yold = 0.0;
     if (ok && g == 0) {
-        dst = (int64_t)f * a.N + a.perm[lb + it];
+        dst = (int64_t)f * a.N + pr;
         yold = ldx(y, dst, dtype);
     }
-    T u[(K + 3) / 4];
-#pragma unroll
-    for (int q = 0; q < (K + 3) / 4; ++q) u[q] = (ok && 4 * q + g < K) ? U[(lb + it) * K + 4 * q + g] : T(0);
 #pragma unroll
     for (int q = 0; q < kZR; ++q) {
         const int i = threadIdx.x + q * kFarThreads;
@@ -166,6 +175,28 @@ static size_t path_lds(const H2Tree& t, int ltop) {
     return sizeof(T) * (size_t)((int64_t)(t.L + 1 - ltop) * (K + EP));
 }
 
+// Leaf-slot copies for the output kernel: Upad[li * cap + i] = U[leaf_beg[li] + i]
+// and perm_pad[li * cap + i] = perm[leaf_beg[li] + i] for i < the leaf's rows,
+// zeros and -1 beyond.
+FPDE_KERNEL void k_pad_rows(int64_t nleaf, int64_t cap, int k, const int64_t* leaf_beg, const double* U,
+                            const int64_t* perm, double* Upad, int64_t* perm_pad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaf * cap) return;
+    const int64_t li = i / cap, it = i % cap;
+    const int64_t lb = leaf_beg[li], nt = leaf_beg[li + 1] - lb;
+    const bool ok = it < nt;
+    perm_pad[i] = ok ? perm[lb + it] : -1;
+    for (int q = 0; q < k; ++q) Upad[i * k + q] = ok ? U[(lb + it) * k + q] : 0.0;
+}
+
+hipError_t launch_pad_rows(int64_t nleaf, int64_t cap, int k, const int64_t* leaf_beg, const double* U,
+                           const int64_t* perm, double* Upad, int64_t* perm_pad, hipStream_t st) {
+    if (nleaf * cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pad_rows, dim3(grid1(nleaf * cap)), dim3(256), 0, st, nleaf, cap, k, leaf_beg, U, perm, Upad,
+                       perm_pad);
+    return hipGetLastError();
+}
+
 template <typename T>
 struct Far1 {
     template <int D, int P>
@@ -179,7 +210,7 @@ struct Far1 {
         const int64_t nrb = (a.cap + 63) / 64;
         const size_t lds = path_lds<D, P, T>(t, fp.ltop);
         hipLaunchKernelGGL((k_far_out<D, P, T>), dim3((unsigned)(a.nleaf * nrb), F), dim3(kFarThreads), lds, st, a,
-                           t, fp.ltop, od.zh, od.U, od.E, dtype, y);
+                           t, fp.ltop, od.zh, od.Upad, fp.perm_pad, od.E, dtype, y);
     }
 };
 

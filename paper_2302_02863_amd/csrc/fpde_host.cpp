@@ -160,10 +160,12 @@ struct fpde_op {
     int64_t *d_far1_ptr = nullptr, *d_far1_src = nullptr;
     double* d_St1 = nullptr;               // [F][nfar1][k][k], transposed like d_St
     double* d_zp = nullptr;                // [F][nchunks][k] partial coupling sums
+    double* d_Upad = nullptr;              // [nleaf * cap][k] bases by leaf slot
+    int64_t* d_perm_pad = nullptr;         // [nleaf * cap] output index by leaf slot, -1 padding
     UpPlan up[2]{};                        // one-launch upsweep plan per precision (0 FP64, 1 FP32)
     FarPlan far_plan{};                    // far targets of the one-vector output kernel
     struct {                               // FP32 operator data of a mixed-precision operator
-        float *U = nullptr, *E = nullptr, *St = nullptr, *St1 = nullptr, *panel = nullptr;
+        float *U = nullptr, *E = nullptr, *St = nullptr, *St1 = nullptr, *panel = nullptr, *Upad = nullptr;
         float *xh = nullptr, *zh = nullptr, *zp = nullptr;   // workspace, one right-hand side
         float *xhR = nullptr, *yhR = nullptr;  // workspace [F][ncl][K][R]
     } f32;
@@ -955,16 +957,19 @@ void build_device(fpde_op& op) {
             for (int64_t c = 0; c < kt.ncl; ++c) fptr1[c + 1] += fptr1[c];
             op.nfar1 = (int64_t)src1.size();
             {   // coupling chunks: at most one pair per slot of a 512-thread block
-                const int64_t cs = 512 / (k <= 32 ? 32 : 64);
+                const int64_t cs = 512 / (k <= 32 ? 32 : 64);   // at most kChunkWords - 4
                 std::vector<int64_t> ck;
                 for (int64_t c = 0; c < kt.ncl; ++c) {
                     const int64_t p0 = fptr1[c], p1 = fptr1[c + 1];
                     if (p1 == p0) continue;
                     const int64_t nch = (p1 - p0 + cs - 1) / cs;
-                    for (int64_t j = 0; j < nch; ++j)
-                        ck.insert(ck.end(), {c, p0 + j * cs, std::min(p1, p0 + (j + 1) * cs), (j << 32) | nch});
+                    for (int64_t j = 0; j < nch; ++j) {
+                        const int64_t e0 = p0 + j * cs, e1 = std::min(p1, p0 + (j + 1) * cs);
+                        ck.insert(ck.end(), {c, e0, e1, (j << 32) | nch});
+                        for (int64_t q = 0; q < kChunkWords - 4; ++q) ck.push_back(e0 + q < e1 ? src1[e0 + q] : 0);
+                    }
                 }
-                op.far_plan.nchunks = (int64_t)ck.size() / 4;
+                op.far_plan.nchunks = (int64_t)ck.size() / kChunkWords;
                 op.far_plan.chunks = A.upload(ck, st);
                 op.far_plan.ctk = A.alloc<unsigned int>((int64_t)F * kt.ncl);
                 hipck(hipMemsetAsync(op.far_plan.ctk, 0, sizeof(unsigned int) * F * kt.ncl, st), "coupling tickets");
@@ -990,6 +995,11 @@ void build_device(fpde_op& op) {
         }
         op.ls2 = kt.L;
         while (op.ls2 > 0 && !multi_fits(h, op.ls2, 1)) --op.ls2;
+        // bases and output indices by leaf slot for the one-vector output kernel
+        op.d_Upad = A.alloc<double>(kt.nleaf() * op.cap * k);
+        op.far_plan.perm_pad = op.d_perm_pad = A.alloc<int64_t>(kt.nleaf() * op.cap);
+        hipck(launch_pad_rows(kt.nleaf(), op.cap, k, op.d_leaf_beg, op.d_U, op.kdev.perm, op.d_Upad, op.d_perm_pad, st),
+              "leaf slots");
         op.d_tickets = A.alloc<unsigned int>((int64_t)F * kt.ncl);
         hipck(hipMemsetAsync(op.d_tickets, 0, sizeof(unsigned int) * F * kt.ncl, st), "tickets");
         if (op.mixed) {   // FP32 copies of the bases, transfers, coupling matrices and panels
@@ -998,6 +1008,8 @@ void build_device(fpde_op& op) {
             op.f32.E = A.alloc<float>(nE);
             op.f32.St = A.alloc<float>(nS);
             op.f32.St1 = A.alloc<float>((int64_t)F * op.nfar1 * k * k);
+            op.f32.Upad = A.alloc<float>(kt.nleaf() * op.cap * k);
+            hipck(launch_to_float(kt.nleaf() * op.cap * k, op.d_Upad, op.f32.Upad, st), "to float");
             op.f32.panel = A.alloc<float>((int64_t)F * op.panel_total);
             hipck(launch_to_float(nU, op.d_U, op.f32.U, st), "to float");
             hipck(launch_to_float(nE, op.kdev.E, op.f32.E, st), "to float");
@@ -1116,11 +1128,12 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
         h1.far_ptr = op.d_far1_ptr;
         h1.far_src = op.d_far1_src;
         if (f32) {
-            OpData<float> od{op.f32.U, op.f32.E, op.f32.St1, op.f32.panel, op.f32.xh, op.f32.zh, op.f32.zp};
+            OpData<float> od{op.f32.U, op.f32.E, op.f32.St1, op.f32.panel, op.f32.xh, op.f32.zh, op.f32.zp,
+                             op.f32.Upad};
             return launch_apply_single(a, h1, pp, op.up[1], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets,
                                        s0, ev);
         }
-        OpData<double> od{op.d_U, op.kdev.E, op.d_St1, op.d_panel, op.d_xh, op.d_zh, op.d_zp};
+        OpData<double> od{op.d_U, op.kdev.E, op.d_St1, op.d_panel, op.d_xh, op.d_zh, op.d_zp, op.d_Upad};
         return launch_apply_single(a, h1, pp, op.up[0], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets, s0,
                                    ev);
     }

@@ -200,6 +200,7 @@ struct OpData {
     T* xh;            // [F][ncl][K] workspace: upsweep coefficients x^
     T* zh;            // [F][ncl][K] coupling sums z^ per target cluster, zero for the others
     T* zp;            // [F][nchunks][K] partial sums of targets split in several coupling chunks
+    const T* Upad;    // [nleaf * cap][K] bases by leaf slot (rows of leaf li at li * cap, zero padded)
 };
 // One-launch upsweep: leaf-stage subtree depth d0, upper-stage depth ds
 struct UpPlan {
@@ -209,15 +210,18 @@ struct UpPlan {
     bool ok;
 };
 // Far targets of the single-vector output kernel
+constexpr int kChunkWords = 4 + 16;
 struct FarPlan {
     const int64_t* tgt;    // [ntgt] clusters with incoming far pairs, in heap order
     int64_t ntgt;
     int ltop;              // level of the shallowest target
     // coupling work: chunks of at most one pair per slot of a coupling block,
-    // 4 words each: target, first pair, end pair, (chunk of the target << 32 | chunks of the target)
+    // kChunkWords words each: target, first pair, end pair, (chunk of the target << 32 |
+    // chunks of the target), then the source cluster of each pair of the chunk
     const int64_t* chunks;
     int64_t nchunks;
     unsigned int* ctk;     // [F][ncl] zero-initialised tickets of targets split in several chunks
+    const int64_t* perm_pad;   // [nleaf * cap] output index by leaf slot, -1 for padding
 };
 UpPlan plan_up_tree(const H2Tree& t, int64_t cap, int lmin, int prec /*0 double, 1 float*/);
 hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const int64_t* near_ptr,
@@ -242,6 +246,9 @@ hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelP
                                int dtype, const void* x, void* y, unsigned int* tickets, hipStream_t st,
                                hipEvent_t* ev);
 
+// leaf-slot copies of the bases and the output indices (fpde_far1.hip)
+hipError_t launch_pad_rows(int64_t nleaf, int64_t cap, int k, const int64_t* leaf_beg, const double* U,
+                           const int64_t* perm, double* Upad, int64_t* perm_pad, hipStream_t st);
 // far field of the one-vector apply after its upsweep (fpde_far1.hip): coupling
 // sums z^ per far target (od.St, od.xh -> od.zh), then the downsweep walk and
 // U y^ added to y
