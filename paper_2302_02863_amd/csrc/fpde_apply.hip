@@ -193,10 +193,13 @@ __device__ __forceinline__ void up_tree(const ApplyPlan& a, const H2Tree& t, con
 }
 
 // Near rows: y[f][perm[row]] = (B+M)_row . x + panel_row . x_near for the
-// rows of block rb of leaf li, 16 lanes per row (blockDim / 16 rows).  The x entries of the leaf's
-// near columns are staged in LDS once per block.  Each lane keeps 8 vector
-// loads of its panel row in flight; the first 8 are issued before the x
-// staging and the CSR row, so their latency overlaps those gathers.
+// rows of block rb of leaf li, 16 lanes per row (blockDim / 16 rows).  Rows are
+// addressed by leaf slot (li * cap + row in the leaf), so every index a lane
+// needs is one load away: the padded panel column list, the ELL row of B + M
+// and the output index.  The x entries of the leaf's near columns are staged in
+// LDS once per block.  Each lane keeps 8 vector loads of its panel row in
+// flight; the first 8 are issued before the x staging and the B + M row, so
+// their latency overlaps those gathers.
 template <typename T>
 __device__ __forceinline__ void near_rows(const ApplyPlan& a, const PanelPlan& pp, const T* panel, int use_near,
                                           const double* csr_val, int dtype, const void* x, void* y, int f,
@@ -210,28 +213,41 @@ __device__ __forceinline__ void near_rows(const ApplyPlan& a, const PanelPlan& p
     const int64_t xo = (int64_t)f * a.N;
     const int g = threadIdx.x & 15;
     const int64_t it = (int64_t)rb * rpb + (threadIdx.x >> 4);
-    const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
-    const bool ok = it < nt;
-    const int64_t row = lb + it;
+    const bool in = it < a.cap;   // panels hold cap rows per leaf; rows past the leaf's are never stored
+    const int64_t slot = li * a.cap + it;
     const int64_t ps = use_near ? pp.pstride[li] : 0;
     const T* pr = panel + (int64_t)f * pp.poff[a.nleaf] + pp.poff[li] + it * ps + 2 * g;
     V2 q[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k)
-        if (ok && 2 * g + 32 * k + 2 <= ps) q[k] = *(const V2*)(pr + 32 * k);
+        if (in && 2 * g + 32 * k + 2 <= ps) q[k] = *(const V2*)(pr + 32 * k);
     if (use_near) {   // padding columns of the row stride hold 0 in the panel and in xs
-        const int64_t c0 = pp.pcols_ptr[li], ncols = pp.pcols_ptr[li + 1] - c0;
-        for (int64_t c = threadIdx.x; c < ps; c += blockDim.x)
-            xs[c] = c < ncols ? (T)ldx(x, xo + pp.pcols[c0 + c], dtype) : T(0);
+        const int32_t* pc = pp.pcols_pad + li * pp.max_stride;
+        for (int64_t c = threadIdx.x; c < ps; c += blockDim.x) {
+            const int j = pc[c];
+            xs[c] = j >= 0 ? (T)ldx(x, xo + j, dtype) : T(0);
+        }
     }
+    const int64_t dst = in ? pp.perm_pad[slot] : -1;
     double acc = 0.0;
-    if (ok && csr_val) {
+    if (pp.ell_val) {   // B + M in ELL form, entries in CSR order
+        if (in) {
+            const int w = pp.ell_w;
+            const int32_t* ec = pp.ell_col + slot * w;
+            const double* ev = pp.ell_val + ((int64_t)f * a.nleaf * a.cap + slot) * w;
+            for (int e = g; e < w; e += 16) {
+                const int j = ec[e];
+                if (j >= 0) acc += ev[e] * ldx(x, xo + j, dtype);
+            }
+        }
+    } else if (in && csr_val && dst >= 0) {
         const double* v = csr_val + (int64_t)f * a.nnz;
+        const int64_t row = a.leaf_beg[li] + it;
         for (int64_t e = a.csr_ptr[row] + g; e < a.csr_ptr[row + 1]; e += 16)
             acc += v[e] * ldx(x, xo + pp.csr_col_dof[e], dtype);
     }
     __syncthreads();
-    if (!ok) return;
+    if (dst < 0) return;
     if (use_near) {
         T s[4] = {0, 0, 0, 0};
         const T* xl = xs + 2 * g;
@@ -251,9 +267,8 @@ __device__ __forceinline__ void near_rows(const ApplyPlan& a, const PanelPlan& p
     }
     for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
     if (g == 0) {
-        const int64_t dst = xo + a.perm[row];
-        if (dtype == 0) ((double*)y)[dst] = acc;
-        else ((float*)y)[dst] = (float)acc;
+        if (dtype == 0) ((double*)y)[xo + dst] = acc;
+        else ((float*)y)[xo + dst] = (float)acc;
     }
 }
 

@@ -189,6 +189,21 @@ FPDE_KERNEL void k_pad_rows(int64_t nleaf, int64_t cap, int k, const int64_t* le
     for (int q = 0; q < k; ++q) Upad[i * k + q] = ok ? U[(lb + it) * k + q] : 0.0;
 }
 
+// ELL values of B + M by leaf slot: out[f][i] = val[f][src[i]], 0 where src[i] < 0
+FPDE_KERNEL void k_ell_values(int64_t n, int F, int64_t nnz, const int64_t* src, const double* val, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t e = src[i];
+    for (int f = 0; f < F; ++f) out[(int64_t)f * n + i] = e >= 0 ? val[(int64_t)f * nnz + e] : 0.0;
+}
+
+hipError_t launch_ell_values(int64_t n, int F, int64_t nnz, const int64_t* src, const double* val, double* out,
+                             hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ell_values, dim3(grid1(n)), dim3(256), 0, st, n, F, nnz, src, val, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_pad_rows(int64_t nleaf, int64_t cap, int k, const int64_t* leaf_beg, const double* U,
                            const int64_t* perm, double* Upad, int64_t* perm_pad, hipStream_t st) {
     if (nleaf * cap == 0) return hipSuccess;

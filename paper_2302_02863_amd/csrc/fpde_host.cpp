@@ -153,6 +153,11 @@ struct fpde_op {
     int64_t *d_poff = nullptr, *d_pstride = nullptr, *d_pcols_ptr = nullptr;
     int32_t* d_pcols = nullptr;
     int64_t panel_max_stride = 0, panel_total = 0;
+    // by leaf slot for the one-vector near rows: panel columns and the ELL form of B + M
+    int32_t* d_pcols_pad = nullptr;        // [nleaf][panel_max_stride], -1 padding
+    int32_t* d_ell_col = nullptr;          // [nleaf * cap][ell_w] dof columns, -1 padding
+    double* d_ell_val = nullptr;           // [F][nleaf * cap][ell_w] values of B + M
+    int ell_w = 0;
     unsigned int* d_tickets = nullptr;     // [F][ncl] ticket counters of the one-vector upsweep (self-resetting)
     double* d_zh = nullptr;                // [F][ncl][k] coupling sums of the one-vector apply
     // far list of the one-vector apply, sources moved down to the upsweep's subtree levels
@@ -840,6 +845,13 @@ void build_device(fpde_op& op) {
             op.d_pstride = A.upload(pstride, st);
             op.d_pcols_ptr = A.upload(pcols_ptr, st);
             op.d_pcols = A.upload(pcols, st);
+            {
+                std::vector<int32_t> pad((size_t)nleaf * op.panel_max_stride, -1);
+                for (int64_t li = 0; li < nleaf; ++li)
+                    std::copy(pcols.begin() + pcols_ptr[li], pcols.begin() + pcols_ptr[li + 1],
+                              pad.begin() + li * op.panel_max_stride);
+                op.d_pcols_pad = A.upload(pad, st);
+            }
             op.d_panel = A.alloc<double>((int64_t)F * op.panel_total);
             hipck(launch_pack_panels(nleaf, op.cap, np.npairs, op.d_near_ptr, op.d_near_src, op.d_leaf_beg, d_pcol_off,
                                      op.d_poff, op.d_pstride, op.d_pcols_ptr, op.d_near, F, op.d_panel, st), "pack");
@@ -895,6 +907,32 @@ void build_device(fpde_op& op) {
         std::vector<int32_t> cdof(op.csr_col.size());
         for (size_t e = 0; e < cdof.size(); ++e) cdof[e] = (int32_t)kt.perm[op.csr_col[e]];
         op.d_csr_col_dof = A.upload(cdof, st);
+        {   // ELL form of B + M by leaf slot, entries in CSR order; kept only while the padding costs
+            // at most half again the CSR's entries
+            int64_t w = 0;
+            for (int64_t i = 0; i < m.N; ++i) w = std::max(w, op.csr_ptr[i + 1] - op.csr_ptr[i]);
+            w = (w + 3) / 4 * 4;
+            const int64_t nslot = nleaf * op.cap;
+            if (w > 0 && nslot * w <= nnz + nnz / 2 + 4 * nslot) {
+                std::vector<int32_t> ecol((size_t)(nslot * w), -1);
+                std::vector<int64_t> esrc((size_t)(nslot * w), -1);
+                for (int64_t li = 0; li < nleaf; ++li)
+                    for (int64_t row = leaf_beg[li]; row < leaf_beg[li + 1]; ++row) {
+                        const int64_t o = (li * op.cap + row - leaf_beg[li]) * w;
+                        for (int64_t e = op.csr_ptr[row]; e < op.csr_ptr[row + 1]; ++e) {
+                            ecol[o + e - op.csr_ptr[row]] = cdof[e];
+                            esrc[o + e - op.csr_ptr[row]] = e;
+                        }
+                    }
+                op.ell_w = (int)w;
+                op.d_ell_col = A.upload(ecol, st);
+                int64_t* d_esrc = A.upload(esrc, st);
+                op.d_ell_val = A.alloc<double>((int64_t)F * nslot * w);
+                hipck(launch_ell_values(nslot * w, F, nnz, d_esrc, op.d_BM, op.d_ell_val, st), "ELL values");
+                hipck(hipStreamSynchronize(st), "ELL sync");
+                A.release(d_esrc);
+            }
+        }
         // launch plans: the one-launch upsweep of the single-vector apply (per
         // precision) and the subtree-root level of the multi-RHS far chain.
         // FPDE_MAX_SUBTREE_DEPTH caps the subtree depths (exercises the deep
@@ -1122,7 +1160,14 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
     const bool f32 = op.mixed && !(parts & FPDE_PART_FP64);
     const int pr = f32 ? 1 : 0;
     const size_t esz = f32 ? sizeof(float) : sizeof(double);
-    const PanelPlan pp{op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr, op.panel_max_stride, op.d_csr_col_dof};
+    PanelPlan pp{op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr, op.panel_max_stride, op.d_csr_col_dof};
+    pp.pcols_pad = op.d_pcols_pad;
+    pp.perm_pad = op.d_perm_pad;
+    if (cv == op.d_BM) {
+        pp.ell_col = op.d_ell_col;
+        pp.ell_val = op.d_ell_val;
+        pp.ell_w = op.ell_w;
+    }
     if (R == 1 && op.up[pr].ok && op.panel_max_stride * (int64_t)esz <= 64 * 1024) {
         H2Tree h1 = h;   // the far list with sources moved down
         h1.far_ptr = op.d_far1_ptr;

@@ -189,6 +189,12 @@ struct PanelPlan {
     const int64_t* pcols_ptr;   // [nleaf+1]
     int64_t max_stride;
     const int32_t* csr_col_dof; // CSR columns of B + M as dof indices
+    // by leaf slot (leaf li, row it -> slot li * cap + it), read by the one-vector apply:
+    const int32_t* pcols_pad = nullptr;  // [nleaf][max_stride] panel column dofs, -1 past the leaf's columns
+    const int64_t* perm_pad = nullptr;   // [nleaf * cap] output index, -1 for slots past the leaf's rows
+    const int32_t* ell_col = nullptr;    // [nleaf * cap][ell_w] dof columns of B + M in CSR order, -1 padding
+    const double* ell_val = nullptr;     // [F][nleaf * cap][ell_w] values of B + M; null: use the CSR
+    int ell_w = 0;
 };
 // Operator data of one precision used by the single-vector apply
 template <typename T>
@@ -247,6 +253,8 @@ hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelP
                                hipEvent_t* ev);
 
 // leaf-slot copies of the bases and the output indices (fpde_far1.hip)
+hipError_t launch_ell_values(int64_t n, int F, int64_t nnz, const int64_t* src, const double* val, double* out,
+                             hipStream_t st);
 hipError_t launch_pad_rows(int64_t nleaf, int64_t cap, int k, const int64_t* leaf_beg, const double* U,
                            const int64_t* perm, double* Upad, int64_t* perm_pad, hipStream_t st);
 // far field of the one-vector apply after its upsweep (fpde_far1.hip): coupling
