@@ -197,15 +197,16 @@ __device__ __forceinline__ void up_tree(const ApplyPlan& a, const H2Tree& t, con
 // addressed by leaf slot (li * cap + row in the leaf), so every index a lane
 // needs is one load away: the padded panel column list, the ELL row of B + M
 // and the output index.  The x entries of the leaf's near columns are staged in
-// LDS once per block.  Each lane keeps 8 vector loads of its panel row in
-// flight; the first 8 are issued before the x staging and the B + M row, so
+// LDS once per block.  Each lane keeps 12 vector loads of its panel row in
+// flight (384 columns a batch, so a leaf with 3 x 3 near leaves of 64 rows
+// takes two batches); the first 12 are issued before the x staging and the B + M row, so
 // their latency overlaps those gathers.
 template <typename T>
 __device__ __forceinline__ void near_rows(const ApplyPlan& a, const PanelPlan& pp, const T* panel, int use_near,
                                           const double* csr_val, int dtype, const void* x, void* y, int f,
                                           int64_t bid, T* xs) {
     using V2 = typename Vec2<T>::type;
-    constexpr int NB = 8;   // vector loads in flight per lane (32 columns apart)
+    constexpr int NB = 12;   // vector loads in flight per lane (32 columns apart)
     const int rpb = blockDim.x / 16;   // rows per block
     const int64_t nrb = (a.cap + rpb - 1) / rpb;
     const int64_t li = bid / nrb;
