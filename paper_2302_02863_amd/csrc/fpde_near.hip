@@ -55,104 +55,208 @@ hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const 
 // block per (leaf, 64-row tile, 64-column tile of right-hand sides, field).
 // The panel times the gathered rows of X is a dense GEMM of 64 x 64 x
 // pstride; four waves each own a 32 x 32 quarter of the tile:
-//   FP32 operator data: v_mfma_f32_32x32x2f32 (lane l supplies A[l%32][l/32],
-//     B[l/32][l%32]; accumulator v holds C[8(v/4) + 4(l/32) + v%4][l%32]);
-//   FP64: 2 x 2 tiles of v_mfma_f64_16x16x4f64 (A[l%16][l/16], B[l/16][l%16];
-//     accumulator v holds C[l/16 + 4v][l%16]).
-// Chunks of 32 panel columns and the matching 32 rows of X are staged in LDS.
-// The tile is then written to LDS and each thread adds the CSR row of B + M
-// (FP64) for one right-hand side and writes y.
+//   FP32 operator data: v_mfma_f32_32x32x2f32, two k per step (lane l supplies
+//     A[l%32][l/32], B[l/32][l%32]; accumulator v holds C[8(v/4) + 4(l/32) + v%4][l%32]);
+//   FP64: 2 x 2 tiles of v_mfma_f64_16x16x4f64, four k per step (A[l%16][l/16],
+//     B[l/16][l%16]; accumulator v holds C[l/16 + 4v][l%16]).
+// Chunks of 32 panel columns and the matching 32 rows of X go global ->
+// registers -> LDS with 16-byte loads, so that every wave instruction reads
+// whole cache lines; the next chunk's loads are in flight during the MFMAs.
+// The panel chunk is stored in LDS with its columns permuted (column KS*s + g
+// of the chunk at position g*(32/KS) + s, KS = k per step), so each lane reads
+// the A values of all its steps with 16-byte LDS reads; X stays row-major.  The
+// leaf's panel column list is staged in LDS once.  The tile then goes to LDS
+// and each thread adds the B + M row (FP64; the ELL form by leaf slot when the
+// operator holds it) for one right-hand side and writes y.
 typedef float fpde_f32x16 __attribute__((ext_vector_type(16)));
 typedef double fpde_f64x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 constexpr int kMT = 64, kNT = 64, kKC = 32;
-constexpr int kApS = kKC + 1;   // LDS row strides (padding against bank conflicts)
-constexpr int kBxS = kNT + 1;
-constexpr int kCS = kNT + 1;
-
+constexpr int kCS = kNT + 1;          // LDS row stride of the output tile
+constexpr int kStageCols = 4096;      // longest panel column list staged in LDS
 template <typename T>
-__device__ __forceinline__ T ldt(const void* x, int64_t i, int dtype) {
-    return dtype == 0 ? (T)((const double*)x)[i] : (T)((const float*)x)[i];
+struct MM;
+template <>
+struct MM<float> {
+    static constexpr int KS = 2;          // k per MFMA step
+    static constexpr int SA = kKC + 4;    // LDS row strides: 16-byte aligned rows, no bank
+    static constexpr int SB = kNT + 32;   // conflicts for the MFMA operand reads
+    using V = float4;
+};
+template <>
+struct MM<double> {
+    static constexpr int KS = 4;
+    static constexpr int SA = kKC + 2;
+    static constexpr int SB = kNT + 16;
+    using V = double2;
+};
+template <typename T>
+constexpr size_t mm_tile_elems() {
+    const size_t g = (size_t)kMT * MM<T>::SA + (size_t)kKC * MM<T>::SB;
+    const size_t c = (size_t)kMT * kCS;
+    return g > c ? g : c;
 }
 }  // namespace
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, const T* panel, int use_near,
-                                                 const double* csr_val, int F, int R, int dtype, const void* x,
-                                                 void* y) {
+__global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, const T* __restrict__ panel,
+                                                 int use_near, const double* __restrict__ csr_val,
+                                                 const int32_t* __restrict__ ell_col,
+                                                 const double* __restrict__ ell_val, int F, int R, int dtype,
+                                                 const void* __restrict__ x, void* __restrict__ y) {
+    constexpr int KS = MM<T>::KS, NS = kKC / KS, SA = MM<T>::SA, SB = MM<T>::SB;
+    constexpr int VW = 16 / sizeof(T);               // elements of a 16-byte vector
+    constexpr int NA = kMT * kKC / VW / 256;          // panel vectors per thread and chunk
+    using V = typename MM<T>::V;
     extern __shared__ __align__(16) unsigned char sraw[];
-    T* Ap = (T*)sraw;                       // [kMT][kApS]
-    T* Bx = Ap + kMT * kApS;                // [kKC][kBxS]
-    T* Cs = Ap;                             // [kMT][kCS] after the GEMM
+    T* Ap = (T*)sraw;                       // [kMT][SA], permuted columns
+    T* Bx = Ap + kMT * SA;                  // [kKC][SB]
+    T* Cs = (T*)sraw;                       // [kMT][kCS] after the GEMM
+    int32_t* pcs = (int32_t*)(sraw + sizeof(T) * mm_tile_elems<T>());   // staged panel column dofs
     const int f = blockIdx.y;
     const int64_t nrt = (a.cap + kMT - 1) / kMT, nct = (R + kNT - 1) / kNT;
     const int64_t li = blockIdx.x / (nrt * nct);
     const int64_t rem = blockIdx.x % (nrt * nct);
     const int64_t row0 = (rem / nct) * kMT;   // first panel row of the tile
     const int r0 = (int)(rem % nct) * kNT;    // first right-hand side
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;   // the wave's quarter
-    const int64_t lb = a.leaf_beg[li], nt = a.leaf_beg[li + 1] - lb;
     const int64_t xo = (int64_t)f * a.N * R;
     fpde_f32x16 c32 = {0};
     fpde_f64x4 c64[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
     if (use_near) {
         const int64_t ps = pp.pstride[li];
-        const int64_t cb = pp.pcols_ptr[li], ncols = pp.pcols_ptr[li + 1] - cb;
+        const int32_t* pcg = pp.pcols_pad + li * pp.max_stride;   // -1 past the leaf's columns
+        const bool staged = pp.max_stride <= kStageCols;
+        if (staged) {
+            for (int64_t c = tid; c < ps; c += 256) pcs[c] = pcg[c];
+            __syncthreads();
+        }
         const T* pl = panel + (int64_t)f * pp.poff[a.nleaf] + pp.poff[li];
-        // this thread's share of a chunk: panel row tid/4, columns (tid%4)*8..+8;
-        // X row for column tid/8, right-hand sides (tid%8)*8..+8
-        const int pr_ = tid >> 2, pc_ = (tid & 3) * 8;
-        const int xk_ = tid >> 3, xr_ = (tid & 7) * 8;
-        const int64_t prow = row0 + pr_;
-        T pa[8], xa[8];
+        const bool xv = (R & 3) == 0;   // X rows start 16-byte aligned
+        V pa[NA];
+        T xa[8];
+        // X chunk element k of this thread: FP32 source (and the scalar fallback)
+        // 2 x 4 consecutive right-hand sides, FP64 source 4 x 2
+        auto xpos32 = [&](int i, int& xr, int& rv) { const int v = tid + 256 * i; xr = v >> 4; rv = (v & 15) * 4; };
+        auto xpos64 = [&](int i, int& xr, int& rv) { const int v = tid + 256 * i; xr = v >> 5; rv = (v & 31) * 2; };
         auto fetch = [&](int64_t k0) {   // global -> registers (next chunk, in flight during the MFMAs)
-            const int64_t col = k0 + pc_;
-            if (prow < a.cap && col + 8 <= ps) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) pa[j] = pl[prow * ps + col + j];
+            for (int i = 0; i < NA; ++i) {
+                const int v = tid + 256 * i;
+                const int64_t row = row0 + v / (kKC / VW), col = k0 + (v % (kKC / VW)) * VW;
+                if (row < a.cap && col < ps) pa[i] = *(const V*)(pl + row * ps + col);
+                else pa[i] = V{};
+            }
+            if (xv && dtype == 1) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    int xr, rv;
+                    xpos32(i, xr, rv);
+                    const int64_t c = k0 + xr;
+                    const int dof = c < ps ? (staged ? pcs[c] : pcg[c]) : -1;
+                    float4 q = {0.f, 0.f, 0.f, 0.f};
+                    if (dof >= 0 && r0 + rv < R) q = *(const float4*)((const float*)x + xo + (int64_t)dof * R + r0 + rv);
+                    xa[4 * i] = (T)q.x; xa[4 * i + 1] = (T)q.y; xa[4 * i + 2] = (T)q.z; xa[4 * i + 3] = (T)q.w;
+                }
+            } else if (xv) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int xr, rv;
+                    xpos64(i, xr, rv);
+                    const int64_t c = k0 + xr;
+                    const int dof = c < ps ? (staged ? pcs[c] : pcg[c]) : -1;
+                    double2 q = {0.0, 0.0};
+                    if (dof >= 0 && r0 + rv < R) q = *(const double2*)((const double*)x + xo + (int64_t)dof * R + r0 + rv);
+                    xa[2 * i] = (T)q.x; xa[2 * i + 1] = (T)q.y;
+                }
             } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) pa[j] = (prow < a.cap && col + j < ps) ? pl[prow * ps + col + j] : T(0);
-            }
-            const int64_t xc = k0 + xk_;
-            const int64_t dof = xc < ncols ? pp.pcols[cb + xc] : -1;
-            const int64_t xi = xo + dof * R + r0 + xr_;
+                for (int i = 0; i < 2; ++i) {
+                    int xr, rv;
+                    xpos32(i, xr, rv);
+                    const int64_t c = k0 + xr;
+                    const int dof = c < ps ? (staged ? pcs[c] : pcg[c]) : -1;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) xa[j] = (dof >= 0 && r0 + xr_ + j < R) ? ldt<T>(x, xi + j, dtype) : T(0);
+                    for (int j = 0; j < 4; ++j)
+                        xa[4 * i + j] = (dof >= 0 && r0 + rv + j < R)
+                                            ? (T)ldx(x, xo + (int64_t)dof * R + r0 + rv + j, dtype) : T(0);
+                }
+            }
         };
         fetch(0);
         for (int64_t k0 = 0; k0 < ps; k0 += kKC) {
             __syncthreads();   // the previous chunk's MFMAs are done with the LDS tiles
+            // panel chunk -> LDS, columns permuted
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                Ap[pr_ * kApS + pc_ + j] = pa[j];
-                Bx[xk_ * kBxS + xr_ + j] = xa[j];
+            for (int i = 0; i < NA; ++i) {
+                const int v = tid + 256 * i;
+                const int row = v / (kKC / VW), c = (v % (kKC / VW)) * VW;
+                if constexpr (sizeof(T) == 4) {   // columns c..c+3 = (g 0, s), (1, s), (0, s+1), (1, s+1)
+                    const int s0 = c / 2;
+                    *(float2*)(Ap + row * SA + s0) = float2{pa[i].x, pa[i].z};
+                    *(float2*)(Ap + row * SA + NS + s0) = float2{pa[i].y, pa[i].w};
+                } else {                          // columns c, c+1 = (c%4, c/4), (c%4 + 1, c/4)
+                    Ap[row * SA + (c % 4) * NS + c / 4] = pa[i].x;
+                    Ap[row * SA + (c % 4 + 1) * NS + c / 4] = pa[i].y;
+                }
+            }
+            // X chunk -> LDS, row-major
+            if (xv && dtype != 1) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int xr, rv;
+                    xpos64(i, xr, rv);
+                    Bx[xr * SB + rv] = xa[2 * i];
+                    Bx[xr * SB + rv + 1] = xa[2 * i + 1];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    int xr, rv;
+                    xpos32(i, xr, rv);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) Bx[xr * SB + rv + j] = xa[4 * i + j];
+                }
             }
             __syncthreads();
             if (k0 + kKC < ps) fetch(k0 + kKC);
             if constexpr (sizeof(T) == 4) {
+                const int g = lane >> 5, i32 = lane & 31;
+                const float4* ar = (const float4*)(Ap + (wr + i32) * SA + g * NS);
+                float4 a4[4];
 #pragma unroll
-                for (int k = 0; k < kKC; k += 2) {
-                    const float av = Ap[(wr + (lane & 31)) * kApS + k + (lane >> 5)];
-                    const float bv = Bx[(k + (lane >> 5)) * kBxS + wc + (lane & 31)];
-                    c32 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, c32, 0, 0, 0);
+                for (int q = 0; q < 4; ++q) a4[q] = ar[q];
+                const float av[16] = {a4[0].x, a4[0].y, a4[0].z, a4[0].w, a4[1].x, a4[1].y, a4[1].z, a4[1].w,
+                                      a4[2].x, a4[2].y, a4[2].z, a4[2].w, a4[3].x, a4[3].y, a4[3].z, a4[3].w};
+#pragma unroll
+                for (int st = 0; st < NS; ++st) {
+                    const float bv = Bx[(KS * st + g) * SB + wc + i32];
+                    c32 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[st], bv, c32, 0, 0, 0);
                 }
             } else {
+                const int g = lane >> 4, i16 = lane & 15;
+                const double2* ar0 = (const double2*)(Ap + (wr + i16) * SA + g * NS);
+                const double2* ar1 = (const double2*)(Ap + (wr + 16 + i16) * SA + g * NS);
 #pragma unroll
-                for (int k = 0; k < kKC; k += 4) {
-                    double av[2], bv[2];
+                for (int q = 0; q < NS / 2; ++q) {   // two steps per 16-byte read of A
+                    const double2 a0 = ar0[q], a1 = ar1[q];
 #pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        av[i] = Ap[(wr + 16 * i + (lane & 15)) * kApS + k + (lane >> 4)];
-                        bv[i] = Bx[(k + (lane >> 4)) * kBxS + wc + 16 * i + (lane & 15)];
+                    for (int h = 0; h < 2; ++h) {
+                        const int st = 2 * q + h;
+                        const double av[2] = {h ? a0.y : a0.x, h ? a1.y : a1.x};
+                        double bv[2];
+#pragma unroll
+                        for (int tj = 0; tj < 2; ++tj) bv[tj] = Bx[(KS * st + g) * SB + wc + 16 * tj + i16];
+#pragma unroll
+                        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                            for (int tj = 0; tj < 2; ++tj)
+                                c64[ti][tj] =
+                                    __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], c64[ti][tj], 0, 0, 0);
                     }
-#pragma unroll
-                    for (int i = 0; i < 2; ++i)
-#pragma unroll
-                        for (int j = 0; j < 2; ++j)
-                            c64[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c64[i][j], 0, 0, 0);
                 }
             }
         }
@@ -173,18 +277,35 @@ __global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, cons
                     Cs[(wr + 16 * i + (lane >> 4) + 4 * v) * kCS + wc + 16 * j + (lane & 15)] = c64[i][j][v];
     }
     __syncthreads();
-    // CSR rows of B + M and the output: thread -> one rhs, rows strided by 4 (a wave
-    // shares each row, so the column and value loads are uniform across it)
+    // B + M rows and the output: thread -> one right-hand side, rows strided by
+    // 4; a wave shares each row, so its column and value loads are uniform
     const int rc = tid & 63;
     const int r = r0 + rc;
     if (r >= R) return;
-    for (int rr = tid >> 6; rr < kMT; rr += 4) {
+    const int64_t nslot = a.nleaf * a.cap;
+    for (int rr = wv; rr < kMT; rr += 4) {
         const int64_t it = row0 + rr;
-        if (it >= nt) break;
-        const int64_t row = lb + it;
+        if (it >= a.cap) break;
+        const int64_t slot = li * a.cap + it;
+        const int64_t dst = pp.perm_pad[slot];
+        if (dst < 0) break;   // slots past the leaf's rows come last
         double acc = (double)Cs[rr * kCS + rc];
-        if (csr_val) {
+        if (ell_val) {
+            const int w = pp.ell_w;   // a multiple of 4
+            const int32_t* ec = ell_col + slot * w;
+            const double* ev = ell_val + ((int64_t)f * nslot + slot) * w;
+            double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            for (int e = 0; e < w; e += 4) {   // four independent gathers in flight
+                const int j0 = ec[e], j1 = ec[e + 1], j2 = ec[e + 2], j3 = ec[e + 3];
+                if (j0 >= 0) acc += ev[e] * ldx(x, xo + (int64_t)j0 * R + r, dtype);
+                if (j1 >= 0) s1 += ev[e + 1] * ldx(x, xo + (int64_t)j1 * R + r, dtype);
+                if (j2 >= 0) s2 += ev[e + 2] * ldx(x, xo + (int64_t)j2 * R + r, dtype);
+                if (j3 >= 0) s3 += ev[e + 3] * ldx(x, xo + (int64_t)j3 * R + r, dtype);
+            }
+            acc += (s1 + s2) + s3;
+        } else if (csr_val) {
             const double* v = csr_val + (int64_t)f * a.nnz;
+            const int64_t row = a.leaf_beg[li] + it;
             const int64_t e1 = a.csr_ptr[row + 1];
             int64_t e = a.csr_ptr[row];
             double s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -197,9 +318,9 @@ __global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, cons
             for (; e < e1; ++e) acc += v[e] * ldx(x, xo + (int64_t)pp.csr_col_dof[e] * R + r, dtype);
             acc += (s1 + s2) + s3;
         }
-        const int64_t dst = xo + (int64_t)a.perm[row] * R + r;
-        if (dtype == 0) ((double*)y)[dst] = acc;
-        else ((float*)y)[dst] = (float)acc;
+        const int64_t o = xo + dst * R + r;
+        if (dtype == 0) ((double*)y)[o] = acc;
+        else ((float*)y)[o] = (float)acc;
     }
 }
 
@@ -208,14 +329,17 @@ static hipError_t near_mm_t(const ApplyPlan& a, const PanelPlan& pp, const T* pa
                             const double* csr_val, int F, int R, int dtype, const void* x, void* y, hipStream_t st,
                             hipEvent_t e0, hipEvent_t e1) {
     const int64_t nrt = (a.cap + kMT - 1) / kMT, nct = (R + kNT - 1) / kNT;
-    const size_t lds = sizeof(T) * (size_t)((kMT * kApS + kKC * kBxS) > kMT * kCS ? (kMT * kApS + kKC * kBxS)
-                                                                                   : kMT * kCS);
+    size_t lds = sizeof(T) * mm_tile_elems<T>();
+    if (use_near && pp.max_stride <= kStageCols) lds += sizeof(int32_t) * (size_t)pp.max_stride;
     const dim3 grid((unsigned)(a.nleaf * nrt * nct), F);
+    // the ELL rows hold B + M; other subsets of the near field read the CSR
+    const int32_t* ec = pp.ell_val ? pp.ell_col : nullptr;
     if (e0)
-        hipExtLaunchKernelGGL(k_near_mm<T>, grid, dim3(256), lds, st, e0, e1, 0, a, pp, panel, use_near, csr_val, F, R,
-                              dtype, x, y);
+        hipExtLaunchKernelGGL(k_near_mm<T>, grid, dim3(256), lds, st, e0, e1, 0, a, pp, panel, use_near, csr_val, ec,
+                              pp.ell_val, F, R, dtype, x, y);
     else
-        hipLaunchKernelGGL(k_near_mm<T>, grid, dim3(256), lds, st, a, pp, panel, use_near, csr_val, F, R, dtype, x, y);
+        hipLaunchKernelGGL(k_near_mm<T>, grid, dim3(256), lds, st, a, pp, panel, use_near, csr_val, ec, pp.ell_val,
+                           F, R, dtype, x, y);
     return hipGetLastError();
 }
 

@@ -112,6 +112,27 @@ def test_apply_parts_and_full(name):
     assert err < TOL
 
 
+def test_apply_parts_several_rhs():
+    """The several-right-hand-side kernels on part subsets: B + M together read the
+    ELL rows by leaf slot, B or M alone the CSR; the near panels alone and with both."""
+    import paper_2302_02863_amd as fp
+    P, ref, op = _case("square")
+    K, parts = assemble_K_h2(P.mesh, P.s[0], P.kappa[0], P.opts, K_exact=ref["split"]["K"], return_parts=True)
+    tree = parts["tree"]
+    Knear = np.zeros_like(K)
+    for a, b in parts["near"]:
+        ix = np.ix_(tree.members[a], tree.members[b])
+        Knear[ix] = K[ix]
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((1, op.n_dofs, 8))
+    for mask, Aref in ((fp.PART_B, ref["B"]), (fp.PART_M, ref["M"]), (fp.PART_B | fp.PART_M, ref["B"] + ref["M"]),
+                       (fp.PART_KNEAR, Knear), (fp.PART_B | fp.PART_M | fp.PART_KNEAR, ref["B"] + ref["M"] + Knear)):
+        y = _apply(op, x, mask)[0]
+        yr = Aref @ x[0]
+        err = np.linalg.norm(y - yr, axis=0) / np.linalg.norm(yr, axis=0)
+        assert err.max() < TOL, (mask, err.max())
+
+
 def test_many_rhs_fields_and_float32():
     import paper_2302_02863_amd as fp
     P = configs.square(8, 4, leaf_size=12, leaf_size_rho=24, cheb_p=3)
