@@ -155,7 +155,7 @@ struct fpde_op {
     int64_t panel_max_stride = 0, panel_total = 0;
     // by leaf slot for the one-vector near rows: panel columns and the ELL form of B + M
     int32_t* d_pcols_pad = nullptr;        // [nleaf][panel_max_stride], -1 padding
-    int32_t* d_ell_col = nullptr;          // [nleaf * cap][ell_w] dof columns, -1 padding
+    int32_t* d_ell_col = nullptr;          // [nleaf * cap][ell_w] dof columns (see PanelPlan::ell_col)
     double* d_ell_val = nullptr;           // [F][nleaf * cap][ell_w] values of B + M
     int ell_w = 0;
     unsigned int* d_tickets = nullptr;     // [F][ncl] ticket counters of the one-vector upsweep (self-resetting)
@@ -907,13 +907,16 @@ void build_device(fpde_op& op) {
         std::vector<int32_t> cdof(op.csr_col.size());
         for (size_t e = 0; e < cdof.size(); ++e) cdof[e] = (int32_t)kt.perm[op.csr_col[e]];
         op.d_csr_col_dof = A.upload(cdof, st);
-        {   // ELL form of B + M by leaf slot, entries in CSR order; kept only while the padding costs
+        {   // ELL form of B + M by leaf slot, entries in CSR order (rows are never empty: the diagonal
+            // is always stored); kept only while the padding costs
             // at most half again the CSR's entries
             int64_t w = 0;
             for (int64_t i = 0; i < m.N; ++i) w = std::max(w, op.csr_ptr[i + 1] - op.csr_ptr[i]);
             w = (w + 3) / 4 * 4;
             const int64_t nslot = nleaf * op.cap;
-            if (w > 0 && nslot * w <= nnz + nnz / 2 + 4 * nslot) {
+            bool empty_row = false;
+            for (int64_t i = 0; i < m.N; ++i) empty_row = empty_row || op.csr_ptr[i + 1] == op.csr_ptr[i];
+            if (w > 0 && !empty_row && nslot * w <= nnz + nnz / 2 + 4 * nslot) {
                 std::vector<int32_t> ecol((size_t)(nslot * w), -1);
                 std::vector<int64_t> esrc((size_t)(nslot * w), -1);
                 for (int64_t li = 0; li < nleaf; ++li)
@@ -923,6 +926,10 @@ void build_device(fpde_op& op) {
                             ecol[o + e - op.csr_ptr[row]] = cdof[e];
                             esrc[o + e - op.csr_ptr[row]] = e;
                         }
+                        // padding: the row's first column with the value 0 (a kernel may read
+                        // every entry of a row without a test)
+                        for (int64_t e = op.csr_ptr[row + 1] - op.csr_ptr[row]; e < w; ++e)
+                            ecol[o + e] = cdof[op.csr_ptr[row]];
                     }
                 op.ell_w = (int)w;
                 op.d_ell_col = A.upload(ecol, st);

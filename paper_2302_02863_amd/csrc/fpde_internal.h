@@ -192,7 +192,9 @@ struct PanelPlan {
     // by leaf slot (leaf li, row it -> slot li * cap + it), read by the one-vector apply:
     const int32_t* pcols_pad = nullptr;  // [nleaf][max_stride] panel column dofs, -1 past the leaf's columns
     const int64_t* perm_pad = nullptr;   // [nleaf * cap] output index, -1 for slots past the leaf's rows
-    const int32_t* ell_col = nullptr;    // [nleaf * cap][ell_w] dof columns of B + M in CSR order, -1 padding
+    const int32_t* ell_col = nullptr;    // [nleaf * cap][ell_w] dof columns of B + M in CSR order; a row's
+                                         // padding repeats its first column (value 0), slots past the leaf's
+                                         // rows hold -1
     const double* ell_val = nullptr;     // [F][nleaf * cap][ell_w] values of B + M; null: use the CSR
     int ell_w = 0;
 };

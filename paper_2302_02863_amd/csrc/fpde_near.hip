@@ -99,6 +99,75 @@ constexpr size_t mm_tile_elems() {
 }
 }  // namespace
 
+// B + M rows of a tile from the ELL form by leaf slot, W entries a row (W <= 32;
+// a row's padding entries repeat its first column with the value 0):
+// lane e < W of the wave loads entry e (column and value) of the row, so one
+// load round trip fetches a whole row; the wave then broadcasts the entries
+// with readlane and issues all W gathers of x at once, and the next row's
+// entries load while this row's gathers are in flight.  Rows rr = wv, wv + 4,
+// ... of the tile; lane = right-hand side r0 + lane (stored only when < R).
+template <int W, typename XT, typename T>
+__device__ __forceinline__ void ell_rows(const ApplyPlan& a, const PanelPlan& pp, const int32_t* __restrict__ ell_col,
+                                         const double* __restrict__ ell_val, const T* Cs, int64_t li, int64_t row0,
+                                         int wv, int lane, int f, int R, int r0, int64_t xo,
+                                         const XT* __restrict__ x, XT* __restrict__ y) {
+    const int64_t nslot = a.nleaf * a.cap;
+    const int r = r0 + lane;
+    const bool rok = r < R;
+    const int rx = rok ? r : r0;   // lanes past R gather a valid entry and store nothing
+    auto load = [&](int rr, int& jc, double& vv, int64_t& dst) {
+        const int64_t it = row0 + rr;
+        jc = -1;
+        vv = 0.0;
+        dst = -1;
+        if (rr < kMT && it < a.cap) {
+            const int64_t slot = li * a.cap + it;
+            dst = pp.perm_pad[slot];
+            if (lane < W) {
+                jc = ell_col[slot * W + lane];
+                vv = ell_val[((int64_t)f * nslot + slot) * W + lane];
+            }
+        }
+    };
+    int jc;
+    double vv;
+    int64_t dst;
+    load(wv, jc, vv, dst);
+    for (int rr = wv; rr < kMT; rr += 4) {
+        if (dst < 0) break;   // the same in every lane; slots past the leaf's rows come last
+        XT xg[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) xg[e] = x[xo + (int64_t)__builtin_amdgcn_readlane(jc, e) * R + rx];
+        const int64_t d = dst;
+        const int64_t vb = __double_as_longlong(vv);
+        const int vlo = (int)vb, vhi = (int)(vb >> 32);
+        load(rr + 4, jc, vv, dst);   // the next row's entries, in flight during the sums
+        double acc[4] = {(double)Cs[rr * kCS + lane], 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const int64_t b = (int64_t)(uint32_t)__builtin_amdgcn_readlane(vlo, e) |
+                              ((int64_t)__builtin_amdgcn_readlane(vhi, e) << 32);
+            acc[e & 3] += __longlong_as_double(b) * (double)xg[e];
+        }
+        if (rok) y[xo + d * R + r] = (XT)(acc[0] + ((acc[1] + acc[2]) + acc[3]));
+    }
+}
+
+template <int W, typename T>
+__device__ __forceinline__ bool ell_rows_w(int w, const ApplyPlan& a, const PanelPlan& pp,
+                                           const int32_t* __restrict__ ell_col, const double* __restrict__ ell_val,
+                                           const T* Cs, int64_t li, int64_t row0, int wv, int lane, int f, int R,
+                                           int r0, int64_t xo, int dtype, const void* x, void* y) {
+    if (w != W) return false;
+    if (dtype == 0)
+        ell_rows<W, double, T>(a, pp, ell_col, ell_val, Cs, li, row0, wv, lane, f, R, r0, xo, (const double*)x,
+                               (double*)y);
+    else
+        ell_rows<W, float, T>(a, pp, ell_col, ell_val, Cs, li, row0, wv, lane, f, R, r0, xo, (const float*)x,
+                              (float*)y);
+    return true;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, const T* __restrict__ panel,
                                                  int use_near, const double* __restrict__ csr_val,
@@ -278,7 +347,15 @@ __global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, cons
     }
     __syncthreads();
     // B + M rows and the output: thread -> one right-hand side, rows strided by
-    // 4; a wave shares each row, so its column and value loads are uniform
+    // 4; a wave shares each row
+    if (ell_val) {
+        const int w = pp.ell_w;
+#define FPDE_ELL_W(W_) ell_rows_w<W_, T>(w, a, pp, ell_col, ell_val, Cs, li, row0, wv, lane, f, R, r0, xo, dtype, x, y)
+        if (FPDE_ELL_W(4) || FPDE_ELL_W(8) || FPDE_ELL_W(12) || FPDE_ELL_W(16) || FPDE_ELL_W(20) || FPDE_ELL_W(24) ||
+            FPDE_ELL_W(28) || FPDE_ELL_W(32))
+            return;
+#undef FPDE_ELL_W
+    }
     const int rc = tid & 63;
     const int r = r0 + rc;
     if (r >= R) return;
