@@ -1,8 +1,8 @@
 """Full-size parity on sampled rows that the oracle computes one by one
 (oracle.sampled): the 128 x 128 square workload (16129 dofs, 131072 cells) in the
-launch configuration the benchmark times, and the batched 256 x 256 workload
-(16 fields x 64 right-hand sides), at 1e-10 of the output's max norm (1e-6 for the
-mixed-precision operator)."""
+launch configuration the benchmark times, the batched 256 x 256 workload
+(16 fields x 64 right-hand sides) and the 512 x 512 disk workload (261121 dofs),
+at 1e-10 of the output's max norm (1e-6 for the mixed-precision operator)."""
 import numpy as np
 import pytest
 
@@ -80,3 +80,47 @@ def test_batched256_sampled_rows():
                 err = np.abs(y[rows] - out["total"]).max() / np.abs(y).max()
                 print(f"[fullsize] batched {precision} field {f} rhs {r}: {err:.2e}", flush=True)
                 assert err < tol, (precision, f, r, err)
+
+
+@pytest.mark.timeout(900)
+def test_disk512_sampled_rows_mixed_and_solve():
+    """The disk workload at full size (elliptical map of a 512 x 512 grid plus an annulus
+    to R = 1.1: 261121 dofs; s rising from 0.25 inside |x| = 0.5 to 0.75 outside, a = 1):
+    the FP64 operator at 1e-10 of the output's max norm on sampled rows (one random row,
+    one next to the interface); the mixed-precision operator (FP32 H2 and panel data,
+    FP64 B + M) within 1e-6 of the FP64 apply; mixed CG with iterative refinement on the
+    FP64 residual within 1e-8 of the FP64 CG solution for f = 1."""
+    import paper_2302_02863_amd as fp
+    P = configs.disk(512)
+    m = P.mesh
+    x = torch.tensor(P.x, device="cuda")
+    ones = torch.ones(m.n_nodes, dtype=torch.float64, device="cuda")
+    ys, us = {}, {}
+    for precision in ("fp64", "mixed"):
+        o = dict(P.opts)
+        o["precision"] = precision
+        print(f"[fullsize] disk build {precision} N={m.n_dofs}", flush=True)
+        op = fp.Operator(m, P.s, P.kappa, o)
+        ys[precision] = op.apply(x).cpu().numpy()[0, :, 0]
+        F = op.load_vector(ones).reshape(1, -1, 1)
+        u, info = op.solve(F, rtol=1e-12, maxit=20000)
+        print(f"[fullsize] disk {precision} solve: {info}", flush=True)
+        assert info["converged"], info
+        us[precision] = u.cpu().numpy()[0, :, 0]
+        op.close()
+    d = np.linalg.norm(ys["mixed"] - ys["fp64"]) / np.linalg.norm(ys["fp64"])
+    print(f"[fullsize] disk mixed vs FP64 apply: {d:.2e}", flush=True)
+    assert d < 1e-6
+    d = np.linalg.norm(us["mixed"] - us["fp64"]) / np.linalg.norm(us["fp64"])
+    print(f"[fullsize] disk mixed vs FP64 solution: {d:.2e}", flush=True)
+    assert d < 1e-8
+    rng = np.random.default_rng(29)
+    radius = np.hypot(m.coords[0, :m.n_dofs], m.coords[1, :m.n_dofs])
+    rows = [int(rng.integers(m.n_dofs)), int(rng.choice(np.flatnonzero(radius > 1 - 1.6 * m.info["h"])))]
+    print(f"[fullsize] disk oracle rows {rows}", flush=True)
+    so = SampledOracle(m, P.s[0], P.kappa[0], P.opts)
+    out = so.row_apply(rows, P.x[0, :, 0])
+    y = ys["fp64"]
+    err = np.abs(y[rows] - out["total"]).max() / np.abs(y).max()
+    print(f"[fullsize] disk sampled rows: {err:.2e}", flush=True)
+    assert err < TOL
