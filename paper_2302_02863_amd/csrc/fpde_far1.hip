@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kCoupleThreads) void k_couple(H2Tree t, FarPlan fp,
 template <int D, int P, typename T>
 __global__ __launch_bounds__(kFarThreads) void k_far_out(ApplyPlan a, H2Tree t, int ltop, const T* zh,
                                                            const T* Upad, const int64_t* perm_pad, const T* E,
-                                                           int dtype, void* y) {
+                                                           int dtype, void* y, CgFuse cg) {
     constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
     extern __shared__ __align__(16) unsigned char sraw[];
     const int L = t.L, nlev = L + 1 - ltop;
@@ -130,10 +130,11 @@ __global__ __launch_bounds__(kFarThreads) void k_far_out(ApplyPlan a, H2Tree t, 
     const int64_t pr = in ? perm_pad[slot] : -1;
     const bool ok = pr >= 0;
     int64_t dst = 0;
-    double yold = 0.0;
+    double yold = 0.0, pv = 0.0;
     if (ok && g == 0) {
         dst = (int64_t)f * a.N + pr;
         yold = ldx(y, dst, dtype);
+        if (cg.p) pv = cg.p[dst];
     }
 #pragma unroll
     for (int q = 0; q < kZR; ++q) {
@@ -162,9 +163,32 @@ __global__ __launch_bounds__(kFarThreads) void k_far_out(ApplyPlan a, H2Tree t, 
         if (4 * q + g < K) acc += u[q] * cur[4 * q + g];
     acc += __shfl_xor(acc, 1, 4);
     acc += __shfl_xor(acc, 2, 4);
+    double yn = 0.0;
     if (ok && g == 0) {
-        if (dtype == 0) ((double*)y)[dst] = yold + (double)acc;
-        else ((float*)y)[dst] = (float)(yold + (double)acc);
+        yn = yold + (double)acc;
+        if (dtype == 0) {
+            ((double*)y)[dst] = yn;
+        } else {
+            ((float*)y)[dst] = (float)yn;
+            yn = (double)(float)yn;
+        }
+    }
+    if (cg.p) {   // fused CG iteration: the block's share of p . y (tree in LDS, fixed order)
+        __shared__ double red[kFarThreads];
+        red[threadIdx.x] = yn * pv;
+        __syncthreads();
+        for (int s = kFarThreads / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            cg.part[(int64_t)f * gridDim.x + blockIdx.x] = red[0];
+            if (blockIdx.x == 0) {
+                cg.rr[f] = cg.rr_next[f];
+                cg.active[f] = cg.active_next[f];
+                if (f == 0) cg.n_active[0] = 0;
+            }
+        }
     }
 }
 
@@ -225,7 +249,7 @@ struct Far1 {
         const int64_t nrb = (a.cap + 63) / 64;
         const size_t lds = path_lds<D, P, T>(t, fp.ltop);
         hipLaunchKernelGGL((k_far_out<D, P, T>), dim3((unsigned)(a.nleaf * nrb), F), dim3(kFarThreads), lds, st, a,
-                           t, fp.ltop, od.zh, od.Upad, fp.perm_pad, od.E, dtype, y);
+                           t, fp.ltop, od.zh, od.Upad, fp.perm_pad, od.E, dtype, y, fp.cg);
     }
 };
 

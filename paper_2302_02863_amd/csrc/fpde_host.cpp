@@ -184,6 +184,7 @@ struct fpde_op {
     int64_t sw_R = 0;
     double *d_r = nullptr, *d_p = nullptr, *d_Ap = nullptr, *d_d = nullptr, *d_rout = nullptr;
     double *d_part1 = nullptr, *d_part2 = nullptr, *d_part3 = nullptr, *d_bb = nullptr, *d_rro = nullptr;
+    double* d_part_far = nullptr;   // [F][output-kernel blocks] p . Ap partials of fused CG iterations (R = 1)
     CgScalars cg{};
     int* h_nact = nullptr;                    // pinned host copy of the active-system count
     fpde_stats_t stats{};
@@ -1152,10 +1153,17 @@ ApplyPlan make_apply_plan(const fpde_op& op, const H2Tree& h) {
     return a;
 }
 
+// The one-vector kernels run this apply (the operator's precision pr: 0 FP64, 1 FP32 data)
+bool single_path(const fpde_op& op, int pr, int64_t R) {
+    const size_t esz = pr ? sizeof(float) : sizeof(double);
+    return R == 1 && op.up[pr].ok && op.panel_max_stride * (int64_t)esz <= 64 * 1024;
+}
+
 // Enqueue one apply on s0 (far chain forked to s1 through fk/jn when s1 != s0).
-// ev: optional 5 profiling events (requires s1 == s0).  Capturable.
+// ev: optional 5 profiling events (requires s1 == s0).  cg: a CG iteration fused into
+// the one-vector output kernel (callers check cg_fusable first).  Capturable.
 hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void* y, int64_t R, hipStream_t s0,
-                         hipStream_t s1, hipEvent_t fk, hipEvent_t jn, hipEvent_t* ev) {
+                         hipStream_t s1, hipEvent_t fk, hipEvent_t jn, hipEvent_t* ev, const CgFuse* cg = nullptr) {
     const int F = op.F, p = op.opts.cheb_p;
     const H2Tree h = make_h2(op.kt, op.kdev, p);
     const ApplyPlan a = make_apply_plan(op, h);
@@ -1175,18 +1183,20 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
         pp.ell_val = op.d_ell_val;
         pp.ell_w = op.ell_w;
     }
-    if (R == 1 && op.up[pr].ok && op.panel_max_stride * (int64_t)esz <= 64 * 1024) {
+    if (single_path(op, pr, R)) {
+        FarPlan fp = op.far_plan;
+        if (cg) fp.cg = *cg;
         H2Tree h1 = h;   // the far list with sources moved down
         h1.far_ptr = op.d_far1_ptr;
         h1.far_src = op.d_far1_src;
         if (f32) {
             OpData<float> od{op.f32.U, op.f32.E, op.f32.St1, op.f32.panel, op.f32.xh, op.f32.zh, op.f32.zp,
                              op.f32.Upad};
-            return launch_apply_single(a, h1, pp, op.up[1], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets,
+            return launch_apply_single(a, h1, pp, op.up[1], fp, parts, F, cv, od, dtype, x, y, op.d_tickets,
                                        s0, ev);
         }
         OpData<double> od{op.d_U, op.kdev.E, op.d_St1, op.d_panel, op.d_xh, op.d_zh, op.d_zp, op.d_Upad};
-        return launch_apply_single(a, h1, pp, op.up[0], op.far_plan, parts, F, cv, od, dtype, x, y, op.d_tickets, s0,
+        return launch_apply_single(a, h1, pp, op.up[0], fp, parts, F, cv, od, dtype, x, y, op.d_tickets, s0,
                                    ev);
     }
     // several right-hand sides: near panels as MFMA GEMMs and the far field as
@@ -1348,6 +1358,7 @@ void ensure_solve_ws(fpde_op& op, int64_t R) {
     Arena& A = op.arena;
     for (void* q : {(void*)op.d_r, (void*)op.d_p, (void*)op.d_Ap, (void*)op.d_d, (void*)op.d_rout,
                     (void*)op.d_part1, (void*)op.d_part2, (void*)op.d_part3, (void*)op.d_bb, (void*)op.d_rro,
+                    (void*)op.d_part_far,
                     (void*)op.cg.rr, (void*)op.cg.rr_next, (void*)op.cg.alpha, (void*)op.cg.beta, (void*)op.cg.tol2,
                     (void*)op.cg.active, (void*)op.cg.active_next, (void*)op.cg.iters, (void*)op.cg.flags,
                     (void*)op.cg.n_active})
@@ -1362,6 +1373,7 @@ void ensure_solve_ws(fpde_op& op, int64_t R) {
     op.d_part1 = A.alloc<double>(op.F * nb * R);
     op.d_part2 = A.alloc<double>(op.F * nb * R);
     op.d_part3 = A.alloc<double>(op.F * nb * R);
+    op.d_part_far = R == 1 ? A.alloc<double>(op.F * op.kt.nleaf() * ((op.cap + 63) / 64)) : nullptr;
     op.d_bb = A.alloc<double>(S);
     op.d_rro = A.alloc<double>(S);
     op.cg.rr = A.alloc<double>(S);
@@ -1380,10 +1392,30 @@ void ensure_solve_ws(fpde_op& op, int64_t R) {
 
 // One CG iteration on the system A d = rout (apply of precision `mixed`):
 // Ap = A p; p.Ap; alpha, d += alpha p, r -= alpha Ap, r.r; beta, p = r + beta p.
+// One right-hand side per field on the one-vector kernels with a far field: the output
+// kernel computes p . Ap and commits the previous iteration's state (no CG_DOT pass)
+bool cg_fusable(const fpde_op& op, bool mixed, int64_t R) {
+    return single_path(op, mixed ? 1 : 0, R) && op.far_plan.ntgt > 0 && op.d_part_far;
+}
+
 hipError_t enqueue_cg_iteration(fpde_op& op, bool mixed, int64_t R, hipStream_t s0, hipStream_t s1) {
     const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
     const int parts = mixed ? FPDE_PART_ALL : (FPDE_PART_ALL | FPDE_PART_FP64);
-    hipError_t e = enqueue_apply(op, parts, FPDE_F64, op.d_p, op.d_Ap, R, s0, s1, op.ev_fork, op.ev_join, nullptr);
+    hipError_t e;
+    if (cg_fusable(op, mixed, R)) {
+        const CgFuse cf{op.d_p, op.d_part_far, op.cg.rr, op.cg.rr_next, op.cg.active, op.cg.active_next,
+                        op.cg.n_active};
+        if ((e = enqueue_apply(op, parts, FPDE_F64, op.d_p, op.d_Ap, R, s0, s1, op.ev_fork, op.ev_join, nullptr,
+                               &cf)) != hipSuccess)
+            return e;
+        const int64_t nb_far = op.kt.nleaf() * ((op.cap + 63) / 64);   // blocks of the output kernel per field
+        if ((e = launch_cg_rowblock(CG_UPDATE_UR, dm, op.d_p, op.d_Ap, op.d_d, op.d_r, nullptr, op.d_part2, nullptr,
+                                    op.d_part_far, op.cg, s0, nb_far)) != hipSuccess)
+            return e;
+        return launch_cg_rowblock(CG_UPDATE_P, dm, op.d_r, nullptr, nullptr, nullptr, op.d_p, nullptr, nullptr,
+                                  op.d_part2, op.cg, s0);
+    }
+    e = enqueue_apply(op, parts, FPDE_F64, op.d_p, op.d_Ap, R, s0, s1, op.ev_fork, op.ev_join, nullptr);
     if (e != hipSuccess) return e;
     if ((e = launch_cg_rowblock(CG_DOT, dm, op.d_p, op.d_Ap, nullptr, nullptr, nullptr, op.d_part1, nullptr, nullptr,
                                 op.cg, s0)) != hipSuccess)

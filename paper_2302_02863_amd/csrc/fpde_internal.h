@@ -217,6 +217,17 @@ struct UpPlan {
     size_t path_lds;   // LDS of the output kernel's root-path walk (bytes, whole depth)
     bool ok;
 };
+// A CG iteration fused into the one-vector output kernel (one right-hand side per
+// field): the kernel adds p . y of its rows to part[f][block], and block 0 of
+// field f commits the previous iteration's |r|^2 and activity of system f (block
+// 0 of field 0 also clears the active-system count), which the first CG pass
+// after a plain apply does otherwise (see fpde_solve.hip).  p null: not fused.
+struct CgFuse {
+    const double* p = nullptr;   // [F][N] search direction
+    double* part = nullptr;      // [F][blocks of the output kernel]
+    double *rr = nullptr, *rr_next = nullptr;
+    int *active = nullptr, *active_next = nullptr, *n_active = nullptr;
+};
 // Far targets of the single-vector output kernel
 constexpr int kChunkWords = 4 + 16;
 struct FarPlan {
@@ -230,6 +241,7 @@ struct FarPlan {
     int64_t nchunks;
     unsigned int* ctk;     // [F][ncl] zero-initialised tickets of targets split in several chunks
     const int64_t* perm_pad;   // [nleaf * cap] output index by leaf slot, -1 for padding
+    CgFuse cg{};               // set for the applies of fused CG iterations
 };
 UpPlan plan_up_tree(const H2Tree& t, int64_t cap, int lmin, int prec /*0 double, 1 float*/);
 hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const int64_t* near_ptr,
@@ -348,9 +360,10 @@ int64_t cg_row_blocks(int64_t N, int R);
 // r -= alpha b, part1 = r.r; CG_UPDATE_P p = a + beta p; CG_RESID r = b - a, part1 = r.r,
 // part2 = b.b; CG_COPY_RP r = p = b, u = 0, part1 = b.b.  part_in: the partials the
 // coefficient of CG_UPDATE_UR / CG_UPDATE_P is summed from.
+// nb_in: partials per system in part_in (default: the pass's own block count)
 hipError_t launch_cg_rowblock(int op, const CgDims& d, const double* a, const double* b, double* u, double* r,
                               double* p, double* part1, double* part2, const double* part_in, const CgScalars& c,
-                              hipStream_t st);
+                              hipStream_t st, int64_t nb_in = -1);
 hipError_t launch_cg_start(const CgDims& d, const double* part, const double* bb0, double tau_in, double rtol,
                            const CgScalars& c, hipStream_t st);
 hipError_t launch_cg_sum2(const CgDims& d, const double* part1, const double* part2, double* o1, double* o2,

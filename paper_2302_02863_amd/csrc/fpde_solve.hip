@@ -61,7 +61,8 @@ __device__ inline double sum_parts(const double* part, int64_t nb, int R, int64_
 //                 the first block of the field commits |r|^2 and activity of the
 //                 previous iteration (rr = rr_next, active = active_next); the
 //                 first block of field 0 clears the active-system counter
-//   CG_UPDATE_UR: alpha = rr / p.Ap (p.Ap summed from part_in); a system with a
+//   CG_UPDATE_UR: alpha = rr / p.Ap (p.Ap summed from the nb_in partials of part_in: CG_DOT's, or
+//                 those of the apply's output kernel when the iteration is fused); a system with a
 //                 non-positive p.Ap takes alpha = 0 and is flagged (breakdown);
 //                 u += alpha p, r -= alpha Ap, part1 = r . r             (a=p, b=Ap)
 //   CG_UPDATE_P:  rr_new = r.r from part_in, beta = rr_new / rr, p = r + beta p;
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
                                                   const double* __restrict__ b, double* __restrict__ u,
                                                   double* __restrict__ r, double* __restrict__ p,
                                                   double* __restrict__ part1, double* __restrict__ part2,
-                                                  const double* __restrict__ part_in, CgScalars c) {
+                                                  const double* __restrict__ part_in, int64_t nb_in, CgScalars c) {
     __shared__ double red[kBS];
     __shared__ double coef[kBS];
     __shared__ int nact;
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
             // stride over the blocks, then a fixed-order tree (same value in every block)
             double pv = 0.0;
             if (col < R)
-                for (int64_t b = rl; b < nb; b += nrl) pv += part_in[((int64_t)f * nb + b) * R + col];
+                for (int64_t b = rl; b < nb_in; b += nrl) pv += part_in[((int64_t)f * nb_in + b) * R + col];
             red[t] = pv;
             __syncthreads();
             for (int s = nrl / 2; s >= 1; s >>= 1) {
@@ -241,11 +242,13 @@ int64_t cg_row_blocks(int64_t N, int R) {
 
 hipError_t launch_cg_rowblock(int op, const CgDims& d, const double* a, const double* b, double* u, double* r,
                               double* p, double* part1, double* part2, const double* part_in, const CgScalars& c,
-                              hipStream_t st) {
+                              hipStream_t st, int64_t nb_in) {
     const int64_t rpb = (d.N + d.nb - 1) / d.nb;
+    if (nb_in < 0) nb_in = d.nb;
     const dim3 g((unsigned)d.nb, (unsigned)d.F);
 #define FPDE_ROWBLOCK(OPV)                                                                                          \
-    hipLaunchKernelGGL(k_rowblock<OPV>, g, dim3(kBS), 0, st, d.N, d.R, rpb, a, b, u, r, p, part1, part2, part_in, c)
+    hipLaunchKernelGGL(k_rowblock<OPV>, g, dim3(kBS), 0, st, d.N, d.R, rpb, a, b, u, r, p, part1, part2, part_in, \
+                       nb_in, c)
     switch (op) {
         case CG_DOT: FPDE_ROWBLOCK(CG_DOT); break;
         case CG_UPDATE_UR: FPDE_ROWBLOCK(CG_UPDATE_UR); break;
