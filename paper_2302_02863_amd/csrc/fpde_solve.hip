@@ -7,7 +7,9 @@
 // solve is bitwise reproducible.  The per-system scalars stay on the device:
 // each block that needs alpha or beta sums the partials itself (same order,
 // same value in every block), so one CG iteration is the operator apply and
-// three row-block kernels, launched back to back with no host round trip.
+// three row-block kernels, launched back to back with no host round trip; with
+// one right-hand side per field the apply's output kernel computes p . Ap and
+// does CG_DOT's commit, and CG_DOT is not launched.
 // State that the blocks of a kernel read (|r|^2, activity) is only committed
 // by the next kernel, so no block reads a value another block of the same
 // kernel writes.
