@@ -42,10 +42,11 @@ def workload(name: str):
 
 def algorithmic_bytes_near(op, st, F, R, dim, p):
     """HBM bytes one launch of the near/upsweep kernel must move, no re-reads counted:
-    the near leaf blocks (sum over near pairs of |s| |s'| FP64 entries), the CSR of
-    B + M (FP64 values, int32 columns, int64 row pointers), x read once, y written
-    once, the leaf bases U (N x k FP64) and the transfers (D P^2 per cluster) read
-    once, the cluster coefficients (k per cluster) written once."""
+    the near leaf blocks (sum over near pairs of |s| |s'| FP64 entries), the nonzeros
+    of B + M (FP64 values, int32 columns) and one 8-byte index per row, x read once,
+    y written once, the leaf bases U (N x k FP64) and the transfers (D P^2 per
+    cluster) read once, the cluster coefficients (k per cluster) written once.  The
+    kernel reads B + M in an ELL form by leaf slot; its padding is not counted."""
     leafptr = op.export("K_LEAFPTR")
     sizes = leafptr[1:] - leafptr[:-1]
     pairs = op.export("K_NEAR").reshape(-1, 2)
@@ -274,7 +275,7 @@ def main():
         "config": cfg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
-                     "kernel": kname + " (CSR B+M, dense near leaf blocks, far-field upsweep)",
+                     "kernel": kname + " (B+M rows, dense near leaf blocks, far-field upsweep)",
                      "bytes_per_launch": b_out, "avg_ms": out_ms},
         "phases_ms_per_apply": {k: prof[k] / max(1, prof["n_applies"]) for k in ("ms_far", "ms_out", "ms_far_out",
                                                                                "ms_total")},
