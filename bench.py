@@ -114,7 +114,7 @@ def time_applies(op, x, y, stream, steps, warmup, parts=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(steps):
-        op.apply(x, y, stream=stream, **kw)          # one hipGraph launch per apply
+        op.apply(x, y, stream=stream, **kw)          # the apply's kernels, launched directly
     torch.cuda.synchronize()
     return time.perf_counter() - t1
 
@@ -205,6 +205,33 @@ def batched(steps, warmup):
     return out
 
 
+def scaling(steps, warmup, sizes=(32, 64, 128, 256)):
+    """Build time and one-vector FP64 apply time of the square workload (same recipe:
+    jitter, order and diffusivity fields) for growing n: linear scaling in N."""
+    import torch
+    import paper_2302_02863_amd as fp
+    from fpde_inputs import configs
+    out = []
+    for n in sizes:
+        P = configs.square(n)
+        t0 = time.perf_counter()
+        op = fp.Operator(P.mesh, P.s, P.kappa, P.opts)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        st = op.stats()
+        x = torch.tensor(P.x, device="cuda:0")
+        y = torch.empty_like(x)
+        el = time_applies(op, x, y, torch.cuda.current_stream(), steps, warmup)
+        N = P.mesh.n_dofs
+        out.append({"n": n, "n_dofs": N, "build_s": build_s,
+                    "build_phase_ms": {k: st[k] for k in ("t_plan_ms", "t_singular_ms", "t_rho_ms", "t_mass_ms",
+                                                          "t_bases_ms", "t_near_blocks_ms")},
+                    "apply_us": el / steps * 1e6, "dof_matvecs_per_s": N * steps / el})
+        op.close()
+        del x, y
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +241,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision apply and the solves")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-field x 64-rhs batched workload")
+    ap.add_argument("--no-scaling", action="store_true", help="skip the build and apply times of square 32..256")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -290,6 +318,8 @@ def main():
         res["mixed"] = mx
     if not args.no_batched:
         res["batched"] = batched(max(5, args.steps // 20), 3)
+    if not args.no_scaling:
+        res["scaling_in_n"] = scaling(max(20, args.steps // 4), 5)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(P)
     print(json.dumps(res))
