@@ -5,7 +5,7 @@
 //   k_blevel       X^_parent = sum_c E_c^T X^_c          (per level)
 //   k_bcoupling    Y^_S = sum_{S' far S} S_(S,S') X^_S'  (MFMA, per target cluster)
 //   k_blevel       Y^_c += E_c Y^_parent                 (per level)
-//   k_bout_leaf    y_leaf += U_leaf Y^_leaf              (per leaf, added to y)
+// and the near kernel (fpde_near.hip) adds y_leaf += U_leaf Y^_leaf to its rows.
 // The coupling products, 2 K^2 R flops per far pair and field, are the bulk
 // of the work: FP32 operator data uses v_mfma_f32_32x32x2f32, FP64 uses
 // v_mfma_f64_16x16x4f64 (lane layouts as in the near-panel GEMM).
@@ -280,61 +280,6 @@ __global__ __launch_bounds__(128) void k_bcoupling(H2Tree t, int F, int R, const
     }
 }
 
-// y[perm[row]][r] += sum_alpha U[row][alpha] Y^_leaf[alpha][r]; one block per (leaf, rhs chunk, field)
-template <typename T>
-__global__ __launch_bounds__(256) void k_bout_leaf(ApplyPlan a, H2Tree t, int F, int R, const T* U, const T* yh,
-                                                   int dtype, void* y) {
-    extern __shared__ __align__(16) unsigned char sraw[];
-    const int K = t.k;
-    const int64_t nrc = (R + kRC - 1) / kRC;
-    const int64_t li = blockIdx.x / nrc;
-    const int r0 = (int)(blockIdx.x % nrc) * kRC;
-    const int f = blockIdx.y;
-    const int64_t lb = a.leaf_beg[li], n = a.leaf_beg[li + 1] - lb;
-    const int64_t c = t.first_leaf + li;
-    T* sU = (T*)sraw;          // [n][K]
-    T* sY = sU + n * K;        // [K][kRC]
-    {   // staging with every load of a thread in flight before the first wait (K <= 32, 64 rows a pass)
-        constexpr int NU = 64 * 32 / 256, NY = 32 * kRC / 256;
-        for (int64_t b0 = 0; b0 < n * K; b0 += 64 * 32) {
-            T vu[NU];
-#pragma unroll
-            for (int m = 0; m < NU; ++m) {
-                const int64_t i = b0 + threadIdx.x + 256 * m;
-                vu[m] = i < n * K ? U[lb * K + i] : T(0);
-            }
-#pragma unroll
-            for (int m = 0; m < NU; ++m) {
-                const int64_t i = b0 + threadIdx.x + 256 * m;
-                if (i < n * K) sU[i] = vu[m];
-            }
-        }
-        T vy[NY];
-#pragma unroll
-        for (int m = 0; m < NY; ++m) {
-            const int i = threadIdx.x + 256 * m;
-            const int al = i / kRC, rr = i % kRC;
-            vy[m] = (al < K && r0 + rr < R) ? yh[(((int64_t)f * t.ncl + c) * K + al) * R + r0 + rr] : T(0);
-        }
-#pragma unroll
-        for (int m = 0; m < NY; ++m) {
-            const int i = threadIdx.x + 256 * m;
-            if (i / kRC < K) sY[i] = vy[m];
-        }
-    }
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < n * kRC; i += blockDim.x) {
-        const int64_t j = i / kRC;
-        const int rr = (int)(i % kRC);
-        if (r0 + rr >= R) continue;
-        T acc = 0;
-        for (int al = 0; al < K; ++al) acc += sU[j * K + al] * sY[al * kRC + rr];
-        const int64_t dst = ((int64_t)f * a.N + a.perm[lb + j]) * R + r0 + rr;
-        if (dtype == 0) ((double*)y)[dst] += (double)acc;
-        else ((float*)y)[dst] = (float)((double)((float*)y)[dst] + (double)acc);
-    }
-}
-
 namespace {
 
 template <typename T>
@@ -372,40 +317,22 @@ hipError_t far_batched_t(const ApplyPlan& a, const H2Tree& t, int F, int R, cons
 }
 
 template <typename T>
-hipError_t far_out_batched_t(const ApplyPlan& a, const H2Tree& t, int F, int R, const T* U, const T* yh, int dtype,
-                             void* y, hipStream_t st) {
-    const int64_t nrc = (R + kRC - 1) / kRC;
-    const size_t lds = sizeof(T) * (size_t)(a.cap * t.k + t.k * kRC);
-    hipLaunchKernelGGL(k_bout_leaf<T>, dim3((unsigned)(a.nleaf * nrc), F), dim3(256), lds, st, a, t, F, R, U, yh,
-                       dtype, y);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t apply_batched_t(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, int parts, int F, int R,
                            const double* csr_val, const OpData<T>& od, T* xh, T* yh, int dtype, const void* x, void* y,
-                           hipStream_t st, hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev) {
+                           hipStream_t st, hipEvent_t* ev) {
+    // The far chain first, then the near kernel, which adds U_leaf Y^_leaf to its rows:
+    // run beside the near kernel on a second stream, the chain's small dependent launches
+    // wait behind the near kernel's blocks and end up on the critical path.
     const bool far = (parts & 8) != 0;
     if (ev) hipEventRecord(ev[0], st);
-    hipStream_t fs = st;
-    if (far && side != st) {
-        hipEventRecord(fork, st);
-        hipStreamWaitEvent(side, fork, 0);
-        fs = side;
-    }
     hipError_t e = hipSuccess;
-    if (far && (e = far_batched_t<T>(a, t, F, R, od, dtype, x, xh, yh, fs)) != hipSuccess) return e;
-    if (ev) hipEventRecord(ev[1], fs);
+    if (far && (e = far_batched_t<T>(a, t, F, R, od, dtype, x, xh, yh, st)) != hipSuccess) return e;
+    if (ev) hipEventRecord(ev[1], st);
+    MmFar<T> fo{};
+    if (far) fo = MmFar<T>{yh, od.Upad, t.ncl, t.first_leaf, t.k};
     e = launch_near_mm(a, pp, od.panel, (parts & 4) != 0, csr_val, F, R, dtype, x, y, st, ev ? ev[2] : nullptr,
-                       ev ? ev[3] : nullptr);
+                       ev ? ev[3] : nullptr, fo);
     if (e != hipSuccess) return e;
-    if (far) {
-        if (fs != st) {
-            hipEventRecord(join, fs);
-            hipStreamWaitEvent(st, join, 0);
-        }
-        if ((e = far_out_batched_t<T>(a, t, F, R, od.U, yh, dtype, y, st)) != hipSuccess) return e;
-    }
     if (ev) hipEventRecord(ev[4], st);
     return hipGetLastError();
 }
@@ -420,16 +347,14 @@ bool batched_fits(const H2Tree& t, int64_t cap, int prec) {
 
 hipError_t launch_apply_batched(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, int parts, int F, int R,
                                 const double* csr_val, const OpData<double>& od, double* xh, double* yh, int dtype,
-                                const void* x, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
-                                hipEvent_t join, hipEvent_t* ev) {
-    return apply_batched_t<double>(a, t, pp, parts, F, R, csr_val, od, xh, yh, dtype, x, y, st, side, fork, join, ev);
+                                const void* x, void* y, hipStream_t st, hipEvent_t* ev) {
+    return apply_batched_t<double>(a, t, pp, parts, F, R, csr_val, od, xh, yh, dtype, x, y, st, ev);
 }
 
 hipError_t launch_apply_batched(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, int parts, int F, int R,
                                 const double* csr_val, const OpData<float>& od, float* xh, float* yh, int dtype,
-                                const void* x, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
-                                hipEvent_t join, hipEvent_t* ev) {
-    return apply_batched_t<float>(a, t, pp, parts, F, R, csr_val, od, xh, yh, dtype, x, y, st, side, fork, join, ev);
+                                const void* x, void* y, hipStream_t st, hipEvent_t* ev) {
+    return apply_batched_t<float>(a, t, pp, parts, F, R, csr_val, od, xh, yh, dtype, x, y, st, ev);
 }
 
 }  // namespace fpde

@@ -1203,13 +1203,13 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
     // batched products in the operator's precision (FP32 data for a mixed operator)
     if (batched_fits(h, op.cap, pr)) {
         if (f32) {
-            OpData<float> od{op.f32.U, op.f32.E, op.f32.St, op.f32.panel, nullptr, nullptr};
+            OpData<float> od{op.f32.U,  op.f32.E, op.f32.St, op.f32.panel, nullptr,
+                             nullptr,   nullptr,  op.f32.Upad};
             return launch_apply_batched(a, h, pp, parts, F, (int)R, cv, od, op.f32.xhR, op.f32.yhR, dtype, x, y, s0,
-                                        s1, fk, jn, ev);
+                                        ev);
         }
-        OpData<double> od{op.d_U, op.kdev.E, op.d_St, op.d_panel, nullptr, nullptr};
-        return launch_apply_batched(a, h, pp, parts, F, (int)R, cv, od, op.d_xh, op.d_yh, dtype, x, y, s0, s1, fk, jn,
-                                    ev);
+        OpData<double> od{op.d_U, op.kdev.E, op.d_St, op.d_panel, nullptr, nullptr, nullptr, op.d_Upad};
+        return launch_apply_batched(a, h, pp, parts, F, (int)R, cv, od, op.d_xh, op.d_yh, dtype, x, y, s0, ev);
     }
     // otherwise (K > 32): FP64 far field with LDS-resident subtrees, or per-level sweeps
     const void* panel = f32 ? (const void*)op.f32.panel : (const void*)op.d_panel;

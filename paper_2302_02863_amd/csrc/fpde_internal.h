@@ -248,13 +248,23 @@ hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const 
                               const int64_t* near_src, const int64_t* leaf_beg, const int64_t* pcol_off,
                               const int64_t* poff, const int64_t* pstride, const int64_t* pcols_ptr, const double* nb,
                               int F, double* panel, hipStream_t st);
-// several right-hand sides: Y = Panel X (MFMA) + (B+M) X per (leaf, 64 rows, 64 rhs, field); x, y [F][N][R]
+// The far field's leaf output U_leaf Y^_leaf added by the several-right-hand-side near
+// kernel (yh null: none); K <= 32
+template <typename T>
+struct MmFar {
+    const T* yh = nullptr;     // [F][ncl][K][R] downsweep coefficients
+    const T* Upad = nullptr;   // [nleaf * cap][K] bases by leaf slot
+    int64_t ncl = 0, first_leaf = 0;
+    int K = 0;
+};
+// several right-hand sides: Y = Panel X (MFMA) + (B+M) X [+ U Y^] per (leaf, 64 rows, 64 rhs, field);
+// x, y [F][N][R]
 hipError_t launch_near_mm(const ApplyPlan& a, const PanelPlan& pp, const double* panel, int use_near,
                           const double* csr_val, int F, int R, int dtype, const void* x, void* y, hipStream_t st,
-                          hipEvent_t e0, hipEvent_t e1);
+                          hipEvent_t e0, hipEvent_t e1, const MmFar<double>& fo = {});
 hipError_t launch_near_mm(const ApplyPlan& a, const PanelPlan& pp, const float* panel, int use_near,
                           const double* csr_val, int F, int R, int dtype, const void* x, void* y, hipStream_t st,
-                          hipEvent_t e0, hipEvent_t e1);
+                          hipEvent_t e0, hipEvent_t e1, const MmFar<float>& fo = {});
 // tickets: [F][ncl] zero-initialised counters of the upsweep (left at zero by every launch).
 // ev (optional, 5 events): start, start, near/upsweep kernel start/stop, end.
 hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, const UpPlan& up,
@@ -285,17 +295,15 @@ hipError_t launch_out_single(const ApplyPlan& a, const H2Tree& t, const FarPlan&
 
 // K <= 32 and the leaf stages fit LDS (prec 0 double, 1 float)
 bool batched_fits(const H2Tree& t, int64_t cap, int prec);
-// near panels (MFMA) + CSR on st; far field in the operator precision on side:
-// leaf upsweep, level transfers, MFMA coupling per target cluster, downsweep;
-// join; y += U Y^ per leaf.  xh, yh: [F][ncl][K][R] workspaces of that precision.
+// far field in the operator precision (leaf upsweep, level transfers, MFMA coupling per
+// target cluster, downsweep), then the near panels (MFMA) + B + M + U Y^ per leaf, all on
+// st.  xh, yh: [F][ncl][K][R] workspaces of that precision; od.Upad required.
 hipError_t launch_apply_batched(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, int parts, int F, int R,
                                 const double* csr_val, const OpData<double>& od, double* xh, double* yh, int dtype,
-                                const void* x, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
-                                hipEvent_t join, hipEvent_t* ev);
+                                const void* x, void* y, hipStream_t st, hipEvent_t* ev);
 hipError_t launch_apply_batched(const ApplyPlan& a, const H2Tree& t, const PanelPlan& pp, int parts, int F, int R,
                                 const double* csr_val, const OpData<float>& od, float* xh, float* yh, int dtype,
-                                const void* x, void* y, hipStream_t st, hipStream_t side, hipEvent_t fork,
-                                hipEvent_t join, hipEvent_t* ev);
+                                const void* x, void* y, hipStream_t st, hipEvent_t* ev);
 
 // ---------------------------------------------------------------- adjoint (fpde_adjoint.hip, singular pairs in
 // fpde_kernels.hip): d/ds_j and d/dkappa_j of sum_r w_r^T A_h u_r

@@ -97,6 +97,12 @@ constexpr size_t mm_tile_elems() {
     const size_t c = (size_t)kMT * kCS;
     return g > c ? g : c;
 }
+
+__device__ __forceinline__ double bcast(double v, int l) {   // v of lane l (wave-uniform l)
+    const int64_t b = __double_as_longlong(v);
+    return __longlong_as_double((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)b, l) |
+                                ((int64_t)__builtin_amdgcn_readlane((int)(b >> 32), l) << 32));
+}
 }  // namespace
 
 // B + M rows of a tile from the ELL form by leaf slot, W entries a row (W <= 32;
@@ -139,16 +145,11 @@ __device__ __forceinline__ void ell_rows(const ApplyPlan& a, const PanelPlan& pp
 #pragma unroll
         for (int e = 0; e < W; ++e) xg[e] = x[xo + (int64_t)__builtin_amdgcn_readlane(jc, e) * R + rx];
         const int64_t d = dst;
-        const int64_t vb = __double_as_longlong(vv);
-        const int vlo = (int)vb, vhi = (int)(vb >> 32);
+        const double v0 = vv;
         load(rr + 4, jc, vv, dst);   // the next row's entries, in flight during the sums
         double acc[4] = {(double)Cs[rr * kCS + lane], 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int e = 0; e < W; ++e) {
-            const int64_t b = (int64_t)(uint32_t)__builtin_amdgcn_readlane(vlo, e) |
-                              ((int64_t)__builtin_amdgcn_readlane(vhi, e) << 32);
-            acc[e & 3] += __longlong_as_double(b) * (double)xg[e];
-        }
+        for (int e = 0; e < W; ++e) acc[e & 3] += bcast(v0, e) * (double)xg[e];
         if (rok) y[xo + d * R + r] = (XT)(acc[0] + ((acc[1] + acc[2]) + acc[3]));
     }
 }
@@ -169,11 +170,11 @@ __device__ __forceinline__ bool ell_rows_w(int w, const ApplyPlan& a, const Pane
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, const T* __restrict__ panel,
+__global__ __launch_bounds__(256, 3) void k_near_mm(ApplyPlan a, PanelPlan pp, const T* __restrict__ panel,
                                                  int use_near, const double* __restrict__ csr_val,
                                                  const int32_t* __restrict__ ell_col,
                                                  const double* __restrict__ ell_val, int F, int R, int dtype,
-                                                 const void* __restrict__ x, void* __restrict__ y) {
+                                                 const void* __restrict__ x, void* __restrict__ y, MmFar<T> fo) {
     constexpr int KS = MM<T>::KS, NS = kKC / KS, SA = MM<T>::SA, SB = MM<T>::SB;
     constexpr int VW = 16 / sizeof(T);               // elements of a 16-byte vector
     constexpr int NA = kMT * kKC / VW / 256;          // panel vectors per thread and chunk
@@ -195,6 +196,45 @@ __global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, cons
     const int64_t xo = (int64_t)f * a.N * R;
     fpde_f32x16 c32 = {0};
     fpde_f64x4 c64[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+    // MFMA steps over the chunk in LDS (32 columns of A, 32 rows of B)
+    auto mma = [&]() {
+        if constexpr (sizeof(T) == 4) {
+            const int g = lane >> 5, i32 = lane & 31;
+            const float4* ar = (const float4*)(Ap + (wr + i32) * SA + g * NS);
+            float4 a4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a4[q] = ar[q];
+            const float av[16] = {a4[0].x, a4[0].y, a4[0].z, a4[0].w, a4[1].x, a4[1].y, a4[1].z, a4[1].w,
+                                  a4[2].x, a4[2].y, a4[2].z, a4[2].w, a4[3].x, a4[3].y, a4[3].z, a4[3].w};
+#pragma unroll
+            for (int st = 0; st < NS; ++st) {
+                const float bv = Bx[(KS * st + g) * SB + wc + i32];
+                c32 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[st], bv, c32, 0, 0, 0);
+            }
+        } else {
+            const int g = lane >> 4, i16 = lane & 15;
+            const double2* ar0 = (const double2*)(Ap + (wr + i16) * SA + g * NS);
+            const double2* ar1 = (const double2*)(Ap + (wr + 16 + i16) * SA + g * NS);
+#pragma unroll
+            for (int q = 0; q < NS / 2; ++q) {   // two steps per 16-byte read of A
+                const double2 a0 = ar0[q], a1 = ar1[q];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int st = 2 * q + h;
+                    const double av[2] = {h ? a0.y : a0.x, h ? a1.y : a1.x};
+                    double bv[2];
+#pragma unroll
+                    for (int tj = 0; tj < 2; ++tj) bv[tj] = Bx[(KS * st + g) * SB + wc + 16 * tj + i16];
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < 2; ++tj)
+                            c64[ti][tj] =
+                                __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], c64[ti][tj], 0, 0, 0);
+                }
+            }
+        }
+    };
     if (use_near) {
         const int64_t ps = pp.pstride[li];
         const int32_t* pcg = pp.pcols_pad + li * pp.max_stride;   // -1 past the leaf's columns
@@ -292,43 +332,31 @@ __global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, cons
             }
             __syncthreads();
             if (k0 + kKC < ps) fetch(k0 + kKC);
-            if constexpr (sizeof(T) == 4) {
-                const int g = lane >> 5, i32 = lane & 31;
-                const float4* ar = (const float4*)(Ap + (wr + i32) * SA + g * NS);
-                float4 a4[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) a4[q] = ar[q];
-                const float av[16] = {a4[0].x, a4[0].y, a4[0].z, a4[0].w, a4[1].x, a4[1].y, a4[1].z, a4[1].w,
-                                      a4[2].x, a4[2].y, a4[2].z, a4[2].w, a4[3].x, a4[3].y, a4[3].z, a4[3].w};
-#pragma unroll
-                for (int st = 0; st < NS; ++st) {
-                    const float bv = Bx[(KS * st + g) * SB + wc + i32];
-                    c32 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[st], bv, c32, 0, 0, 0);
-                }
-            } else {
-                const int g = lane >> 4, i16 = lane & 15;
-                const double2* ar0 = (const double2*)(Ap + (wr + i16) * SA + g * NS);
-                const double2* ar1 = (const double2*)(Ap + (wr + 16 + i16) * SA + g * NS);
-#pragma unroll
-                for (int q = 0; q < NS / 2; ++q) {   // two steps per 16-byte read of A
-                    const double2 a0 = ar0[q], a1 = ar1[q];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int st = 2 * q + h;
-                        const double av[2] = {h ? a0.y : a0.x, h ? a1.y : a1.x};
-                        double bv[2];
-#pragma unroll
-                        for (int tj = 0; tj < 2; ++tj) bv[tj] = Bx[(KS * st + g) * SB + wc + 16 * tj + i16];
-#pragma unroll
-                        for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-                            for (int tj = 0; tj < 2; ++tj)
-                                c64[ti][tj] =
-                                    __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], c64[ti][tj], 0, 0, 0);
-                    }
-                }
-            }
+            mma();
         }
+    }
+    if (fo.yh) {
+        // the far field's leaf output U_leaf Y^_leaf as one more chunk: A = the tile's rows of
+        // the bases by leaf slot, B = the leaf's coefficients Y^ (alpha, beta padded to 32, K <= 32)
+        const T* yl = fo.yh + (((int64_t)f * fo.ncl + fo.first_leaf + li) * fo.K) * R + r0;
+        const int ar_ = tid >> 2, ac_ = (tid & 3) * 8;    // A: row, first of 8 columns
+        const int br_ = tid >> 3, bc_ = (tid & 7) * 8;    // B: row (alpha), first of 8 right-hand sides
+        const int64_t urow = row0 + ar_;
+        T ua[8], ya[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            ua[j] = (urow < a.cap && ac_ + j < fo.K) ? fo.Upad[(li * a.cap + urow) * fo.K + ac_ + j] : T(0);
+            ya[j] = (br_ < fo.K && r0 + bc_ + j < R) ? yl[(int64_t)br_ * R + bc_ + j] : T(0);
+        }
+        __syncthreads();   // the last panel chunk's MFMAs are done with the LDS tiles
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int col = ac_ + j;
+            Ap[ar_ * SA + (col % KS) * NS + col / KS] = ua[j];
+            Bx[br_ * SB + bc_ + j] = ya[j];
+        }
+        __syncthreads();
+        mma();
     }
     __syncthreads();
     // the tile to LDS
@@ -404,7 +432,7 @@ __global__ __launch_bounds__(256) void k_near_mm(ApplyPlan a, PanelPlan pp, cons
 template <typename T>
 static hipError_t near_mm_t(const ApplyPlan& a, const PanelPlan& pp, const T* panel, int use_near,
                             const double* csr_val, int F, int R, int dtype, const void* x, void* y, hipStream_t st,
-                            hipEvent_t e0, hipEvent_t e1) {
+                            hipEvent_t e0, hipEvent_t e1, const MmFar<T>& fo) {
     const int64_t nrt = (a.cap + kMT - 1) / kMT, nct = (R + kNT - 1) / kNT;
     size_t lds = sizeof(T) * mm_tile_elems<T>();
     if (use_near && pp.max_stride <= kStageCols) lds += sizeof(int32_t) * (size_t)pp.max_stride;
@@ -413,23 +441,23 @@ static hipError_t near_mm_t(const ApplyPlan& a, const PanelPlan& pp, const T* pa
     const int32_t* ec = pp.ell_val ? pp.ell_col : nullptr;
     if (e0)
         hipExtLaunchKernelGGL(k_near_mm<T>, grid, dim3(256), lds, st, e0, e1, 0, a, pp, panel, use_near, csr_val, ec,
-                              pp.ell_val, F, R, dtype, x, y);
+                              pp.ell_val, F, R, dtype, x, y, fo);
     else
         hipLaunchKernelGGL(k_near_mm<T>, grid, dim3(256), lds, st, a, pp, panel, use_near, csr_val, ec, pp.ell_val,
-                           F, R, dtype, x, y);
+                           F, R, dtype, x, y, fo);
     return hipGetLastError();
 }
 
 hipError_t launch_near_mm(const ApplyPlan& a, const PanelPlan& pp, const double* panel, int use_near,
                           const double* csr_val, int F, int R, int dtype, const void* x, void* y, hipStream_t st,
-                          hipEvent_t e0, hipEvent_t e1) {
-    return near_mm_t<double>(a, pp, panel, use_near, csr_val, F, R, dtype, x, y, st, e0, e1);
+                          hipEvent_t e0, hipEvent_t e1, const MmFar<double>& fo) {
+    return near_mm_t<double>(a, pp, panel, use_near, csr_val, F, R, dtype, x, y, st, e0, e1, fo);
 }
 
 hipError_t launch_near_mm(const ApplyPlan& a, const PanelPlan& pp, const float* panel, int use_near,
                           const double* csr_val, int F, int R, int dtype, const void* x, void* y, hipStream_t st,
-                          hipEvent_t e0, hipEvent_t e1) {
-    return near_mm_t<float>(a, pp, panel, use_near, csr_val, F, R, dtype, x, y, st, e0, e1);
+                          hipEvent_t e0, hipEvent_t e1, const MmFar<float>& fo) {
+    return near_mm_t<float>(a, pp, panel, use_near, csr_val, F, R, dtype, x, y, st, e0, e1, fo);
 }
 
 // FP32 copy of FP64 operator data (mixed precision)
