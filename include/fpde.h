@@ -148,9 +148,9 @@ fpde_status fpde_build(const fpde_mesh *mesh, int32_t n_fields, const double *s,
 /* y = A x for F fields and nrhs right-hand sides (Sec. 3: y = (B+M)x + K~x).
  *   dtype     FPDE_F64: x, y are double; FPDE_F32: float
  *   x, y      device [F][N][nrhs], must not alias
- * Asynchronous on hip_stream: kernel launches on that stream (with several
- * right-hand sides the far field runs on the operator's side stream, forked
- * from and joined back to hip_stream with events).  Calls on one operator
+ * Asynchronous on hip_stream: kernel launches on that stream (on the
+ * fallback paths for K > 32 or wide nrhs the far field runs on the operator's
+ * side stream, forked from and joined back to hip_stream with events).  Calls on one operator
  * must not run concurrently from several host threads.
  * Errors: FPDE_EINVAL, FPDE_ESTATE, FPDE_EDEVICE. */
 fpde_status fpde_apply(fpde_op *op, int32_t dtype, const void *x, void *y, int64_t nrhs,
