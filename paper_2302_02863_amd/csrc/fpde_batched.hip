@@ -25,11 +25,11 @@ constexpr int kRC = 64;   // right-hand sides per block
 
 // X^_leaf[alpha][r] = sum_j U[j][alpha] x[perm[j]][r]: a (K <= 32) x 64 x n GEMM per
 // (leaf, rhs chunk, field) on MFMA, two waves of 32 right-hand sides, leaf rows
-// staged in LDS 64 at a time (alpha and the row count padded with zeros).
+// staged in LDS 32 at a time (alpha and the row count padded with zeros).
 template <typename T>
 __global__ __launch_bounds__(128) void k_bup_leaf(ApplyPlan a, H2Tree t, int F, int R, const T* U, int dtype,
                                                   const void* x, T* xh) {
-    constexpr int JC = 64, US = 33, XS = kRC + 1;
+    constexpr int JC = 32, US = 33, XS = kRC + 1;
     __shared__ T sU[JC * US];    // [row][alpha]
     __shared__ T sX[JC * XS];    // [row][r]
     const int K = t.k;
