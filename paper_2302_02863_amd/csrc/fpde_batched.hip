@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_blevel(H2Tree t, int64_t c0, int F, int
 // (target cluster, rhs chunk, field); S_e and X^_src(e) are staged in LDS per pair.
 // K <= 32: alpha and beta are padded to 32 with zeros.
 template <typename T>
-__global__ __launch_bounds__(128) void k_bcoupling(H2Tree t, int F, int R, const T* St, const T* xh, T* yh) {
+__device__ __forceinline__ void bcoupling_body(const H2Tree& t, int F, int R, const T* St, const T* xh, T* yh) {
     constexpr int KP = 32, SS = KP + 1, XS = kRC + 1;
     __shared__ T sS[KP * SS];    // [beta][alpha]
     __shared__ T sX[KP * XS];    // [beta][r]
@@ -280,6 +280,17 @@ __global__ __launch_bounds__(128) void k_bcoupling(H2Tree t, int F, int R, const
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(128) void k_bcoupling(H2Tree t, int F, int R, const T* St, const T* xh, T* yh) {
+    bcoupling_body<T>(t, F, R, St, xh, yh);
+}
+// FP64: 200 VGPRs unconstrained (two waves per SIMD); held to three waves per SIMD
+template <>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k_bcoupling<double>(
+    H2Tree t, int F, int R, const double* St, const double* xh, double* yh) {
+    bcoupling_body<double>(t, F, R, St, xh, yh);
+}
+
 namespace {
 
 template <typename T>
@@ -324,16 +335,16 @@ hipError_t apply_batched_t(const ApplyPlan& a, const H2Tree& t, const PanelPlan&
     // run beside the near kernel on a second stream, the chain's small dependent launches
     // wait behind the near kernel's blocks and end up on the critical path.
     const bool far = (parts & 8) != 0;
-    if (ev) hipEventRecord(ev[0], st);
+    if (ev) (void)hipEventRecord(ev[0], st);
     hipError_t e = hipSuccess;
     if (far && (e = far_batched_t<T>(a, t, F, R, od, dtype, x, xh, yh, st)) != hipSuccess) return e;
-    if (ev) hipEventRecord(ev[1], st);
+    if (ev) (void)hipEventRecord(ev[1], st);
     MmFar<T> fo{};
     if (far) fo = MmFar<T>{yh, od.Upad, t.ncl, t.first_leaf, t.k};
     e = launch_near_mm(a, pp, od.panel, (parts & 4) != 0, csr_val, F, R, dtype, x, y, st, ev ? ev[2] : nullptr,
                        ev ? ev[3] : nullptr, fo);
     if (e != hipSuccess) return e;
-    if (ev) hipEventRecord(ev[4], st);
+    if (ev) (void)hipEventRecord(ev[4], st);
     return hipGetLastError();
 }
 
