@@ -51,8 +51,9 @@ hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const 
 
 // ------------------------------------------------------------ several right-hand sides: MFMA panels
 //
-// Y[rows, r0:r0+64] = Panel[rows, :] X[cols, r0:r0+64] + (B+M)[rows, :] X, one
-// block per (leaf, 64-row tile, 64-column tile of right-hand sides, field).
+// Y[rows, r0:r0+64] = Panel[rows, :] X[cols, r0:r0+64] + (B+M)[rows, :] X
+// (+ U[rows, :] Y^_leaf[:, r0:r0+64] when the far field's coefficients are given),
+// one block per (leaf, 64-row tile, 64-column tile of right-hand sides, field).
 // The panel times the gathered rows of X is a dense GEMM of 64 x 64 x
 // pstride; four waves each own a 32 x 32 quarter of the tile:
 //   FP32 operator data: v_mfma_f32_32x32x2f32, two k per step (lane l supplies
@@ -65,9 +66,11 @@ hipError_t launch_pack_panels(int64_t nleaf, int64_t cap, int64_t npairs, const 
 // The panel chunk is stored in LDS with its columns permuted (column KS*s + g
 // of the chunk at position g*(32/KS) + s, KS = k per step), so each lane reads
 // the A values of all its steps with 16-byte LDS reads; X stays row-major.  The
-// leaf's panel column list is staged in LDS once.  The tile then goes to LDS
-// and each thread adds the B + M row (FP64; the ELL form by leaf slot when the
-// operator holds it) for one right-hand side and writes y.
+// leaf's panel column list is staged in LDS once.  The far field's leaf output
+// U Y^ is one more chunk of the same GEMM (A = the tile's basis rows by leaf
+// slot, B = the leaf's coefficients, both padded to 32).  The tile then goes to
+// LDS and each thread adds the B + M row (FP64; the ELL form by leaf slot when
+// the operator holds it) for one right-hand side and writes y.
 typedef float fpde_f32x16 __attribute__((ext_vector_type(16)));
 typedef double fpde_f64x4 __attribute__((ext_vector_type(4)));
 
