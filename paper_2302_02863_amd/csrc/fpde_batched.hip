@@ -121,7 +121,7 @@ template <int D, int P, typename T, bool UP>
 __global__ __launch_bounds__(256) void k_blevel(H2Tree t, int64_t c0, int F, int R, const T* E, T* xh) {
     constexpr int K = KR<D, P>::K, EP = KR<D, P>::EP;
     __shared__ T sE[2 * EP];
-    __shared__ T sA[2 * K * kRC];   // up: both children; down: the parent (first K * kRC)
+    __shared__ T sA[(UP ? 2 : 1) * K * kRC];   // up: both children; down: the parent
     __shared__ T sT[2 * K * kRC];   // after the first dimension
     const int64_t nrc = (R + kRC - 1) / kRC;
     const int64_t c = c0 + blockIdx.x / nrc;
