@@ -430,26 +430,41 @@ void plan(fpde_op& op) {
                 break;
             }
     partition(op.rt, op.opts.eta, 2.0 * op.hmax, &skip, op.rfar, op.rnear);
-    // CSR pattern of B (and M) in tree order
-    std::vector<std::tuple<int64_t, int64_t>> ent;
-    int32_t dofs[5];
-    for (const Pair& p : op.pairs) {
-        int nd = pair_dofs(m, p, dofs);
-        for (int a = 0; a < nd; ++a) {
-            if (dofs[a] >= m.N) continue;
-            for (int b = 0; b < nd; ++b)
-                if (dofs[b] < m.N) ent.emplace_back(op.pos_of_dof[dofs[a]], op.pos_of_dof[dofs[b]]);
+    // CSR pattern of B (and M) in tree order: the (row, column) entries of every pair,
+    // bucketed by row, then each row's columns sorted and made unique
+    {
+        int32_t dofs[5];
+        std::vector<int64_t> cnt(m.N + 1, 0);
+        for (const Pair& p : op.pairs) {
+            const int nd = pair_dofs(m, p, dofs);
+            int ni = 0;
+            for (int b = 0; b < nd; ++b) ni += dofs[b] < m.N;
+            for (int a = 0; a < nd; ++a)
+                if (dofs[a] < m.N) cnt[op.pos_of_dof[dofs[a]] + 1] += ni;
+        }
+        for (int64_t i = 0; i < m.N; ++i) cnt[i + 1] += cnt[i];
+        std::vector<int32_t> col(cnt[m.N]);
+        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+        for (const Pair& p : op.pairs) {
+            const int nd = pair_dofs(m, p, dofs);
+            for (int a = 0; a < nd; ++a) {
+                if (dofs[a] >= m.N) continue;
+                const int64_t row = op.pos_of_dof[dofs[a]];
+                for (int b = 0; b < nd; ++b)
+                    if (dofs[b] < m.N) col[fill[row]++] = (int32_t)op.pos_of_dof[dofs[b]];
+            }
+        }
+        op.csr_ptr.assign(m.N + 1, 0);
+        op.csr_col.clear();
+        op.csr_col.reserve(col.size() / 2);
+        for (int64_t i = 0; i < m.N; ++i) {
+            auto b = col.begin() + cnt[i], e = col.begin() + cnt[i + 1];
+            std::sort(b, e);
+            e = std::unique(b, e);
+            op.csr_col.insert(op.csr_col.end(), b, e);
+            op.csr_ptr[i + 1] = (int64_t)op.csr_col.size();
         }
     }
-    std::sort(ent.begin(), ent.end());
-    ent.erase(std::unique(ent.begin(), ent.end()), ent.end());
-    op.csr_ptr.assign(m.N + 1, 0);
-    op.csr_col.resize(ent.size());
-    for (size_t e = 0; e < ent.size(); ++e) {
-        op.csr_ptr[std::get<0>(ent[e]) + 1]++;
-        op.csr_col[e] = (int32_t)std::get<1>(ent[e]);
-    }
-    for (int64_t i = 0; i < m.N; ++i) op.csr_ptr[i + 1] += op.csr_ptr[i];
     op.stats.t_plan_ms = ms_since(t0);
 }
 

@@ -250,11 +250,18 @@ Tree kd_tree(int dim, const double* pts, int64_t stride, int64_t n, int leaf) {
         for (int k = 1; k < dim; ++k)
             if (hi[k] - lo[k] > hi[axis] - lo[axis]) axis = k;
         const double* px = pts + axis * stride;
-        std::sort(t.perm.begin() + b, t.perm.begin() + e, [px](int64_t i, int64_t j) {
+        const auto less = [px](int64_t i, int64_t j) {
             if (px[i] != px[j]) return px[i] < px[j];
             return i < j;
-        });
+        };
         int64_t half = (e - b) / 2;
+        // The split only needs the first half in (coordinate, id) order as a set; the last
+        // internal level sorts fully, which fixes the order inside every leaf (and so the
+        // whole permutation) exactly as full sorts at every level would.
+        if (c >= (int64_t(1) << (L - 1)) - 1)
+            std::sort(t.perm.begin() + b, t.perm.begin() + e, less);
+        else
+            std::nth_element(t.perm.begin() + b, t.perm.begin() + b + half, t.perm.begin() + e, less);
         t.beg[2 * c + 1] = b;
         t.end[2 * c + 1] = b + half;
         t.beg[2 * c + 2] = b + half;
