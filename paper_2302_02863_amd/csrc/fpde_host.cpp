@@ -388,11 +388,14 @@ void plan(fpde_op& op) {
     op.ncs = node_cells(m);
     op.pairs = touching_pairs(m, op.ncs);
     op.hmax = h_max(m);
-    // device order of pairs: by kind (uniform waves)
-    op.pair_order.resize(op.pairs.size());
-    std::iota(op.pair_order.begin(), op.pair_order.end(), 0);
-    std::stable_sort(op.pair_order.begin(), op.pair_order.end(),
-                     [&](int64_t a, int64_t b) { return op.pairs[a].kind < op.pairs[b].kind; });
+    // device order of pairs: by kind (uniform waves), pair order kept within a kind
+    {
+        int64_t start[4] = {0, 0, 0, 0};
+        for (const Pair& p : op.pairs) ++start[p.kind + 1];
+        for (int k = 0; k < 3; ++k) start[k + 1] += start[k];
+        op.pair_order.resize(op.pairs.size());
+        for (int64_t i = 0; i < (int64_t)op.pairs.size(); ++i) op.pair_order[start[op.pairs[i].kind]++] = i;
+    }
     // K tree over the dofs, extended boxes (supports of the members' basis functions)
     op.kt = kd_tree(d, m.X.data(), m.M, m.N, op.opts.leaf_size);
     Tree& kt = op.kt;
