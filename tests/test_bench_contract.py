@@ -1,0 +1,38 @@
+"""CPU checks of bench.py's command-line contract (no GPU needed): more than one GPU
+is refused with a JSON message and a non-zero exit; the algorithmic byte count of the
+dominant kernel follows its stated formula."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=ROOT)
+    assert r.returncode != 0
+    line = [ln for ln in r.stdout.splitlines() if ln.strip()][-1]
+    msg = json.loads(line)
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_algorithmic_bytes_formula():
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+
+    class FakeOp:   # two leaves of 3 and 2 points, near pairs (0,0), (0,1), (1,1)
+        def export(self, what):
+            if what == "K_LEAFPTR":
+                return np.array([0, 3, 5])
+            if what == "K_NEAR":
+                return np.array([1, 1, 1, 2, 2, 2])
+            raise KeyError(what)
+
+    st = {"k_levels": 2, "n_dofs": 5, "csr_nnz": 13, "k_rank": 4, "k_clusters": 3}   # leaves are heap ids 1, 2
+    b, near = bench.algorithmic_bytes_near(FakeOp(), st, 1, 1, 2, 2)
+    assert near == 3 * 3 + 3 * 2 + 2 * 2
+    expect = near * 8 + 13 * (8 + 4) + 6 * 8 + 2 * 5 * 8 + 5 * 4 * 8 + 3 * 2 * 2 * 2 * 8 + 3 * 4 * 8
+    assert b == expect
