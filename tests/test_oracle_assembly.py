@@ -118,3 +118,22 @@ def test_closed_form_disk():
     errs = [_closed_form_error(configs.disk(n, s_const=0.7, nq_sing=6)) for n in (8, 16)]
     assert errs[1] < 0.75 * errs[0], errs
     assert errs[1] < 0.01, errs
+
+
+@pytest.mark.parametrize("s", [0.6, 0.8])
+def test_condition_number_grows_like_h_to_minus_2s(s):
+    # Sec. 7.2 observes a condition number close to O(h^{-2 s}) for the background order s;
+    # for constant s on the interval the exact Galerkin matrix follows it closely (the
+    # fitted log-log slope is within 0.01 of -2 s for h = 1/8 .. 1/32). A wrong power of
+    # |x - y| in the kernel changes the slope.
+    ks, hs = [], []
+    for n in (16, 32, 64):
+        P = configs.interval_const(n_int=n, s=s)
+        A = assemble_exact(P.mesh, P.s[0], P.kappa[0], P.opts, all_columns=False)
+        A = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+        ev = np.linalg.eigvalsh(0.5 * (A + A.T))
+        assert ev[0] > 0
+        ks.append(ev[-1] / ev[0])
+        hs.append(2.0 / n)
+    slope = np.polyfit(np.log(hs), np.log(ks), 1)[0]
+    assert abs(slope + 2 * s) < 0.05, slope
