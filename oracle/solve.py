@@ -6,6 +6,10 @@
 * ``conjugate_gradient``: textbook unpreconditioned CG (Hestenes-Stiefel) on
   a dense matrix, used to compare iteration counts and stopping behaviour
   (relative residual ||F - A u|| / ||F||).
+* ``l2_error``: ||u - U_h||_{L2} / ||u||_{L2} over the interior cells (the
+  norm of Sec. 7), for a P1 solution U_h (zero on the non-dof nodes) against a
+  function u given pointwise, by a 7-point-per-direction rule on each cell
+  (collapsed coordinates on triangles).
 
 Pinned by tests/test_oracle_solve.py: CG and Cholesky agree, the residual of
 both vanishes to rounding, and the closed-form solutions of the fractional
@@ -15,6 +19,8 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.linalg
+
+from .rules import barycentric_ref, gauss01
 
 
 def solve_dense(A: np.ndarray, F: np.ndarray) -> np.ndarray:
@@ -45,3 +51,35 @@ def conjugate_gradient(A: np.ndarray, F: np.ndarray, rtol: float = 1e-10, maxit:
         rr = rr_new
         it += 1
     return u, it, float(np.sqrt(rr)) / fn
+
+
+def l2_error(mesh, u_dofs: np.ndarray, u_exact, n: int = 7) -> float:
+    """Relative L2 error over the interior cells of the P1 function with dof values u_dofs.
+
+    ``u_exact(x)`` takes points (dim, nq) and returns values (nq,).
+    """
+    g, w = gauss01(n)
+    if mesh.dim == 1:
+        xh, wt = g[None, :], w
+    else:
+        Z, E = np.meshgrid(g, g, indexing="ij")
+        xh = np.stack([Z.ravel(), (Z * E).ravel()])
+        wt = (np.outer(w, w) * Z).ravel()
+    lam = barycentric_ref(mesh.dim, xh)                     # (dim+1, nq)
+    full = np.zeros(mesh.n_nodes)
+    full[:mesh.n_dofs] = u_dofs
+    err2 = nrm2 = 0.0
+    for c in np.flatnonzero(mesh.cell_interior):
+        v = mesh.cells[:, c]
+        X = mesh.coords[:, v]
+        if mesh.dim == 1:
+            J = X[:, 1:] - X[:, :1]
+        else:
+            J = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 1]], axis=1)
+        det = abs(np.linalg.det(J))
+        x = X[:, :1] + J @ xh
+        uh = full[v] @ lam
+        ue = u_exact(x)
+        err2 += det * float((wt * (uh - ue) ** 2).sum())
+        nrm2 += det * float((wt * ue ** 2).sum())
+    return float(np.sqrt(err2 / nrm2))
