@@ -1,19 +1,26 @@
 """Benchmark of the stiffness-operator apply on one MI355X.
 
-One step = one application y = A x of the whole decomposed operator
-(A = B + M + K~: CSR near field + weighted mass, dense near leaf blocks, H2
-far field) to the workload's right-hand side(s), inputs resident in HBM.
+One step = one application Y = A X of the whole decomposed operator
+(A = B + M + K~: rows of B + M, dense near leaf blocks, H2 far field) to every
+right-hand side of every order field of the workload, inputs resident in HBM.
 
-Metric: DOF-matvecs/s = N * F * R * steps / elapsed.  The default workload is
-the 2D unit square with 128 x 128 cells split in two (16129 dofs, 131072 cells
-including the exterior band), jittered nodes, variable order and diffusivity,
-leaf 64, 5 Chebyshev points per dimension, eta = 1, one right-hand side.
+Headline workload: the 2D unit square with 256 x 256 cells split in two
+(65025 dofs, 524288 cells including the exterior band), 16 order fields
+s_k = 0.5 + 0.3 sin(k pi x1) cos(pi x2), 64 right-hand sides each (FP32
+vectors), leaf 64, 5 Chebyshev points per dimension, eta = 1, applied by the
+mixed-precision operator (FP32 near panels, bases, transfers and coupling on
+FP32 MFMA; FP64 rows of B + M and FP64 accumulation of each output).
 
-Prints one JSON line (see the contract in the repository docs) with a
-roofline entry for the dominant kernel (k_near_up: CSR of B + M, packed near
-leaf blocks, and the upsweep of the far field in the same launch) measured
-with HIP events on the apply stream, and a CPU baseline of the oracle on a
-bounded sample of rows of the same workload.
+Metric: DOF-matvecs/s = N * F * R * steps / elapsed of the mixed apply, which
+counts only when its relative error against the FP64 apply (max over the
+1024 vectors of ||y - y64|| / ||y64||) is within 1e-6; the FP64 path's time on
+the same vectors gives the speedup.
+
+Prints one JSON line with a roofline entry for the dominant kernel
+(k_near_mm<float>, the near-panel GEMM on MFMA, timed with HIP events on the
+apply stream), a CPU baseline of the oracle, and extras: the one-vector
+square-128 apply, the disk solve (mixed CG with refinement against FP64 CG),
+the batched solve, adjoint timings and build/apply times for growing N.
 """
 from __future__ import annotations
 
@@ -28,82 +35,65 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+FP64_MFMA_PEAK_TFLOPS = 78.6
+MIXED_TOL = 1e-6
+METRIC = "DOF-matvecs/s of stiffness apply at 1e-6 rel err; mixed vs FP64 path speedup"
 
 
-def workload(name: str):
-    from fpde_inputs import configs
-    if name == "square":
-        return configs.square(128), {"workload": "square-128x128-P1 (16129 dofs, 131072 cells), variable s and kappa",
-                                     "n": 128, "leaf": 64, "cheb_p": 5, "eta": 1.0, "nrhs": 1, "fields": 1}
-    if name == "square-small":
-        return configs.square(32), {"workload": "square-32x32-P1", "n": 32, "nrhs": 1, "fields": 1}
-    raise SystemExit(f"unknown workload {name}")
+# ---------------------------------------------------------------------------- helpers
 
-
-def algorithmic_bytes_near(op, st, F, R, dim, p):
-    """HBM bytes one launch of the near/upsweep kernel must move, no re-reads counted:
-    the near leaf blocks (sum over near pairs of |s| |s'| FP64 entries), the nonzeros
-    of B + M (FP64 values, int32 columns) and one 8-byte index per row, x read once,
-    y written once, the leaf bases U (N x k FP64) and the transfers (D P^2 per
-    cluster) read once, the cluster coefficients (k per cluster) written once.  The
-    kernel reads B + M in an ELL form by leaf slot; its padding is not counted."""
+def near_entries(op, st):
+    """Sum over the near leaf pairs of |sigma| |sigma'| (entries of the dense near blocks)."""
     leafptr = op.export("K_LEAFPTR")
     sizes = leafptr[1:] - leafptr[:-1]
     pairs = op.export("K_NEAR").reshape(-1, 2)
     first = (1 << (int(st["k_levels"]) - 1)) - 1
-    near_entries = int((sizes[pairs[:, 0] - first] * sizes[pairs[:, 1] - first]).sum())
+    return int((sizes[pairs[:, 0] - first] * sizes[pairs[:, 1] - first]).sum())
+
+
+def algorithmic_bytes_near(op, st, F, R, dim, p):
+    """HBM bytes one launch of the one-vector near/upsweep kernel must move, no re-reads
+    counted: the near leaf blocks (sum over near pairs of |s| |s'| FP64 entries), the
+    nonzeros of B + M (FP64 values, int32 columns) and one 8-byte index per row, x read
+    once, y written once, the leaf bases U (N x k FP64) and the transfers (D P^2 per
+    cluster) read once, the cluster coefficients (k per cluster) written once.  The
+    kernel reads B + M in an ELL form by leaf slot; its padding is not counted."""
+    ne = near_entries(op, st)
     N = st["n_dofs"]
     nnz = st["csr_nnz"]
-    b = F * near_entries * 8
+    b = F * ne * 8
     b += F * nnz * 8 + nnz * 4 + (N + 1) * 8
     b += 2 * F * N * R * 8
     k, ncl = int(st["k_rank"]), int(st["k_clusters"])
     b += N * k * 8 + ncl * dim * p * p * 8 + F * ncl * k * 8
-    return b, near_entries
+    return b, ne
 
 
-def measured_traffic(kernel_name):
-    """HBM traffic of the dominant kernel from the committed rocprofv3 counter record,
-    valid only while the kernel source is unchanged (else None)."""
+def algorithmic_flops_near_mm(op, st, F, R):
+    """MFMA flops of one launch of the several-right-hand-side near kernel: the dense near
+    panels times the gathered rows of X (2 x near entries x F x R) plus the far field's
+    leaf output U Y^ (2 x N x k x F x R).  The FP64 rows of B + M (2 x nnz x F x R vector
+    flops) run on the vector units and are not counted against the MFMA peak."""
+    ne = near_entries(op, st)
+    N, k = int(st["n_dofs"]), int(st["k_rank"])
+    return 2.0 * ne * F * R + 2.0 * N * k * F * R, ne
+
+
+def committed_record(name, sources):
+    """A committed rocprofv3 record under profiles/, valid only while the listed kernel
+    sources are unchanged (their sha256 is stored in the record); else None."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "traffic_%s_square128.json" % kernel_name)
-    src = os.path.join(ROOT, "paper_2302_02863_amd", "csrc", "fpde_apply.hip")
+    path = os.path.join(ROOT, "profiles", name)
     try:
-        rec = json.load(open(rec_path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except OSError:
+        rec = json.load(open(path))
+        for src in sources:
+            sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2302_02863_amd", "csrc", src), "rb").read()).hexdigest()
+            if rec.get("source_sha256", {}).get(src) != sha:
+                return None
+    except (OSError, ValueError, AttributeError):
         return None
-    if rec.get("kernel") != kernel_name or rec.get("source_sha256") != sha:
-        return None
-    return rec["traffic_bytes_per_launch"]
-
-
-def cpu_baseline(P, seconds: float = 15.0):
-    """Oracle rows of A_h x computed one by one on the host cores (bounded sample)."""
-    import numpy as np
-    from oracle.sampled import SampledOracle
-    np.seterr(divide="ignore", invalid="ignore")
-    t0 = time.perf_counter()
-    so = SampledOracle(P.mesh, P.s[0], P.kappa[0], P.opts)
-    t_setup = time.perf_counter() - t0
-    rng = np.random.default_rng(11)
-    rows = rng.choice(P.mesh.n_dofs, size=64, replace=False)
-    done = 0
-    t1 = time.perf_counter()
-    for r in rows:
-        so.row_apply([int(r)], P.x[0, :, 0])
-        done += 1
-        if time.perf_counter() - t1 > seconds:
-            break
-    el = time.perf_counter() - t1
-    try:
-        import threadpoolctl
-        cores = max(i["num_threads"] for i in threadpoolctl.threadpool_info()) if threadpoolctl.threadpool_info() else 1
-    except Exception:
-        cores = os.cpu_count() or 1
-    return {"value": done / el, "unit": "DOF-matvecs/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{done} rows of A_h x on the same workload computed entry by entry by the FP64 oracle "
-                      f"(tree/partition/basis setup {t_setup:.1f} s excluded, rows {el:.1f} s)"}
+    return rec
 
 
 def time_applies(op, x, y, stream, steps, warmup, parts=None):
@@ -119,64 +109,39 @@ def time_applies(op, x, y, stream, steps, warmup, parts=None):
     return time.perf_counter() - t1
 
 
-def mixed_and_solve(P, op64, x, y64, stream, steps, warmup):
-    """Mixed-precision apply (FP32 near panels, bases, transfers, coupling; FP64 CSR of B + M)
-    against the FP64 path on the same workload, and FP64 CG versus mixed CG with iterative
-    refinement on the load vector of f = 1."""
-    import numpy as np
+def profiled(op, x, y, n=10):
+    """Per-apply device times from HIP events on the apply stream (fpde_profile)."""
     import torch
-    import paper_2302_02863_amd as fp
-    o = dict(P.opts)
-    o["precision"] = "mixed"
-    opm = fp.Operator(P.mesh, P.s, P.kappa, o)
-    ym = torch.empty_like(x)
-    el_m = time_applies(opm, x, ym, stream, steps, warmup)
-    err = float(torch.linalg.vector_norm(ym - y64) / torch.linalg.vector_norm(y64))
-    out = {"value": P.mesh.n_dofs * x.shape[0] * x.shape[2] * steps / el_m,
-           "ms_per_step": el_m / steps * 1e3, "max_rel_err_vs_fp64": err}
-    # solves: A u = F, F the load vector of f = 1 (computed by the library)
-    F = op64.load_vector(torch.ones(P.mesh.n_nodes, dtype=torch.float64, device=x.device)).reshape(1, -1, 1)
-    F = F.expand(x.shape[0], -1, -1).contiguous()
-    res = {}
-    for name, op in (("fp64", op64), ("mixed", opm)):
-        op.solve(F, rtol=1e-10, maxit=20000)        # warm-up (captures the CG graphs)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        u, info = op.solve(F, rtol=1e-10, maxit=20000)
-        torch.cuda.synchronize()
-        res[name] = (time.perf_counter() - t0, u, info)
-    uerr = float(torch.linalg.vector_norm(res["mixed"][1] - res["fp64"][1]) / torch.linalg.vector_norm(res["fp64"][1]))
-    out["solve"] = {"rtol": 1e-10, "fp64_ms": res["fp64"][0] * 1e3, "mixed_ms": res["mixed"][0] * 1e3,
-                    "fp64_iterations": res["fp64"][2]["iterations"],
-                    "mixed_iterations": res["mixed"][2]["iterations"],
-                    "mixed_refinements": res["mixed"][2]["refinements"],
-                    "speedup": res["fp64"][0] / res["mixed"][0],
-                    "mixed_vs_fp64_solution_rel_diff": uerr}
-    opm.close()
-    return out
+    op.profile(True)
+    for _ in range(n):
+        op.apply(x, y)
+    torch.cuda.synchronize()
+    pr = op.profile(False)
+    return {k: pr[k] / pr["n_applies"] for k in ("ms_far", "ms_out", "ms_far_out", "ms_total")}
 
 
-def near_entries(op, st):
-    leafptr = op.export("K_LEAFPTR")
-    sizes = leafptr[1:] - leafptr[:-1]
-    pairs = op.export("K_NEAR").reshape(-1, 2)
-    first = (1 << (int(st["k_levels"]) - 1)) - 1
-    return int((sizes[pairs[:, 0] - first] * sizes[pairs[:, 1] - first]).sum())
+def per_vector_rel_err(y, yref):
+    """max over (field, rhs) of ||y - yref||_2 / ||yref||_2 (vectors along N)."""
+    import torch
+    d = torch.linalg.vector_norm((y.double() - yref.double()), dim=1)
+    r = torch.linalg.vector_norm(yref.double(), dim=1)
+    return float((d / r).max())
 
 
-def batched(steps, warmup):
-    """The batched workload: 256 x 256 squares (65025 dofs), 16 order fields x 64
-    right-hand sides (FP32 vectors), FP64 operator against the mixed-precision one.
-    The near-panel GEMM (k_near_mm) is MFMA-bound: 2 * entries * F * R flops."""
+# ---------------------------------------------------------------------------- headline
+
+def headline(steps, warmup):
+    """Batched square 256: 16 order fields x 64 right-hand sides, mixed against FP64."""
     import torch
     import paper_2302_02863_amd as fp
     from fpde_inputs import configs
     P = configs.batched(256, n_fields=16, nrhs=64)
     F, N, R = P.x.shape
     x = torch.tensor(P.x, device="cuda:0", dtype=torch.float32)
-    out = {"workload": "square-256x256-P1 batched (65025 dofs), 16 order fields x 64 rhs, FP32 vectors"}
-    ys = {}
-    for prec, peak in (("fp64", 78.6), ("mixed", 157.3)):
+    stream = torch.cuda.current_stream()
+    out = {}
+    ops, ys = {}, {}
+    for prec in ("mixed", "fp64"):
         o = dict(P.opts)
         o["precision"] = prec
         t0 = time.perf_counter()
@@ -184,24 +149,166 @@ def batched(steps, warmup):
         torch.cuda.synchronize()
         build = time.perf_counter() - t0
         y = torch.empty_like(x)
-        el = time_applies(op, x, y, torch.cuda.current_stream(), steps, warmup)
-        op.profile(True)
-        for _ in range(3):
-            op.apply(x, y)
-        torch.cuda.synchronize()
-        pr = op.profile(False)
-        near_ms = pr["ms_out"] / pr["n_applies"]
-        flops = 2.0 * near_entries(op, op.stats()) * F * R
-        tf = flops / (near_ms * 1e-3) / 1e12
+        el = time_applies(op, x, y, stream, steps, warmup)
+        ph = profiled(op, x, y)
+        st = op.stats()
+        flops, ne = algorithmic_flops_near_mm(op, st, F, R)
+        kname = "k_near_mm<%s>" % ("float" if prec == "mixed" else "double")
+        peak = FP32_MFMA_PEAK_TFLOPS if prec == "mixed" else FP64_MFMA_PEAK_TFLOPS
+        tf = flops / (ph["ms_out"] * 1e-3) / 1e12
         out[prec] = {"value": N * F * R * steps / el, "ms_per_step": el / steps * 1e3, "build_s": build,
-                     "near_mfma": {"kernel": "k_near_mm<%s>" % ("double" if prec == "fp64" else "float"),
-                                   "avg_ms": near_ms, "tflops": tf, "peak_tflops": peak, "frac": tf / peak},
-                     "phases_ms_per_apply": {k: pr[k] / pr["n_applies"] for k in ("ms_far", "ms_out", "ms_far_out",
-                                                                                  "ms_total")}}
-        ys[prec] = y.double()
-        op.close()
-    out["mixed_speedup"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
-    out["mixed_max_rel_err_vs_fp64"] = float((ys["mixed"] - ys["fp64"]).norm() / ys["fp64"].norm())
+                     "phases_ms_per_apply": {"far_chain": ph["ms_far"], "near_kernel": ph["ms_out"],
+                                             "total": ph["ms_total"]},
+                     "near_kernel": {"kernel": kname, "avg_ms": ph["ms_out"], "flops_per_launch": flops,
+                                     "tflops": tf, "peak_tflops": peak, "frac": tf / peak},
+                     "build_phase_ms": {k: st[k] for k in ("t_plan_ms", "t_singular_ms", "t_rho_ms", "t_mass_ms",
+                                                           "t_bases_ms", "t_near_blocks_ms")}}
+        ops[prec] = op
+        ys[prec] = y
+    out["near_entries_per_field"] = ne
+    out["counts"] = {k: st[k] for k in ("n_dofs", "csr_nnz", "k_near", "k_far", "k_leaves", "k_rank")}
+    out["max_rel_err_vs_fp64"] = per_vector_rel_err(ys["mixed"], ys["fp64"])
+    out["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    # the far field's own share of the mixed error (fpde_apply_parts with the far blocks only)
+    yk = ops["mixed"].apply(x, parts=fp.PART_KFAR)
+    yk64 = ops["mixed"].apply(x, parts=fp.PART_KFAR | fp.PART_FP64)
+    ynear = ops["mixed"].apply(x, parts=fp.PART_KNEAR)
+    ynear64 = ops["mixed"].apply(x, parts=fp.PART_KNEAR | fp.PART_FP64)
+    torch.cuda.synchronize()
+    yref = ys["fp64"].double()
+    yn = torch.linalg.vector_norm(yref, dim=1)
+    out["error_budget"] = {
+        "far_part_err_over_y": float((torch.linalg.vector_norm(yk.double() - yk64.double(), dim=1) / yn).max()),
+        "near_panel_err_over_y": float((torch.linalg.vector_norm(ynear.double() - ynear64.double(), dim=1)
+                                        / yn).max()),
+        "far_part_norm_over_y": float((torch.linalg.vector_norm(yk64.double(), dim=1) / yn).max()),
+        "near_panel_norm_over_y": float((torch.linalg.vector_norm(ynear64.double(), dim=1) / yn).max())}
+    return P, x, ops, out
+
+
+# ---------------------------------------------------------------------------- extras
+
+def square128(steps, warmup):
+    """One vector on the jittered square 128 (16129 dofs): FP64 and mixed, with the HBM
+    roofline of the fused near/upsweep kernel k_near_up<2,5,double>."""
+    import torch
+    import paper_2302_02863_amd as fp
+    from fpde_inputs import configs
+    P = configs.square(128)
+    F, N, R = P.x.shape
+    x = torch.tensor(P.x, device="cuda:0")
+    t0 = time.perf_counter()
+    op = fp.Operator(P.mesh, P.s, P.kappa, P.opts)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    st = op.stats()
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    el = time_applies(op, x, y, stream, steps, warmup)
+    ph = profiled(op, x, y, n=steps)
+    b, _ = algorithmic_bytes_near(op, st, F, R, P.mesh.dim, int(P.opts["cheb_p"]))
+    ach = b / (ph["ms_out"] * 1e-3) / 1e9
+    rec = committed_record("traffic_k_near_up_square128.json", ["fpde_apply.hip"])
+    out = {"workload": "square-128x128-P1 (16129 dofs, 131072 cells), variable s and kappa, 1 rhs",
+           "fp64": {"value": N * steps / el, "ms_per_step": el / steps * 1e3},
+           "roofline": {"bound": "hbm", "kernel": "k_near_up<2,5,double>", "achieved": ach, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_ms": ph["ms_out"],
+                        "traffic": rec["traffic_bytes_per_launch"] if rec else None},
+           "phases_ms_per_apply": ph, "build_s": build_s,
+           "build_phase_ms": {k: st[k] for k in ("t_plan_ms", "t_singular_ms", "t_rho_ms", "t_mass_ms", "t_bases_ms",
+                                                 "t_near_blocks_ms")}}
+    o = dict(P.opts)
+    o["precision"] = "mixed"
+    opm = fp.Operator(P.mesh, P.s, P.kappa, o)
+    ym = torch.empty_like(x)
+    el_m = time_applies(opm, x, ym, stream, steps, warmup)
+    out["mixed"] = {"value": N * steps / el_m, "ms_per_step": el_m / steps * 1e3,
+                    "max_rel_err_vs_fp64": per_vector_rel_err(ym, y), "speedup_vs_fp64": el / el_m}
+    # one-vector solve of the load vector of f = 1
+    Fv = op.load_vector(torch.ones(P.mesh.n_nodes, dtype=torch.float64, device=x.device)).reshape(1, -1, 1)
+    out["solve"] = solve_pair(op, opm, Fv, rtol=1e-10)
+    # adjoint: gradient of w^T A u in every nodal s and kappa
+    out["adjoint_ms"] = time_adjoint(op, x, x)
+    opm.close()
+    op.close()
+    return out
+
+
+def solve_pair(op64, opm, Fv, rtol, maxit=50000, ref_rtol=None):
+    """FP64 CG against mixed CG with refinement on the FP64 residual, same rtol; the
+    solution error of each against a reference solve (FP64 CG to ref_rtol) if given."""
+    import torch
+    res = {}
+    uref = None
+    if ref_rtol is not None:
+        uref, _ = op64.solve(Fv, rtol=ref_rtol, maxit=maxit)
+    for name, op in (("fp64", op64), ("mixed", opm)):
+        op.solve(Fv, rtol=rtol, maxit=maxit)        # warm-up (workspaces allocated on first use)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, info = op.solve(Fv, rtol=rtol, maxit=maxit)
+        torch.cuda.synchronize()
+        res[name] = {"ms": (time.perf_counter() - t0) * 1e3, "iterations": info["iterations"],
+                     "refinements": info["refinements"], "rel_residual": info["rel_residual"]}
+        if uref is not None:
+            res[name]["solution_rel_err"] = per_vector_rel_err(u, uref)
+        res[name]["_u"] = u
+    res["mixed_vs_fp64_solution_rel_diff"] = per_vector_rel_err(res["mixed"].pop("_u"), res["fp64"].pop("_u"))
+    res["rtol"] = rtol
+    res["speedup"] = res["fp64"]["ms"] / res["mixed"]["ms"]
+    return res
+
+
+def time_adjoint(op, w, u, n=3):
+    import torch
+    op.apply_adjoint(w, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        op.apply_adjoint(w, u)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / n * 1e3
+
+
+def disk_solve():
+    """The disk workload (elliptical 512 x 512 grid, 261121 dofs, tanh order profile,
+    exterior beyond R = 1.1): time to a solution within 1e-8 of the reference (FP64 CG
+    to 1e-13), FP64 CG against mixed CG with refinement, both stopped at rtol 1e-10."""
+    import torch
+    import paper_2302_02863_amd as fp
+    from fpde_inputs import configs
+    P = configs.disk(512)
+    t0 = time.perf_counter()
+    op = fp.Operator(P.mesh, P.s, P.kappa, P.opts)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    o = dict(P.opts)
+    o["precision"] = "mixed"
+    opm = fp.Operator(P.mesh, P.s, P.kappa, o)
+    x = torch.tensor(P.x, device="cuda:0")
+    y = torch.empty_like(x)
+    ym = torch.empty_like(x)
+    el = time_applies(op, x, y, torch.cuda.current_stream(), 50, 5)
+    el_m = time_applies(opm, x, ym, torch.cuda.current_stream(), 50, 5)
+    Fv = op.load_vector(torch.ones(P.mesh.n_nodes, dtype=torch.float64, device=x.device)).reshape(1, -1, 1)
+    out = {"workload": "disk-512 (261121 dofs), tanh order profile, exterior beyond R=1.1, f=1",
+           "build_s": build_s, "apply_ms": {"fp64": el / 50 * 1e3, "mixed": el_m / 50 * 1e3},
+           "apply_mixed_rel_err_vs_fp64": per_vector_rel_err(ym, y),
+           "solve": solve_pair(op, opm, Fv, rtol=1e-10, ref_rtol=1e-13)}
+    opm.close()
+    op.close()
+    return out
+
+
+def batched_solve_and_adjoint(P, x, ops):
+    """The headline workload's 1024 systems A_f u = b (b = the N(0,1) vectors in FP64),
+    FP64 CG against mixed CG with refinement to rtol 1e-8; adjoint with one vector per field."""
+    import torch
+    b = x.double().contiguous()
+    out = {"solve": solve_pair(ops["fp64"], ops["mixed"], b, rtol=1e-8, maxit=100000)}
+    out["adjoint_ms_16_fields_1_rhs"] = time_adjoint(ops["fp64"], b[:, :, :1].contiguous(),
+                                                     b[:, :, 1:2].contiguous(), n=2)
+    torch.cuda.synchronize()
     return out
 
 
@@ -232,16 +339,145 @@ def scaling(steps, warmup, sizes=(32, 64, 128, 256)):
     return out
 
 
+def measured_denominators():
+    """Achieved rates of plain library work on this GPU, next to the datasheet peaks:
+    a 1 GiB device-to-device copy (torch) and an 8192^3 FP32 GEMM (torch.mm)."""
+    import torch
+    a = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    n = 20
+    t0 = time.perf_counter()
+    for _ in range(n):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * a.numel() * 8 * n / (time.perf_counter() - t0) / 1e9
+    del a, b
+    m = 8192
+    A = torch.randn(m, m, device="cuda:0")
+    B = torch.randn(m, m, device="cuda:0")
+    C = A @ B
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        C = A @ B
+    torch.cuda.synchronize()
+    gemm_tf = 2 * m ** 3 * 5 / (time.perf_counter() - t0) / 1e12
+    return {"copy_GBps": copy_gbs, "fp32_gemm_TFLOPs": gemm_tf, "hbm_peak_GBps": HBM_PEAK_GBS,
+            "fp32_mfma_peak_TFLOPs": FP32_MFMA_PEAK_TFLOPS, "fp64_mfma_peak_TFLOPs": FP64_MFMA_PEAK_TFLOPS}
+
+
+# ---------------------------------------------------------------------------- CPU baseline
+
+def _host_info():
+    import numpy as np          # noqa: F401  (loads the BLAS threadpoolctl reports)
+    import scipy.linalg         # noqa: F401
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = []
+    try:
+        import threadpoolctl
+        blas = [{k: i.get(k) for k in ("internal_api", "version", "num_threads", "threading_layer")}
+                for i in threadpoolctl.threadpool_info()]
+    except Exception:
+        pass
+    return model, blas
+
+
+def _median(f, n):
+    ts = []
+    for _ in range(n):
+        t0 = time.perf_counter()
+        f()
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def cpu_baseline(P, seconds: float = 15.0):
+    """The FP64 oracle on the host cores.
+
+    value: rows of A_h x of the headline workload (field 0, one right-hand side),
+    computed one by one by the sampled-row oracle (oracle.sampled) for about
+    ``seconds``; its cluster-tree/partition setup is excluded and reported.
+    dense: the dense oracle (assembly, A @ X and Cholesky, median of 5) on the 1D
+    workload at full size (511 dofs), and its A @ X and Cholesky at the square-128
+    size (16129 dofs, 2.1 GB) on an SPD matrix of that size, whose dense assembly
+    by the oracle does not fit a bounded run (O(N^2) kernel evaluations)."""
+    import numpy as np
+    from fpde_inputs import configs
+    from oracle.assembly import assemble_exact, assemble_split, load_vector
+    from oracle.h2 import assemble_h2
+    from oracle.sampled import SampledOracle
+    from oracle.solve import solve_dense
+    np.seterr(divide="ignore", invalid="ignore")
+    model, blas = _host_info()
+    t0 = time.perf_counter()
+    so = SampledOracle(P.mesh, P.s[0], P.kappa[0], P.opts)
+    t_setup = time.perf_counter() - t0
+    rng = np.random.default_rng(11)
+    rows = rng.choice(P.mesh.n_dofs, size=64, replace=False)
+    done = 0
+    t1 = time.perf_counter()
+    for r in rows:
+        so.row_apply([int(r)], P.x[0, :, 0])
+        done += 1
+        if time.perf_counter() - t1 > seconds:
+            break
+    el = time.perf_counter() - t1
+    dense = {}
+    C1 = configs.interval(n_int=512)
+    m = C1.mesh
+    dense["interval512"] = {
+        "n_dofs": m.n_dofs,
+        "assembly_exact_s": _median(lambda: assemble_exact(m, C1.s[0], C1.kappa[0], C1.opts, all_columns=False), 5),
+        "assembly_h2_consistent_s": _median(lambda: assemble_h2(m, C1.s[0], C1.kappa[0], C1.opts), 5)}
+    ref = assemble_h2(m, C1.s[0], C1.kappa[0], C1.opts, split=assemble_split(m, C1.s[0], C1.kappa[0], C1.opts))
+    A = ref["B"] + ref["K"] + ref["M"]
+    X = np.random.default_rng(12).standard_normal((m.n_dofs, 64))
+    Fv = load_vector(m, C1.f, C1.opts)
+    dense["interval512"]["apply_64rhs_s"] = _median(lambda: A @ X, 5)
+    dense["interval512"]["cholesky_solve_s"] = _median(lambda: solve_dense(A, Fv), 5)
+    n2 = 16129
+    G = np.random.default_rng(13).standard_normal((n2, n2))
+    G = G + G.T
+    G[np.diag_indices(n2)] += 4.0 * np.sqrt(n2) + 10.0      # SPD by diagonal dominance of the spectrum
+    X2 = np.random.default_rng(14).standard_normal((n2, 64))
+    x1 = X2[:, 0].copy()
+    dense["square128_size"] = {"n_dofs": n2, "apply_1rhs_s": _median(lambda: G @ x1, 5),
+                               "apply_64rhs_s": _median(lambda: G @ X2, 5),
+                               "cholesky_solve_s": _median(lambda: solve_dense(G, x1), 3),
+                               "note": "SPD matrix of the square-128 size; timings of the oracle's A @ X and "
+                                       "Cholesky routines, which do not depend on the entries"}
+    del G
+    return {"value": done / el, "unit": "DOF-matvecs/s", "cores": os.cpu_count() or 1, "kind": "oracle",
+            "sample": f"{done} rows of A_h x (field 0, one right-hand side) of the headline workload computed "
+                      f"entry by entry by the FP64 sampled-row oracle in {el:.1f} s (its tree/partition/basis "
+                      f"setup, {t_setup:.1f} s, excluded)",
+            "cpu_model": model, "blas": blas, "dense_oracle": dense}
+
+
+# ---------------------------------------------------------------------------- main
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="square")
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision apply and the solves")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 16-field x 64-rhs batched workload")
-    ap.add_argument("--no-scaling", action="store_true", help="skip the build and apply times of square 32..256")
+    ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--no-square", action="store_true")
+    ap.add_argument("--no-disk", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the batched solve and adjoint")
+    ap.add_argument("--no-scaling", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -260,66 +496,51 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(1)
 
-    import numpy as np
-    import torch
-    import paper_2302_02863_amd as fp
-
-    P, cfg = workload(args.workload)
-    dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
-    op = fp.Operator(P.mesh, P.s, P.kappa, P.opts)
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
-    st = op.stats()
+    P, x, ops, hl = headline(args.steps, args.warmup)
     F, N, R = P.x.shape
-    x = torch.tensor(P.x, device=dev)
-    y = torch.empty_like(x)
-    stream = torch.cuda.current_stream()
-    el = time_applies(op, x, y, stream, args.steps, args.warmup)
-    # same launches without the graph, HIP events on the apply stream between the phases
-    op.profile(True)
-    for _ in range(args.steps):
-        op.apply(x, y, stream=stream)
-    torch.cuda.synchronize()
-    prof = op.profile(False)
-    value = N * F * R * args.steps / el
-    out_ms = prof["ms_out"] / max(1, prof["n_applies"])
-    b_out, near_entries = algorithmic_bytes_near(op, st, F, R, P.mesh.dim, int(P.opts.get("cheb_p", 5)))
-    achieved = b_out / (out_ms * 1e-3) / 1e9
-    kname = "k_near_up"
+    mixed = hl["mixed"]
+    kn = mixed["near_kernel"]
+    rec = committed_record("traffic_k_near_mm_float_batched256.json", ["fpde_near.hip"])
     res = {
-        "metric": "DOF-matvecs/s of stiffness apply at 1e-6 rel err; mixed vs FP64 path speedup",
-        "value": value,
+        "metric": METRIC,
+        "value": mixed["value"] if hl["max_rel_err_vs_fp64"] <= MIXED_TOL else 0.0,
         "unit": "DOF-matvecs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
+        "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
-        "config": cfg,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
-                     "kernel": kname + " (B+M rows, dense near leaf blocks, far-field upsweep)",
-                     "bytes_per_launch": b_out, "avg_ms": out_ms},
-        "phases_ms_per_apply": {k: prof[k] / max(1, prof["n_applies"]) for k in ("ms_far", "ms_out", "ms_far_out",
-                                                                               "ms_total")},
-        "build_s": build_s,
-        "build_phase_ms": {k: st[k] for k in ("t_plan_ms", "t_singular_ms", "t_rho_ms", "t_mass_ms", "t_bases_ms",
-                                              "t_near_blocks_ms")},
-        "counts": {k: st[k] for k in ("n_dofs", "csr_nnz", "k_near", "k_far", "k_leaves", "rho_near", "rho_far")},
+        "config": {"workload": "square-256x256-P1 batched: 65025 dofs, 16 order fields x 64 rhs (FP32 vectors), "
+                               "mixed-precision operator",
+                   "n": 256, "fields": F, "nrhs": R, "leaf": 64, "cheb_p": 5, "eta": 1.0, "precision": "mixed"},
+        "roofline": {"bound": "mfma", "kernel": kn["kernel"] + " (near-panel GEMM + far leaf output on FP32 MFMA, "
+                                                             "FP64 rows of B + M)",
+                     "achieved": kn["tflops"], "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": kn["tflops"] / FP32_MFMA_PEAK_TFLOPS, "flops_per_launch": kn["flops_per_launch"],
+                     "avg_ms": kn["avg_ms"], "traffic": rec["traffic_bytes_per_launch"] if rec else None},
+        "max_rel_err_vs_fp64": hl["max_rel_err_vs_fp64"],
+        "speedup_vs_fp64": hl["speedup_vs_fp64"],
+        "headline": hl,
     }
-    if not args.no_mixed:
-        mx = mixed_and_solve(P, op, x, y, stream, args.steps, args.warmup)
-        mx["speedup_vs_fp64"] = mx["value"] / value
-        res["mixed"] = mx
-    if not args.no_batched:
-        res["batched"] = batched(max(5, args.steps // 20), 3)
-    if not args.no_scaling:
-        res["scaling_in_n"] = scaling(max(20, args.steps // 4), 5)
+    extras = {}
+    if not args.no_extras and not args.no_solve:
+        extras["batched_solve_adjoint"] = batched_solve_and_adjoint(P, x, ops)
+    for op in ops.values():
+        op.close()
+    del ops, x
+    if not args.no_extras:
+        extras["measured_denominators"] = measured_denominators()
+        if not args.no_square:
+            extras["square128"] = square128(max(100, args.steps), 20)
+        if not args.no_disk:
+            extras["disk512"] = disk_solve()
+        if not args.no_scaling:
+            extras["scaling_in_n"] = scaling(50, 5)
+    res["extras"] = extras
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(P)
     print(json.dumps(res))

@@ -16,6 +16,9 @@ Named workloads (sizes follow the configurations the library is measured on):
   to R=1.1 and the exterior beyond R handled analytically.
 * ``batched``  2D square without jitter, kappa=1, F order fields
   s_k = 0.5+0.3 sin(k pi x1) cos(pi x2), R right-hand sides ~ N(0,1) (seed 3).
+* ``adjoint_disk``  small disk with an analytic exterior and two fields (the
+  disk's order with kappa = 1, and a perturbed order with kappa = 1 + 0.3 x1),
+  two right-hand sides u ~ N(0,1) (seed 14) and weights w ~ N(0,1) (seed 15).
 """
 from __future__ import annotations
 
@@ -149,3 +152,17 @@ def batched(n: int = 256, pad: int | None = None, n_fields: int = 16, nrhs: int 
     rng = np.random.default_rng(3)
     vec = rng.standard_normal((n_fields, m.n_dofs, nrhs)).astype(np.float32).astype(np.float64)
     return Problem("batched", m, s, kappa, _opts(**kw), np.ones(m.n_nodes), vec)
+
+
+def adjoint_disk(n: int = 8, **kw) -> Problem:
+    """Two (s, kappa) fields on disk(n); x holds u [2, N, 2], extra["w"] the weights w."""
+    kw.setdefault("leaf_size", 6)
+    kw.setdefault("leaf_size_rho", 12)
+    kw.setdefault("cheb_p", 3)
+    P = disk(n, **kw)
+    x1, x2 = P.mesh.coords
+    s = np.stack([P.s[0], P.s[0] + 0.05 * np.sin(2 * np.pi * x1) * np.cos(np.pi * x2)])
+    kappa = np.stack([np.ones_like(x1), 1.0 + 0.3 * x1])
+    u = np.random.default_rng(14).standard_normal((2, P.mesh.n_dofs, 2))
+    w = np.random.default_rng(15).standard_normal((2, P.mesh.n_dofs, 2))
+    return Problem("adjoint_disk", P.mesh, s, kappa, P.opts, P.f, u, {"w": w})

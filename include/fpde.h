@@ -161,8 +161,12 @@ fpde_status fpde_apply(fpde_op *op, int32_t dtype, const void *x, void *y, int64
 fpde_status fpde_apply_parts(fpde_op *op, int32_t parts, int32_t dtype, const void *x, void *y,
                              int64_t nrhs, void *hip_stream);
 
-/* Load vector F_i = int_{Omega_i} f psi_i (per-element rule, f P1-interpolated)
- * for device f_nodal [n_nodes] into device F [N].  Asynchronous. */
+/* Load vector of the weak form's right-hand side, F_i = int_{Omega_i} f psi_i
+ * (Sec. 2.3: A(U, V) = int_{Omega_i} f V for the P1 test functions psi_i),
+ * by the per-element rule of Sec. 5.2 with f P1-interpolated from its nodal
+ * values.  f_nodal: device [n_nodes] double (read); F: device [N] double
+ * (overwritten), caller-owned.  Asynchronous on hip_stream.
+ * Errors: FPDE_EINVAL (NULL pointers), FPDE_ESTATE (plan-only), FPDE_EDEVICE. */
 fpde_status fpde_load_vector(fpde_op *op, const double *f_nodal, double *F, void *hip_stream);
 
 /* Solve A u = F by conjugate gradients (the paper solves with CG, Sec. 7) for
@@ -186,7 +190,7 @@ fpde_status fpde_load_vector(fpde_op *op, const double *f_nodal, double *F, void
 fpde_status fpde_solve(fpde_op *op, const double *F, double *u, int64_t nrhs, double rtol,
                        int32_t maxit, fpde_solve_info *info, void *hip_stream);
 
-/* Gradient of J = sum_r w_r^T A_h(s, kappa) u_r with respect to the nodal
+/* alpha times the gradient of J = sum_r w_r^T A_h(s, kappa) u_r with respect to the nodal
  * order s_j and diffusivity kappa_j of every mesh node and field: the
  * derivative of the discrete bilinear form of Sec. 2-3 (A_h as built, Thm. 6.2)
  * for fixed s_bar.  Every dependence goes through the kernel
@@ -194,8 +198,9 @@ fpde_status fpde_solve(fpde_op *op, const double *F, double *u, int64_t nrhs, do
  * Chebyshev points of the singular rules (Sec. 4), the near and far blocks of
  * K~ (Sec. 5) and the density of M~ (Sec. 6.2, eq. e:rho); the P1 weights of
  * s and kappa at those points carry it to the nodes.  For u the solution of
- * A_h u = F and w the solution of A_h w = g, dJ(u)/ds = -grad_s(w, u) gives
- * the gradient of an objective through the solve.
+ * A_h u = F and w the solution of A_h w = g, alpha = -1 gives dJ(u)/ds, the
+ * gradient of an objective through the solve (A_h du = -(dA_h) u at fixed F).
+ *   alpha       finite scale of both outputs (1 for the plain derivative)
  *   w, u        device [F][N][nrhs] double (dof vectors), must not alias the outputs
  *   grad_s,
  *   grad_kappa  device [F][n_nodes] double, overwritten (summed over nrhs)
@@ -203,7 +208,7 @@ fpde_status fpde_solve(fpde_op *op, const double *F, double *u, int64_t nrhs, do
  * the density (no operator data is re-stored).
  * Errors: FPDE_EINVAL, FPDE_ESTATE (plan-only operator, or partitions that are
  * not symmetric / nq_reg too large, reported by fpde_last_error), FPDE_EDEVICE. */
-fpde_status fpde_apply_adjoint(fpde_op *op, const double *w, const double *u, int64_t nrhs,
+fpde_status fpde_apply_adjoint(fpde_op *op, double alpha, const double *w, const double *u, int64_t nrhs,
                                double *grad_s, double *grad_kappa, void *hip_stream);
 
 /* Device-time profile of fpde_apply.  While profiling is on, each apply runs

@@ -76,7 +76,7 @@ def lib():
         L.fpde_apply_parts.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.c_int64, vp]
         L.fpde_load_vector.argtypes = [vp, vp, vp, vp]
         L.fpde_solve.argtypes = [vp, vp, vp, C.c_int64, C.c_double, C.c_int32, C.POINTER(SolveInfo), vp]
-        L.fpde_apply_adjoint.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
+        L.fpde_apply_adjoint.argtypes = [vp, C.c_double, vp, vp, C.c_int64, vp, vp, vp]
         L.fpde_stats.argtypes = [vp, C.POINTER(Stats)]
         L.fpde_export.argtypes = [vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_int64)]
         L.fpde_profile.argtypes = [vp, C.c_int32, C.POINTER(Profile)]

@@ -458,4 +458,16 @@ hipError_t launch_adj_gather(int64_t n, const int64_t* ptr, const int64_t* idx, 
     return hipGetLastError();
 }
 
+// x[i] *= alpha (the scale of the adjoint's output)
+FPDE_KERNEL void k_scale(int64_t n, double alpha, double* x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] *= alpha;
+}
+
+hipError_t launch_scale(int64_t n, double alpha, double* x, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale, dim3(grid1(n)), dim3(256), 0, st, n, alpha, x);
+    return hipGetLastError();
+}
+
 }  // namespace fpde

@@ -1281,11 +1281,13 @@ void ensure_adj_ws(fpde_op& op, int64_t R) {
     J.ws_R = R;
 }
 
-// gs, gk [F][M] = d/ds_j, d/dkappa_j of sum_r w_r^T A_h u_r
-void adjoint_impl(fpde_op& op, const double* w, const double* u, int64_t R, double* gs, double* gk, hipStream_t st) {
+// gs, gk [F][M] = alpha d/ds_j, alpha d/dkappa_j of sum_r w_r^T A_h u_r
+void adjoint_impl(fpde_op& op, double alpha, const double* w, const double* u, int64_t R, double* gs, double* gk,
+                  hipStream_t st) {
     if (op.plan_only) fail(FPDE_ESTATE, "operator was built with FPDE_FLAG_PLAN_ONLY");
     if (!op.adj.ok) fail(FPDE_ESTATE, "adjoint unavailable: " + op.adj.why);
     if (!w || !u || !gs || !gk || R < 1) fail(FPDE_EINVAL, "bad vectors");
+    if (!std::isfinite(alpha)) fail(FPDE_EINVAL, "alpha must be finite");
     ensure_ws(op, R);
     ensure_adj_ws(op, R);
     auto& J = op.adj;
@@ -1367,6 +1369,10 @@ void adjoint_impl(fpde_op& op, const double* w, const double* u, int64_t R, doub
     hipck(launch_adj_far(hr, 1.0, as, J.chat, rf, J.mom, rf, 1, F, J.rGs, J.rGk, st), "adjoint far density");
     hipck(launch_adj_gather(M, J.rst_ptr, J.rst_idx, J.rst_w, J.rGs, rf, F, gs, M, st), "gather");
     hipck(launch_adj_gather(M, J.rst_ptr, J.rst_idx, J.rst_w, J.rGk, rf, F, gk, M, st), "gather");
+    if (alpha != 1.0) {
+        hipck(launch_scale((int64_t)F * M, alpha, gs, st), "scale");
+        hipck(launch_scale((int64_t)F * M, alpha, gk, st), "scale");
+    }
 }
 
 // ------------------------------------------------------------------ CG solve and iterative refinement
@@ -1660,11 +1666,11 @@ fpde_status fpde_solve(fpde_op* op, const double* Fv, double* u, int64_t nrhs, d
     });
 }
 
-fpde_status fpde_apply_adjoint(fpde_op* op, const double* w, const double* u, int64_t nrhs, double* grad_s,
-                               double* grad_kappa, void* hip_stream) {
+fpde_status fpde_apply_adjoint(fpde_op* op, double alpha, const double* w, const double* u, int64_t nrhs,
+                               double* grad_s, double* grad_kappa, void* hip_stream) {
     return guarded([&] {
         if (!op) fail(FPDE_EINVAL, "op is NULL");
-        adjoint_impl(*op, w, u, nrhs, grad_s, grad_kappa, (hipStream_t)hip_stream);
+        adjoint_impl(*op, alpha, w, u, nrhs, grad_s, grad_kappa, (hipStream_t)hip_stream);
     });
 }
 

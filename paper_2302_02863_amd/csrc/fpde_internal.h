@@ -118,6 +118,7 @@ hipError_t launch_load_nv(int64_t N, int nv, const int64_t* nc_ptr, const int64_
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* z,
                         hipStream_t st);
 hipError_t launch_fill(int64_t n, double v, double* x, hipStream_t st);
+hipError_t launch_scale(int64_t n, double alpha, double* x, hipStream_t st);
 
 // ---------------------------------------------------------------- apply kernels
 

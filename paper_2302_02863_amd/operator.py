@@ -123,8 +123,8 @@ class Operator:
             check(st, "fpde_solve")
         return u, out
 
-    def apply_adjoint(self, w, u, stream=None):
-        """(grad_s, grad_kappa) [F, n_nodes] of sum_r w_r^T A(s, kappa) u_r for device float64 [F, N, R]."""
+    def apply_adjoint(self, w, u, alpha: float = 1.0, stream=None):
+        """alpha (grad_s, grad_kappa) [F, n_nodes] of sum_r w_r^T A(s, kappa) u_r for device float64 [F, N, R]."""
         import torch
         if w.dim() == 2:
             w = w.unsqueeze(-1)
@@ -139,7 +139,8 @@ class Operator:
         u = u.contiguous()
         gs = torch.empty((self.n_fields, self.n_nodes), dtype=torch.float64, device=w.device)
         gk = torch.empty_like(gs)
-        check(lib().fpde_apply_adjoint(self._h, C.c_void_p(w.data_ptr()), C.c_void_p(u.data_ptr()), w.shape[2],
+        check(lib().fpde_apply_adjoint(self._h, float(alpha), C.c_void_p(w.data_ptr()), C.c_void_p(u.data_ptr()),
+                                       w.shape[2],
                                        C.c_void_p(gs.data_ptr()), C.c_void_p(gk.data_ptr()), _stream_handle(stream)),
               "fpde_apply_adjoint")
         return gs, gk

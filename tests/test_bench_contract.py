@@ -1,6 +1,7 @@
 """CPU checks of bench.py's command-line contract (no GPU needed): more than one GPU
 is refused with a JSON message and a non-zero exit; the algorithmic byte count of the
-dominant kernel follows its stated formula."""
+one-vector near kernel and the algorithmic MFMA flop count of the several-right-hand-side
+near kernel (the headline's dominant kernel) follow their stated formulas."""
 import json
 import os
 import subprocess
@@ -36,3 +37,23 @@ def test_algorithmic_bytes_formula():
     assert near == 3 * 3 + 3 * 2 + 2 * 2
     expect = near * 8 + 13 * (8 + 4) + 6 * 8 + 2 * 5 * 8 + 5 * 4 * 8 + 3 * 2 * 2 * 2 * 8 + 3 * 4 * 8
     assert b == expect
+
+
+def test_algorithmic_flops_formula():
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+
+    class FakeOp:   # leaves of 3 and 2 points, near pairs (0,0), (0,1), (1,0), (1,1)
+        def export(self, what):
+            if what == "K_LEAFPTR":
+                return np.array([0, 3, 5])
+            if what == "K_NEAR":
+                return np.array([1, 1, 1, 2, 2, 1, 2, 2])
+            raise KeyError(what)
+
+    st = {"k_levels": 2, "n_dofs": 5, "k_rank": 4}
+    F, R = 3, 7
+    fl, ne = bench.algorithmic_flops_near_mm(FakeOp(), st, F, R)
+    assert ne == 9 + 6 + 6 + 4
+    assert fl == 2.0 * ne * F * R + 2.0 * 5 * 4 * F * R

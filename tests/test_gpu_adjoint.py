@@ -114,3 +114,62 @@ def test_autograd_solve_gradient():
             got = float(g @ d)
             print(f"[autograd] {which} trial {trial}: {got:.15e} vs {ref:.15e}", flush=True)
             assert abs(got - ref) <= 1e-8 * float(np.abs(g * d).sum()), (which, got, ref)
+
+
+def test_full_gradient_two_fields_against_golden():
+    """Every entry of the gradient over all 113 nodes of a disk with an analytic exterior,
+    K~ far blocks and density far blocks, for two (s, kappa) fields and two right-hand sides,
+    against the oracle's complex-step gradient stored by tests/golden/make_adjoint_disk8.py.
+    alpha = -1 returns the exact negation."""
+    import os
+    import paper_2302_02863_amd as fp
+    P = configs.adjoint_disk(8)
+    m = P.mesh
+    ref = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "adjoint_disk8_F2.txt"))
+    rs = np.zeros((2, m.n_nodes))
+    rk = np.zeros((2, m.n_nodes))
+    rs[ref[:, 0].astype(int), ref[:, 1].astype(int)] = ref[:, 2]
+    rk[ref[:, 0].astype(int), ref[:, 1].astype(int)] = ref[:, 3]
+    assert ref.shape[0] == 2 * m.n_nodes
+    op = fp.Operator(m, P.s, P.kappa, P.opts)
+    st = op.stats()
+    print(f"[adjoint] disk8 F=2: N={m.n_dofs} M={m.n_nodes} k_far={st['k_far']} rho_far={st['rho_far']}",
+          flush=True)
+    assert st["k_far"] > 0 and st["rho_far"] > 0
+    w = torch.tensor(P.extra["w"], device="cuda")
+    u = torch.tensor(P.x, device="cuda")
+    gs, gk = op.apply_adjoint(w, u)
+    ns, nk = op.apply_adjoint(w, u, alpha=-1.0)
+    torch.cuda.synchronize()
+    gs, gk, ns, nk = (t.cpu().numpy() for t in (gs, gk, ns, nk))
+    assert np.array_equal(ns, -gs) and np.array_equal(nk, -gk)
+    for f in range(2):
+        es = np.abs(gs[f] - rs[f]).max() / np.abs(rs[f]).max()
+        ek = np.abs(gk[f] - rk[f]).max() / np.abs(rk[f]).max()
+        print(f"[adjoint] field {f}: max node error / max |g|: s {es:.2e}, kappa {ek:.2e}", flush=True)
+        assert es <= TOL and ek <= TOL, (f, es, ek)
+    op.close()
+
+
+def test_fracsolve_shapes_and_repeated_backward():
+    """FracSolve returns u in F's shape (here [F, N]) and keeps its operator alive for a
+    second backward through a retained graph, which gives the same gradient bit for bit."""
+    from paper_2302_02863_amd.autograd import frac_solve
+    from oracle.assembly import load_vector
+    P = configs.square(6, 3, leaf_size=8, leaf_size_rho=16, cheb_p=3)
+    m = P.mesh
+    F = torch.tensor(load_vector(m, P.f, P.opts), device="cuda").reshape(1, -1)
+    s = torch.tensor(P.s, requires_grad=True)
+    k = torch.tensor(P.kappa, requires_grad=True)
+    Fr = F.clone().requires_grad_(True)
+    u = frac_solve(s, k, Fr, m, P.opts, 1e-13)
+    assert u.shape == Fr.shape
+    J = (u ** 2).sum()
+    J.backward(retain_graph=True)
+    g1 = (s.grad.clone(), k.grad.clone(), Fr.grad.clone())
+    assert g1[2].shape == Fr.shape
+    s.grad = k.grad = Fr.grad = None
+    J.backward()
+    torch.cuda.synchronize()
+    for a, b in zip(g1, (s.grad, k.grad, Fr.grad)):
+        assert torch.equal(a, b)

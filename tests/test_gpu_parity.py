@@ -158,8 +158,8 @@ def test_many_rhs_fields_and_float32():
 
 
 def test_wide_rhs_fallback_and_profiled_path():
-    """Many right-hand sides take the per-level sweep path; profiling runs the fused launches
-    without the graph.  Both must equal the graph path / oracle."""
+    """Many right-hand sides take the per-level sweep path; a profiled apply (events between
+    the launches) must equal the plain apply bit for bit, and both the oracle."""
     import paper_2302_02863_amd as fp
     P, ref, op = _case("square")
     A = ref["B"] + ref["K"] + ref["M"]
@@ -169,12 +169,12 @@ def test_wide_rhs_fallback_and_profiled_path():
         y = _apply(op, x, fp.PART_ALL)[0]
         yr = A @ x[0]
         assert np.linalg.norm(y - yr) / np.linalg.norm(yr) < TOL, R
-    y_graph = _apply(op, P.x, fp.PART_ALL)
+    y_plain = _apply(op, P.x, fp.PART_ALL)
     op.profile(True)
     y_prof = _apply(op, P.x, fp.PART_ALL)
     pr = op.profile(False)
     assert pr["n_applies"] == 1 and pr["ms_out"] > 0
-    assert np.array_equal(y_graph, y_prof)
+    assert np.array_equal(y_plain, y_prof)
 
 
 MIXED_TOL = 1e-6   # per matvec, relative 2-norm against the FP64 oracle
@@ -200,7 +200,7 @@ def test_mixed_precision_apply(name):
     print(f"[parity] {name}: mixed apply rel err {err:.2e}")
     y64 = _apply(op, P.x, fp.PART_ALL | fp.PART_FP64)
     assert np.array_equal(y64, _apply(op64, P.x, fp.PART_ALL))
-    # mixed graph and profiled launches agree bit for bit
+    # plain and profiled mixed applies agree bit for bit
     yg = _apply(op, P.x, fp.PART_ALL)
     op.profile(True)
     yp = _apply(op, P.x, fp.PART_ALL)
