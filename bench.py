@@ -241,7 +241,9 @@ def solve_pair(op64, opm, Fv, rtol, maxit=50000, ref_rtol=None):
     res = {}
     uref = None
     if ref_rtol is not None:
-        uref, _ = op64.solve(Fv, rtol=ref_rtol, maxit=maxit)
+        uref, rinfo = op64.solve(Fv, rtol=ref_rtol, maxit=maxit, raise_on_noconv=False)
+        res["reference"] = {"rtol": ref_rtol, "rel_residual": rinfo["rel_residual"],
+                            "iterations": rinfo["iterations"]}
     for name, op in (("fp64", op64), ("mixed", opm)):
         op.solve(Fv, rtol=rtol, maxit=maxit)        # warm-up (workspaces allocated on first use)
         torch.cuda.synchronize()
@@ -272,8 +274,8 @@ def time_adjoint(op, w, u, n=3):
 
 def disk_solve():
     """The disk workload (elliptical 512 x 512 grid, 261121 dofs, tanh order profile,
-    exterior beyond R = 1.1): time to a solution within 1e-8 of the reference (FP64 CG
-    to 1e-13), FP64 CG against mixed CG with refinement, both stopped at rtol 1e-10."""
+    exterior beyond R = 1.1): FP64 CG against mixed CG with refinement, both stopped at
+    rtol 1e-10, and their solution errors against a reference FP64 solve to rtol 1e-12."""
     import torch
     import paper_2302_02863_amd as fp
     from fpde_inputs import configs
@@ -294,7 +296,7 @@ def disk_solve():
     out = {"workload": "disk-512 (261121 dofs), tanh order profile, exterior beyond R=1.1, f=1",
            "build_s": build_s, "apply_ms": {"fp64": el / 50 * 1e3, "mixed": el_m / 50 * 1e3},
            "apply_mixed_rel_err_vs_fp64": per_vector_rel_err(ym, y),
-           "solve": solve_pair(op, opm, Fv, rtol=1e-10, ref_rtol=1e-13)}
+           "solve": solve_pair(op, opm, Fv, rtol=1e-10, ref_rtol=1e-12)}
     opm.close()
     op.close()
     return out
@@ -497,6 +499,7 @@ def main():
         sys.exit(1)
 
     P, x, ops, hl = headline(args.steps, args.warmup)
+    print("[bench] headline done", file=sys.stderr, flush=True)
     F, N, R = P.x.shape
     mixed = hl["mixed"]
     kn = mixed["near_kernel"]
@@ -527,19 +530,28 @@ def main():
         "headline": hl,
     }
     extras = {}
+
+    def extra(name, fn, *a):
+        # an extra that fails is reported, not fatal: the headline line still prints
+        try:
+            extras[name] = fn(*a)
+        except Exception as exc:      # noqa: BLE001
+            extras[name] = {"error": f"{type(exc).__name__}: {exc}"}
+        print(f"[bench] {name} done", file=sys.stderr, flush=True)
+
     if not args.no_extras and not args.no_solve:
-        extras["batched_solve_adjoint"] = batched_solve_and_adjoint(P, x, ops)
+        extra("batched_solve_adjoint", batched_solve_and_adjoint, P, x, ops)
     for op in ops.values():
         op.close()
     del ops, x
     if not args.no_extras:
-        extras["measured_denominators"] = measured_denominators()
+        extra("measured_denominators", measured_denominators)
         if not args.no_square:
-            extras["square128"] = square128(max(100, args.steps), 20)
+            extra("square128", square128, max(100, args.steps), 20)
         if not args.no_disk:
-            extras["disk512"] = disk_solve()
+            extra("disk512", disk_solve)
         if not args.no_scaling:
-            extras["scaling_in_n"] = scaling(50, 5)
+            extra("scaling_in_n", scaling, 50, 5)
     res["extras"] = extras
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(P)
