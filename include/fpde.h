@@ -161,6 +161,24 @@ fpde_status fpde_apply(fpde_op *op, int32_t dtype, const void *x, void *y, int64
 fpde_status fpde_apply_parts(fpde_op *op, int32_t parts, int32_t dtype, const void *x, void *y,
                              int64_t nrhs, void *hip_stream);
 
+/* fpde_apply without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same y = A x with one right-hand side per field (nrhs must
+ * be 1) on the one-vector path (an operator with far blocks and panel rows
+ * within 64 KiB), with the apply's workspace (cluster coefficients, coupling partial
+ * sums and tickets, about (2 k + 2) F n_clusters + F k n_chunks words) taken
+ * from a static device scratch of 8 MiB that the library holds on every GPU
+ * it runs on until the process ends, instead of the operator's workspace.
+ * Calls no hipMalloc, hipFree or allocating library routine.  Every call on
+ * one GPU shares that GPU's scratch (cleared at the start of each call by a
+ * fill kernel), so calls that overlap on one GPU, from any operators, race.
+ *   dtype, x, y, hip_stream as fpde_apply; asynchronous on hip_stream.
+ * Errors: FPDE_EINVAL (nrhs != 1, dtype, NULL vectors, an operator without the
+ * one-vector path, or a workspace above the scratch size, reported with the
+ * bytes needed), FPDE_ESTATE (plan-only), FPDE_EDEVICE. */
+fpde_status fpde_apply_noalloc(fpde_op *op, int32_t dtype, const void *x, void *y, int64_t nrhs,
+                               void *hip_stream);
+
 /* Load vector of the weak form's right-hand side, F_i = int_{Omega_i} f psi_i
  * (Sec. 2.3: A(U, V) = int_{Omega_i} f V for the P1 test functions psi_i),
  * by the per-element rule of Sec. 5.2 with f P1-interpolated from its nodal

@@ -74,6 +74,7 @@ def lib():
                                  C.POINTER(Opts), C.POINTER(vp)]
         L.fpde_apply.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, vp]
         L.fpde_apply_parts.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.c_int64, vp]
+        L.fpde_apply_noalloc.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, vp]
         L.fpde_load_vector.argtypes = [vp, vp, vp, vp]
         L.fpde_solve.argtypes = [vp, vp, vp, C.c_int64, C.c_double, C.c_int32, C.POINTER(SolveInfo), vp]
         L.fpde_apply_adjoint.argtypes = [vp, C.c_double, vp, vp, C.c_int64, vp, vp, vp]
@@ -84,6 +85,7 @@ def lib():
         L.fpde_destroy.restype = None
         L.fpde_last_error.restype = C.c_char_p
         for n in ("fpde_opts_default", "fpde_gauss_legendre", "fpde_build", "fpde_apply", "fpde_apply_parts",
+                  "fpde_apply_noalloc",
                   "fpde_load_vector", "fpde_solve", "fpde_apply_adjoint", "fpde_stats", "fpde_export",
                   "fpde_profile"):
             getattr(L, n).restype = C.c_int32

@@ -33,6 +33,7 @@ SOURCES = [
     ("fpde_batched.hip", HIP_FLAGS),
     ("fpde_solve.hip", HIP_FLAGS),
     ("fpde_adjoint.hip", HIP_FLAGS),
+    ("fpde_noalloc.hip", HIP_FLAGS),
     ("fpde_host.cpp", HOST_FLAGS),
     ("fpde_plan.cpp", HOST_FLAGS),
 ]

@@ -1238,6 +1238,62 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
                              op.d_yh, y, s0, s1, fk, jn, ev);
 }
 
+// The one-vector apply with its workspace carved from the library's static device
+// scratch instead of the operator's allocations: no hipMalloc, hipFree or allocating
+// library call.  Layout (each part 256-byte aligned): x^ [F][ncl][k], then z^ [F][ncl][k],
+// the upsweep tickets and the coupling tickets [F][ncl] (cleared together, since the
+// kernels need them zero and the scratch keeps the last call's contents), then the
+// coupling partial sums [F][nchunks][k].
+void apply_noalloc_impl(fpde_op& op, int dtype, const void* x, void* y, int64_t R, hipStream_t st) {
+    if (op.plan_only) fail(FPDE_ESTATE, "operator was built with FPDE_FLAG_PLAN_ONLY");
+    if (dtype != FPDE_F64 && dtype != FPDE_F32) fail(FPDE_EINVAL, "dtype must be FPDE_F64 or FPDE_F32");
+    if (!x || !y) fail(FPDE_EINVAL, "bad vectors");
+    if (R != 1) fail(FPDE_EINVAL, "the allocation-free apply takes one right-hand side per field (nrhs = 1)");
+    const int pr = op.mixed ? 1 : 0;
+    if (!single_path(op, pr, 1) || op.far_plan.ntgt <= 0)
+        fail(FPDE_EINVAL, "the allocation-free apply needs the one-vector path (an operator with far blocks and "
+                          "panel rows within 64 KiB)");
+    const int F = op.F, p = op.opts.cheb_p, k = op.mesh.dim == 2 ? p * p : p;
+    const size_t esz = pr ? sizeof(float) : sizeof(double);
+    const int64_t ncl = op.kt.ncl, nch = std::max<int64_t>(1, op.far_plan.nchunks);
+    auto up256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t b_coef = up256((size_t)F * ncl * k * esz), b_tk = up256((size_t)F * ncl * sizeof(unsigned int));
+    const size_t o_xh = 0, o_zh = b_coef, o_tk = o_zh + b_coef, o_ctk = o_tk + b_tk, o_zp = o_ctk + b_tk;
+    const size_t need = o_zp + up256((size_t)F * nch * k * esz);
+    if (need > kScratchBytes)
+        fail(FPDE_EINVAL, "the allocation-free apply needs " + std::to_string(need) + " bytes of workspace; the static "
+                          "scratch holds " + std::to_string(kScratchBytes));
+    void* base = nullptr;
+    hipck(scratch_address(&base), "scratch address");
+    unsigned char* sb = (unsigned char*)base;
+    hipck(launch_zero_words((int64_t)((o_zp - o_zh) / 4), (uint32_t*)(sb + o_zh), st), "clear scratch");
+    const H2Tree h = make_h2(op.kt, op.kdev, p);
+    const ApplyPlan a = make_apply_plan(op, h);
+    PanelPlan pp{op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr, op.panel_max_stride, op.d_csr_col_dof};
+    pp.pcols_pad = op.d_pcols_pad;
+    pp.perm_pad = op.d_perm_pad;
+    pp.ell_col = op.d_ell_col;
+    pp.ell_val = op.d_ell_val;
+    pp.ell_w = op.ell_w;
+    FarPlan fp = op.far_plan;
+    fp.ctk = (unsigned int*)(sb + o_ctk);
+    H2Tree h1 = h;   // the far list with sources moved down
+    h1.far_ptr = op.d_far1_ptr;
+    h1.far_src = op.d_far1_src;
+    unsigned int* tk = (unsigned int*)(sb + o_tk);
+    if (pr) {
+        OpData<float> od{op.f32.U, op.f32.E, op.f32.St1, op.f32.panel, (float*)(sb + o_xh), (float*)(sb + o_zh),
+                         (float*)(sb + o_zp), op.f32.Upad};
+        hipck(launch_apply_single(a, h1, pp, op.up[1], fp, FPDE_PART_ALL, F, op.d_BM, od, dtype, x, y, tk, st,
+                                  nullptr), "apply");
+    } else {
+        OpData<double> od{op.d_U, op.kdev.E, op.d_St1, op.d_panel, (double*)(sb + o_xh), (double*)(sb + o_zh),
+                          (double*)(sb + o_zp), op.d_Upad};
+        hipck(launch_apply_single(a, h1, pp, op.up[0], fp, FPDE_PART_ALL, F, op.d_BM, od, dtype, x, y, tk, st,
+                                  nullptr), "apply");
+    }
+}
+
 void apply_impl(fpde_op& op, int parts, int dtype, const void* x, void* y, int64_t R, hipStream_t st) {
     if (op.plan_only) fail(FPDE_ESTATE, "operator was built with FPDE_FLAG_PLAN_ONLY");
     if (dtype != FPDE_F64 && dtype != FPDE_F32) fail(FPDE_EINVAL, "dtype must be FPDE_F64 or FPDE_F32");
@@ -1630,9 +1686,19 @@ fpde_status fpde_build(const fpde_mesh* mesh, int32_t n_fields, const double* s,
             hipck(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming), "event");
             hipck(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming), "event");
             build_device(*op);
+            // set-up of the allocation-free apply: this device's scratch address, once per device
+            void* scratch = nullptr;
+            hipck(scratch_address(&scratch), "scratch address");
         }
         fill_stats(*op);
         *out = op.release();
+    });
+}
+
+fpde_status fpde_apply_noalloc(fpde_op* op, int32_t dtype, const void* x, void* y, int64_t nrhs, void* hip_stream) {
+    return guarded([&] {
+        if (!op) fail(FPDE_EINVAL, "op is NULL");
+        apply_noalloc_impl(*op, dtype, x, y, nrhs, (hipStream_t)hip_stream);
     });
 }
 

@@ -379,4 +379,14 @@ hipError_t launch_cg_sum2(const CgDims& d, const double* part1, const double* pa
                           hipStream_t st);
 hipError_t launch_vec_add(int64_t n, const double* d, double* u, hipStream_t st);
 
+// ---------------------------------------------------------------- static scratch (fpde_noalloc.hip)
+
+// Size of the file-scope device scratch of the allocation-free apply: every GPU the
+// library runs on holds one copy until the process ends.
+constexpr size_t kScratchBytes = size_t(8) << 20;
+// Device address of the current device's copy (hipGetSymbolAddress on the first call per device).
+hipError_t scratch_address(void** out);
+// p[0, n) = 0 for n 32-bit words
+hipError_t launch_zero_words(int64_t n, uint32_t* p, hipStream_t st);
+
 }  // namespace fpde

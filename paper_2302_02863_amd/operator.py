@@ -94,6 +94,24 @@ class Operator:
             check(st, "fpde_apply")
         return y
 
+    def apply_noalloc(self, x, y, stream=None):
+        """fpde_apply_noalloc: y = A x for caller-allocated device tensors x, y [F, N, 1] (float64 or
+        float32) with the library's static scratch as workspace (no device allocation)."""
+        import torch
+        if x.dim() != 3 or tuple(x.shape) != (self.n_fields, self.n_dofs, 1) or not x.is_cuda:
+            raise ValueError(f"x must be a device tensor [F={self.n_fields}, N={self.n_dofs}, 1]")
+        if not (x.is_contiguous() and y.is_contiguous()) or y.shape != x.shape or y.dtype != x.dtype:
+            raise ValueError("x and y must be contiguous tensors of the same shape and dtype")
+        if x.dtype is torch.float64:
+            dtype = _abi.F64
+        elif x.dtype is torch.float32:
+            dtype = _abi.F32
+        else:
+            raise ValueError("x must be float64 or float32")
+        check(lib().fpde_apply_noalloc(self._h, dtype, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), 1,
+                                       _stream_handle(stream)), "fpde_apply_noalloc")
+        return y
+
     def load_vector(self, f_nodal, stream=None):
         import torch
         f = f_nodal.contiguous()
