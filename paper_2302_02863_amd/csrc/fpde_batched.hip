@@ -197,9 +197,10 @@ __device__ __forceinline__ void bcoupling_body(const H2Tree& t, int F, int R, co
     __shared__ T sX[KP * XS];    // [beta][r]
     const int K = t.k;
     const int64_t nrc = (R + kRC - 1) / kRC;
-    const int64_t S = blockIdx.x / nrc;
-    const int r0 = (int)(blockIdx.x % nrc) * kRC;
-    const int f = blockIdx.y;
+    const int64_t lb = xcd_block((int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
+    const int f = (int)(lb / gridDim.x);
+    const int64_t S = (lb % gridDim.x) / nrc;
+    const int r0 = (int)((lb % gridDim.x) % nrc) * kRC;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t nfar = t.far_ptr[t.ncl];
     bf32x16 c32 = {0};

@@ -41,6 +41,17 @@ __device__ __forceinline__ T get(const T* p) {
     return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Workgroups of a launch go to the 8 XCDs round-robin by linear id (x fastest).
+// xcd_block maps that id to a logical block so that XCD j runs the j-th
+// contiguous eighth of the logical range: blocks that run at the same time on
+// one XCD then work on neighbouring clusters and share their gathered rows in
+// that XCD's L2.  Identity when the grid is not a multiple of 8.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t hw, int64_t total) {
+    if (total % kXcds) return hw;
+    return (hw % kXcds) * (total / kXcds) + hw / kXcds;
+}
+
 // sum over the 64 lanes of a wavefront
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

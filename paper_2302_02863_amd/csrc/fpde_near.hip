@@ -187,10 +187,12 @@ __global__ __launch_bounds__(256, 3) void k_near_mm(ApplyPlan a, PanelPlan pp, c
     T* Bx = Ap + kMT * SA;                  // [kKC][SB]
     T* Cs = (T*)sraw;                       // [kMT][kCS] after the GEMM
     int32_t* pcs = (int32_t*)(sraw + sizeof(T) * mm_tile_elems<T>());   // staged panel column dofs
-    const int f = blockIdx.y;
     const int64_t nrt = (a.cap + kMT - 1) / kMT, nct = (R + kNT - 1) / kNT;
-    const int64_t li = blockIdx.x / (nrt * nct);
-    const int64_t rem = blockIdx.x % (nrt * nct);
+    const int64_t lb = xcd_block((int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
+    const int f = (int)(lb / gridDim.x);
+    const int64_t bx = lb % gridDim.x;
+    const int64_t li = bx / (nrt * nct);
+    const int64_t rem = bx % (nrt * nct);
     const int64_t row0 = (rem / nct) * kMT;   // first panel row of the tile
     const int r0 = (int)(rem % nct) * kNT;    // first right-hand side
     const int tid = threadIdx.x, lane = tid & 63;
