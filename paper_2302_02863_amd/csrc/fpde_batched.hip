@@ -193,8 +193,10 @@ __global__ __launch_bounds__(256) void k_blevel(H2Tree t, int64_t c0, int F, int
 template <typename T>
 __device__ __forceinline__ void bcoupling_body(const H2Tree& t, int F, int R, const T* St, const T* xh, T* yh) {
     constexpr int KP = 32, SS = KP + 1, XS = kRC + 1;
-    __shared__ T sS[KP * SS];    // [beta][alpha]
-    __shared__ T sX[KP * XS];    // [beta][r]
+    // far pairs staged per iteration (two measured slower: registers halve the occupancy)
+    constexpr int NP = 1;
+    __shared__ T sS[NP][KP * SS];    // [beta][alpha]
+    __shared__ T sX[NP][KP * XS];    // [beta][r]
     const int K = t.k;
     const int64_t nrc = (R + kRC - 1) / kRC;
     const int64_t lb = xcd_block((int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
@@ -207,55 +209,70 @@ __device__ __forceinline__ void bcoupling_body(const H2Tree& t, int F, int R, co
     bf64x4 c64[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
     // operands of a pair: S_e (thread -> alpha = tid % 32, beta = tid / 32 + 4m) and
     // X^ of its source (rhs = tid % 64, beta = tid / 64 + 2m), fetched into registers
-    // one pair ahead so that the loads overlap the MFMAs
+    // one stage ahead so that the loads overlap the MFMAs; a missing pair loads zeros
     constexpr int NS = KP * KP / 128, NX = KP * kRC / 128;
-    T rs[NS], rx[NX];
-    auto fetch = [&](int64_t e) {
-        const int64_t src = t.far_src[e];
-        const T* Se = St + ((int64_t)f * nfar + e) * K * K;
-        const T* Xe = xh + (((int64_t)f * t.ncl + src) * K) * R;
+    T rs[NP][NS], rx[NP][NX];
+    const int64_t e0 = t.far_ptr[S], e1 = t.far_ptr[S + 1];
+    auto fetch = [&](int64_t eb) {
 #pragma unroll
-        for (int m = 0; m < NS; ++m) {
-            const int be = (tid >> 5) + 4 * m, al = tid & 31;
-            rs[m] = (be < K && al < K) ? Se[be * K + al] : T(0);
-        }
+        for (int p = 0; p < NP; ++p) {
+            const int64_t e = eb + p;
+            const bool ok = e < e1;
+            const int64_t src = ok ? t.far_src[e] : 0;
+            const T* Se = St + ((int64_t)f * nfar + (ok ? e : 0)) * K * K;
+            const T* Xe = xh + (((int64_t)f * t.ncl + src) * K) * R;
 #pragma unroll
-        for (int m = 0; m < NX; ++m) {
-            const int be = (tid >> 6) + 2 * m, rr = tid & 63;
-            rx[m] = (be < K && r0 + rr < R) ? Xe[(int64_t)be * R + r0 + rr] : T(0);
+            for (int m = 0; m < NS; ++m) {
+                const int be = (tid >> 5) + 4 * m, al = tid & 31;
+                rs[p][m] = (ok && be < K && al < K) ? Se[be * K + al] : T(0);
+            }
+#pragma unroll
+            for (int m = 0; m < NX; ++m) {
+                const int be = (tid >> 6) + 2 * m, rr = tid & 63;
+                rx[p][m] = (ok && be < K && r0 + rr < R) ? Xe[(int64_t)be * R + r0 + rr] : T(0);
+            }
         }
     };
-    const int64_t e0 = t.far_ptr[S], e1 = t.far_ptr[S + 1];
     if (e0 < e1) fetch(e0);
-    for (int64_t e = e0; e < e1; ++e) {
+    for (int64_t e = e0; e < e1; e += NP) {
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < NS; ++m) sS[((tid >> 5) + 4 * m) * SS + (tid & 31)] = rs[m];
+        for (int p = 0; p < NP; ++p) {
 #pragma unroll
-        for (int m = 0; m < NX; ++m) sX[((tid >> 6) + 2 * m) * XS + (tid & 63)] = rx[m];
+            for (int m = 0; m < NS; ++m) sS[p][((tid >> 5) + 4 * m) * SS + (tid & 31)] = rs[p][m];
+#pragma unroll
+            for (int m = 0; m < NX; ++m) sX[p][((tid >> 6) + 2 * m) * XS + (tid & 63)] = rx[p][m];
+        }
         __syncthreads();
-        if (e + 1 < e1) fetch(e + 1);
-        if constexpr (sizeof(T) == 4) {
+        if (e + NP < e1) fetch(e + NP);
+        const int np = e1 - e < NP ? (int)(e1 - e) : NP;
 #pragma unroll
-            for (int k = 0; k < KP; k += 2) {
-                const float av = sS[(k + (lane >> 5)) * SS + (lane & 31)];
-                const float bv = sX[(k + (lane >> 5)) * XS + wv * 32 + (lane & 31)];
-                c32 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, c32, 0, 0, 0);
-            }
-        } else {
+        for (int p = 0; p < NP; ++p) {
+            if (p >= np) break;   // block-uniform
+            if constexpr (sizeof(T) == 4) {
 #pragma unroll
-            for (int k = 0; k < KP; k += 4) {
-                double av[2], bv[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    av[i] = sS[(k + (lane >> 4)) * SS + 16 * i + (lane & 15)];
-                    bv[i] = sX[(k + (lane >> 4)) * XS + wv * 32 + 16 * i + (lane & 15)];
+                for (int k = 0; k < KP; k += 2) {   // beta past K is zero padding: skipped
+                    if (k >= K) break;
+                    const float av = sS[p][(k + (lane >> 5)) * SS + (lane & 31)];
+                    const float bv = sX[p][(k + (lane >> 5)) * XS + wv * 32 + (lane & 31)];
+                    c32 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, c32, 0, 0, 0);
                 }
+            } else {
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int k = 0; k < KP; k += 4) {
+                    if (k >= K) break;
+                    double av[2], bv[2];
 #pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        c64[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c64[i][j], 0, 0, 0);
+                    for (int i = 0; i < 2; ++i) {
+                        av[i] = sS[p][(k + (lane >> 4)) * SS + 16 * i + (lane & 15)];
+                        bv[i] = sX[p][(k + (lane >> 4)) * XS + wv * 32 + 16 * i + (lane & 15)];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            c64[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c64[i][j], 0, 0, 0);
+                }
             }
         }
     }
