@@ -20,7 +20,8 @@ Prints one JSON line with a roofline entry for the dominant kernel
 (k_near_mm<float>, the near-panel GEMM on MFMA, timed with HIP events on the
 apply stream), a CPU baseline of the oracle, and extras: the one-vector
 square-128 apply, the disk solve (mixed CG with refinement against FP64 CG),
-the batched solve, adjoint timings and build/apply times for growing N.
+the batched solve, adjoint timings, the variable-order bump problem's
+self-convergence and build/apply times for growing N.
 """
 from __future__ import annotations
 
@@ -314,6 +315,48 @@ def batched_solve_and_adjoint(P, x, ops):
     return out
 
 
+def bump_self_convergence(levels=(3, 4, 5, 6, 7)):
+    """The paper's variable-order bump problem (Sec. 7.2): build and FP64 solve (rtol 1e-11)
+    on the uniform grids T_j, and the self-convergence e_j = U_{j+1} - I U_j in L2(Omega_i)
+    and at the nodes, with fitted rates."""
+    import numpy as np
+    import torch
+    import paper_2302_02863_amd as fp
+    from fpde_inputs import configs
+    from fpde_inputs.meshes import grid_values, prolong_p1
+    from oracle.solve import l2_norm
+    sols, rows = {}, []
+    for j in levels:
+        P = configs.bump(j)
+        t0 = time.perf_counter()
+        op = fp.Operator(P.mesh, P.s, P.kappa, P.opts)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        F = op.load_vector(torch.tensor(P.f, device="cuda:0")).reshape(1, -1, 1)
+        op.solve(F, rtol=1e-11, maxit=50000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, info = op.solve(F, rtol=1e-11, maxit=50000)
+        torch.cuda.synchronize()
+        solve_ms = (time.perf_counter() - t0) * 1e3
+        sols[j] = (P.mesh, u.cpu().numpy()[0, :, 0])
+        rows.append({"j": j, "n_dofs": P.mesh.n_dofs, "cells": P.mesh.n_cells, "build_s": build_s,
+                     "solve_ms": solve_ms, "cg_iterations": info["iterations"]})
+        op.close()
+    errs = []
+    for j in levels[:-1]:
+        (mc, uc), (mf, uf) = sols[j], sols[j + 1]
+        Gf = prolong_p1(grid_values(mc, uc)[0])
+        _, idx = grid_values(mf, uf)
+        d = uf - Gf[idx[0, :mf.n_dofs], idx[1, :mf.n_dofs]]
+        errs.append({"j": j, "h": mc.info["h"], "l2": l2_norm(mf, d), "linf": float(np.abs(d).max())})
+    hs = np.log([e["h"] for e in errs])
+    return {"workload": "variable-order bump, s* = 0.7, eta = 0.2, l = 1, x^c = (-0.4, 0.4), f = 20, "
+                        "Omega = (-2,2)^2, Omega_i = (-1,1)^2", "levels": rows, "self_convergence": errs,
+            "rate_l2": float(np.polyfit(hs, np.log([e["l2"] for e in errs]), 1)[0]),
+            "rate_linf": float(np.polyfit(hs, np.log([e["linf"] for e in errs]), 1)[0])}
+
+
 def scaling(steps, warmup, sizes=(32, 64, 128, 256)):
     """Build time and one-vector FP64 apply time of the square workload (same recipe:
     jitter, order and diffusivity fields) for growing n: linear scaling in N."""
@@ -550,6 +593,7 @@ def main():
             extra("square128", square128, max(100, args.steps), 20)
         if not args.no_disk:
             extra("disk512", disk_solve)
+        extra("bump", bump_self_convergence)
         if not args.no_scaling:
             extra("scaling_in_n", scaling, 50, 5)
     res["extras"] = extras

@@ -16,6 +16,11 @@ Named workloads (sizes follow the configurations the library is measured on):
   to R=1.1 and the exterior beyond R handled analytically.
 * ``batched``  2D square without jitter, kappa=1, F order fields
   s_k = 0.5+0.3 sin(k pi x1) cos(pi x2), R right-hand sides ~ N(0,1) (seed 3).
+* ``bump``  the variable-order test of the paper's Sec. 7.2: Omega = (-2,2)^2,
+  interior (-1,1)^2 on the uniform grid T_j (2^{j+1} squares a side inside,
+  split along one diagonal), s = s* + eta bump(x1 - c1; l) bump(x2 - c2; l)
+  with bump(x; l) = exp(-1/(1-r^2)), r = 2x/l, for |r| < 1 (else 0), s* = 0.7,
+  eta = 0.2, l = 1, c = (-0.4, 0.4), a = 1, f = 20.
 * ``adjoint_disk``  small disk with an analytic exterior and two fields (the
   disk's order with kappa = 1, and a perturbed order with kappa = 1 + 0.3 x1),
   two right-hand sides u ~ N(0,1) (seed 14) and weights w ~ N(0,1) (seed 15).
@@ -166,3 +171,27 @@ def adjoint_disk(n: int = 8, **kw) -> Problem:
     u = np.random.default_rng(14).standard_normal((2, P.mesh.n_dofs, 2))
     w = np.random.default_rng(15).standard_normal((2, P.mesh.n_dofs, 2))
     return Problem("adjoint_disk", P.mesh, s, kappa, P.opts, P.f, u, {"w": w})
+
+
+def bump_order(x1, x2, s_star=0.7, eta=0.2, ell=1.0, center=(-0.4, 0.4)):
+    """s* + eta bump(x1 - c1; l) bump(x2 - c2; l), bump(x; l) = exp(-1/(1-r^2)), r = 2x/l."""
+    def bump(x):
+        r = 2.0 * x / ell
+        out = np.zeros_like(r)
+        m = np.abs(r) < 1.0
+        out[m] = np.exp(-1.0 / (1.0 - r[m] ** 2))
+        return out
+    return s_star + eta * bump(x1 - center[0]) * bump(x2 - center[1])
+
+
+def bump(j: int = 6, eta: float = 0.2, s_star: float = 0.7, f: float = 20.0, **kw) -> Problem:
+    """The paper's variable-order bump problem on the uniform grid T_j of (-2,2)^2."""
+    n = 2 ** (j + 1)
+    m = square_mesh(n, n // 2, jitter=0.0, lo=-1.0, hi=1.0)
+    x1, x2 = m.coords
+    s = bump_order(x1, x2, s_star=s_star, eta=eta)[None, :]
+    kappa = np.ones_like(s)
+    rng = np.random.default_rng(16)
+    vec = rng.standard_normal((1, m.n_dofs, 1))
+    return Problem("bump", m, s, kappa, _opts(**kw), np.full(m.n_nodes, f), vec,
+                   {"j": j, "eta": eta, "s_star": s_star})

@@ -189,3 +189,30 @@ def disk_mesh(n: int, layers: int, radius_out: float, exterior_radius: float = 0
     cells[1, flip], cells[2, flip] = cells[2, flip].copy(), cells[1, flip].copy()
     return Mesh(2, coords, cells, interior, int(is_dof.sum()), float(exterior_radius),
                 {"h": 2.0 / n, "kind": "disk", "n": n, "layers": layers, "radius_out": radius_out})
+
+
+def grid_values(mesh: Mesh, u_dofs: np.ndarray):
+    """Nodal values of a P1 function on the full node grid of a ``square_mesh`` without
+    jitter: returns (G, idx) with G[i, k] the value at grid node (i, k) (zero off the dofs)
+    and idx (2, M) the grid index of every mesh node."""
+    h = mesh.info["h"]
+    lo = mesh.coords.min(axis=1)
+    full = np.zeros(mesh.n_nodes)
+    full[:mesh.n_dofs] = u_dofs
+    idx = np.rint((mesh.coords - lo[:, None]) / h).astype(np.int64)
+    G = np.zeros((idx[0].max() + 1, idx[1].max() + 1))
+    G[idx[0], idx[1]] = full
+    return G, idx
+
+
+def prolong_p1(Gc: np.ndarray) -> np.ndarray:
+    """P1 interpolation of grid values onto the grid of half the spacing.  The squares are
+    split along the diagonal (i, k)-(i+1, k+1), so a square's centre lies on that edge and
+    takes the mean of its two end nodes."""
+    n1, n2 = Gc.shape
+    Gf = np.zeros((2 * n1 - 1, 2 * n2 - 1))
+    Gf[0::2, 0::2] = Gc
+    Gf[1::2, 0::2] = 0.5 * (Gc[:-1, :] + Gc[1:, :])
+    Gf[0::2, 1::2] = 0.5 * (Gc[:, :-1] + Gc[:, 1:])
+    Gf[1::2, 1::2] = 0.5 * (Gc[:-1, :-1] + Gc[1:, 1:])
+    return Gf

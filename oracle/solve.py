@@ -6,6 +6,8 @@
 * ``conjugate_gradient``: textbook unpreconditioned CG (Hestenes-Stiefel) on
   a dense matrix, used to compare iteration counts and stopping behaviour
   (relative residual ||F - A u|| / ||F||).
+* ``l2_norm``: ||U_h||_{L2} over the interior cells of a P1 function (exact:
+  the per-cell rule integrates the square of a linear function exactly).
 * ``l2_error``: ||u - U_h||_{L2} / ||u||_{L2} over the interior cells (the
   norm of Sec. 7), for a P1 solution U_h (zero on the non-dof nodes) against a
   function u given pointwise, by a 7-point-per-direction rule on each cell
@@ -83,3 +85,19 @@ def l2_error(mesh, u_dofs: np.ndarray, u_exact, n: int = 7) -> float:
         err2 += det * float((wt * (uh - ue) ** 2).sum())
         nrm2 += det * float((wt * ue ** 2).sum())
     return float(np.sqrt(err2 / nrm2))
+
+
+def l2_norm(mesh, u_dofs: np.ndarray) -> float:
+    """||U_h||_{L2} over the interior cells for the P1 function with dof values u_dofs."""
+    full = np.zeros(mesh.n_nodes)
+    full[:mesh.n_dofs] = u_dofs
+    X = mesh.coords[:, mesh.cells]                     # (dim, dim+1, nc)
+    if mesh.dim == 1:
+        vol = np.abs(X[0, 1] - X[0, 0])
+    else:
+        vol = 0.5 * np.abs((X[0, 1] - X[0, 0]) * (X[1, 2] - X[1, 0]) - (X[1, 1] - X[1, 0]) * (X[0, 2] - X[0, 0]))
+    U = full[mesh.cells]                               # (dim+1, nc)
+    # integral of a linear function squared over a simplex: vol * (sum u_a^2 + (sum u_a)^2) / ((d+1)(d+2))
+    d = mesh.dim
+    q = vol * ((U ** 2).sum(axis=0) + U.sum(axis=0) ** 2) / ((d + 1) * (d + 2))
+    return float(np.sqrt((q * mesh.cell_interior).sum()))

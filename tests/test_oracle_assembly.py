@@ -171,3 +171,24 @@ def test_condition_number_grows_like_h_to_minus_2s(s):
         hs.append(2.0 / n)
     slope = np.polyfit(np.log(hs), np.log(ks), 1)[0]
     assert abs(slope + 2 * s) < 0.05, slope
+
+
+def test_l2_norm_of_p1_functions():
+    # the closed form per cell, integral of (sum u_a lambda_a)^2 = |tau| (sum u_a^2 + (sum u_a)^2) / ((d+1)(d+2)),
+    # against a quadrature exact for quadratics on every interior cell (1D and 2D)
+    from oracle.rules import barycentric_ref, element_rule
+    from oracle.solve import l2_norm
+    rng = np.random.default_rng(3)
+    for P in (configs.interval(n_int=16, n_ext=4), _small_square(4, 2, jitter=0.1)):
+        m = P.mesh
+        u = rng.standard_normal(m.n_dofs)
+        full = np.zeros(m.n_nodes)
+        full[:m.n_dofs] = u
+        xh, w = element_rule(m.dim, 4)
+        lam = barycentric_ref(m.dim, xh)
+        tot = 0.0
+        for c in np.flatnonzero(m.cell_interior):
+            X = m.coords[:, m.cells[:, c]]
+            J = X[:, 1:] - X[:, :1] if m.dim == 1 else np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 1]], axis=1)
+            tot += abs(np.linalg.det(J)) * float(w @ (full[m.cells[:, c]] @ lam) ** 2)
+        assert abs(l2_norm(m, u) - np.sqrt(tot)) < 1e-13 * np.sqrt(tot)
