@@ -56,6 +56,7 @@ enum { FPDE_F64 = 0, FPDE_F32 = 1 };
 
 /* flags */
 #define FPDE_FLAG_PLAN_ONLY 0x1ull   /* host planning only: no device work (for inspection) */
+#define FPDE_FLAG_JACOBI    0x2ull   /* fpde_solve preconditions CG with the diagonal of A_h */
 
 /* Simplicial mesh of Omega = closure(Omega_i) U Omega_e (Sec. 2.3).  Nodes
  * [0, n_dofs) are the nodes strictly inside Omega_i.  SoA layouts:
@@ -111,6 +112,10 @@ typedef struct {
     double  rel_residual;    /* max over systems of ||F - A u|| / ||F|| at exit   */
     int32_t converged;
     int32_t refinements;     /* iterative-refinement passes                       */
+    double  cond_estimate;   /* largest over systems of lambda_max / lambda_min of the
+                                Lanczos matrix of the first CG pass (its first 2048
+                                steps): a lower bound on the condition number of A_h,
+                                or of D^-1 A_h with FPDE_FLAG_JACOBI; 0 if fewer than 2 steps */
 } fpde_solve_info;
 
 typedef struct fpde_op fpde_op;
@@ -197,7 +202,8 @@ fpde_status fpde_load_vector(fpde_op *op, const double *f_nodal, double *F, void
  * The solve is an iterative-refinement loop on the FP64 residual: each pass
  * runs unpreconditioned CG on A d = r from d = 0 and adds d to u.  An FP64
  * operator's CG runs to 0.5 rtol in one pass (a second pass only corrects
- * drift of the recursive residual); an FPDE_PREC_MIXED operator's CG uses the
+ * drift of the recursive residual); with FPDE_FLAG_JACOBI each pass is CG
+ * preconditioned by the diagonal D of A_h (stopping still on ||r||); an FPDE_PREC_MIXED operator's CG uses the
  * mixed-precision apply and stops each pass at a relative reduction of
  * sqrt(rtol), clamped to [1e-7, 1e-2].  CG iterations are launched back to
  * back on hip_stream; the host polls convergence every few iterations.  Synchronises hip_stream.  info (host, may be NULL): total

@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "FPDE_OK", -1: "FPDE_EINVAL", -2: "FPDE_EDOMAIN", -3: "FPDE_E
 PREC_FP64, PREC_MIXED = 0, 1
 F64, F32 = 0, 1
 FLAG_PLAN_ONLY = 0x1
+FLAG_JACOBI = 0x2
 PART_B, PART_M, PART_KNEAR, PART_KFAR, PART_ALL, PART_FP64 = 0x1, 0x2, 0x4, 0x8, 0xF, 0x10
 
 EXPORT = dict(CSR_ROWPTR=1, CSR_COLS=2, CSR_B=3, CSR_M=4, K_PERM=5, K_LEAFPTR=6, K_FAR=7, K_NEAR=8,
@@ -55,7 +56,7 @@ class Profile(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double), ("converged", C.c_int32),
-                ("refinements", C.c_int32)]
+                ("refinements", C.c_int32), ("cond_estimate", C.c_double)]
 
 
 _lib = None

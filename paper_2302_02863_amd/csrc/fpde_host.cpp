@@ -187,6 +187,8 @@ struct fpde_op {
     double* d_part_far = nullptr;   // [F][output-kernel blocks] p . Ap partials of fused CG iterations (R = 1)
     CgScalars cg{};
     int* h_nact = nullptr;                    // pinned host copy of the active-system count
+    double* d_dinv = nullptr;                 // [F][N] 1 / diag(A_h) (FPDE_FLAG_JACOBI), dof order
+    double *d_hist_a = nullptr, *d_hist_b = nullptr;   // Lanczos coefficients of a CG pass [kHist][S]
     fpde_stats_t stats{};
     // profiling: events recorded per apply (gather begin, gather end, far end, out end)
     bool profiling = false;
@@ -842,9 +844,10 @@ void build_device(fpde_op& op) {
         op.d_leaf_beg = A.upload(leaf_beg, st);
         op.d_near_ptr = A.upload(near_ptr, st);
         op.d_near_src = A.upload(near_src_leaf, st);
+        std::vector<int64_t> pcols_ptr(nleaf + 1, 0), poff(nleaf + 1, 0), pstride(nleaf);
+        std::vector<int32_t> pcols;
         {   // panels: columns of each leaf = concatenated source leaves of its near pairs
-            std::vector<int64_t> pcol_off(np.npairs), poff(nleaf + 1, 0), pstride(nleaf), pcols_ptr(nleaf + 1, 0);
-            std::vector<int32_t> pcols;
+            std::vector<int64_t> pcol_off(np.npairs);
             for (int64_t li = 0; li < nleaf; ++li) {
                 int64_t ncol = 0;
                 for (int64_t e = near_ptr[li]; e < near_ptr[li + 1]; ++e) {
@@ -958,6 +961,29 @@ void build_device(fpde_op& op) {
                 hipck(hipStreamSynchronize(st), "ELL sync");
                 A.release(d_esrc);
             }
+        }
+        if (op.opts.flags & FPDE_FLAG_JACOBI) {
+            // 1 / diag(A_h): the diagonal entry of B + M plus the leaf self-block entry of the
+            // near panel (far blocks never hold a diagonal entry)
+            std::vector<int64_t> bm_idx(m.N, -1), p_idx(m.N, -1);
+            for (int64_t li = 0; li < nleaf; ++li)
+                for (int64_t t = leaf_beg[li]; t < leaf_beg[li + 1]; ++t) {
+                    const int64_t dof = kt.perm[t];
+                    for (int64_t e = op.csr_ptr[t]; e < op.csr_ptr[t + 1]; ++e)
+                        if (op.csr_col[e] == t) bm_idx[dof] = e;
+                    for (int64_t c = pcols_ptr[li]; c < pcols_ptr[li + 1]; ++c)
+                        if (pcols[c] == dof) p_idx[dof] = poff[li] + (t - leaf_beg[li]) * pstride[li] + (c - pcols_ptr[li]);
+                }
+            for (int64_t i = 0; i < m.N; ++i)
+                if (bm_idx[i] < 0 || p_idx[i] < 0) fail(FPDE_EINVAL, "Jacobi: no diagonal entry for a dof");
+            int64_t* d_bi = A.upload(bm_idx, st);
+            int64_t* d_pi = A.upload(p_idx, st);
+            op.d_dinv = A.alloc<double>((int64_t)F * m.N);
+            hipck(launch_jacobi_diag(m.N, F, nnz, d_bi, op.d_BM, op.panel_total, d_pi, op.d_panel, op.d_dinv, st),
+                  "Jacobi diagonal");
+            hipck(hipStreamSynchronize(st), "Jacobi sync");   // bm_idx, p_idx end here
+            A.release(d_bi);
+            A.release(d_pi);
         }
         // launch plans: the one-launch upsweep of the single-vector apply (per
         // precision) and the subtree-root level of the multi-RHS far chain.
@@ -1433,6 +1459,48 @@ void adjoint_impl(fpde_op& op, double alpha, const double* w, const double* u, i
 
 // ------------------------------------------------------------------ CG solve and iterative refinement
 
+// CG iterations whose Lanczos coefficients are kept for the condition estimate
+constexpr int kHist = 2048;
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix (diagonal d, off-diagonal
+// e, e[k] couples k and k + 1): the sign changes of the Sturm sequence (LDL^T pivots).
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (size_t k = 0; k < d.size(); ++k) {
+        const double off = k > 0 ? e[k - 1] * e[k - 1] : 0.0;
+        q = d[k] - x - (k > 0 ? off / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// Extreme eigenvalues of the Lanczos matrix of m CG steps, T_kk = 1/alpha_k + beta_{k-1}/alpha_{k-1},
+// T_{k,k+1} = sqrt(beta_k)/alpha_k, by bisection on the Sturm count in the Gershgorin interval:
+// estimates of the extreme eigenvalues of the (preconditioned) operator CG ran on.
+std::pair<double, double> lanczos_extremes(const double* al, const double* be, int m) {
+    std::vector<double> d(m), e(m > 0 ? m - 1 : 0);
+    for (int k = 0; k < m; ++k) d[k] = 1.0 / al[k] + (k > 0 ? be[k - 1] / al[k - 1] : 0.0);
+    for (int k = 0; k + 1 < m; ++k) e[k] = std::sqrt(be[k]) / al[k];
+    double lo = INFINITY, hi = -INFINITY;
+    for (int k = 0; k < m; ++k) {
+        const double rad = (k > 0 ? std::fabs(e[k - 1]) : 0.0) + (k + 1 < m ? std::fabs(e[k]) : 0.0);
+        lo = std::min(lo, d[k] - rad);
+        hi = std::max(hi, d[k] + rad);
+    }
+    auto kth = [&](int idx) {   // the idx-th smallest eigenvalue (0-based)
+        double a = lo, b = hi;
+        for (int it = 0; it < 200 && b - a > 1e-14 * std::max(std::fabs(a), std::fabs(b)); ++it) {
+            const double c = 0.5 * (a + b);
+            if (sturm_count(d, e, c) > idx) b = c;
+            else a = c;
+        }
+        return 0.5 * (a + b);
+    };
+    return {kth(0), kth(m - 1)};
+}
+
 void ensure_solve_ws(fpde_op& op, int64_t R) {
     if (op.sw_R >= R) return;
     Arena& A = op.arena;
@@ -1441,7 +1509,7 @@ void ensure_solve_ws(fpde_op& op, int64_t R) {
                     (void*)op.d_part_far,
                     (void*)op.cg.rr, (void*)op.cg.rr_next, (void*)op.cg.alpha, (void*)op.cg.beta, (void*)op.cg.tol2,
                     (void*)op.cg.active, (void*)op.cg.active_next, (void*)op.cg.iters, (void*)op.cg.flags,
-                    (void*)op.cg.n_active})
+                    (void*)op.cg.n_active, (void*)op.d_hist_a, (void*)op.d_hist_b})
         if (q) A.release(q);
     const int64_t n = (int64_t)op.F * op.mesh.N * R, S = (int64_t)op.F * R;
     const int64_t nb = cg_row_blocks(op.mesh.N, (int)R);
@@ -1453,6 +1521,8 @@ void ensure_solve_ws(fpde_op& op, int64_t R) {
     op.d_part1 = A.alloc<double>(op.F * nb * R);
     op.d_part2 = A.alloc<double>(op.F * nb * R);
     op.d_part3 = A.alloc<double>(op.F * nb * R);
+    op.d_hist_a = A.alloc<double>((int64_t)kHist * S);
+    op.d_hist_b = A.alloc<double>((int64_t)kHist * S);
     op.d_part_far = R == 1 ? A.alloc<double>(op.F * op.kt.nleaf() * ((op.cap + 63) / 64)) : nullptr;
     op.d_bb = A.alloc<double>(S);
     op.d_rro = A.alloc<double>(S);
@@ -1480,6 +1550,7 @@ bool cg_fusable(const fpde_op& op, bool mixed, int64_t R) {
 
 hipError_t enqueue_cg_iteration(fpde_op& op, bool mixed, int64_t R, hipStream_t s0, hipStream_t s1) {
     const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
+    double* pc3 = op.d_dinv ? op.d_part3 : nullptr;   // r . r partials of the preconditioned iteration
     const int parts = mixed ? FPDE_PART_ALL : (FPDE_PART_ALL | FPDE_PART_FP64);
     hipError_t e;
     if (cg_fusable(op, mixed, R)) {
@@ -1489,38 +1560,46 @@ hipError_t enqueue_cg_iteration(fpde_op& op, bool mixed, int64_t R, hipStream_t 
                                &cf)) != hipSuccess)
             return e;
         const int64_t nb_far = op.kt.nleaf() * ((op.cap + 63) / 64);   // blocks of the output kernel per field
-        if ((e = launch_cg_rowblock(CG_UPDATE_UR, dm, op.d_p, op.d_Ap, op.d_d, op.d_r, nullptr, op.d_part2, nullptr,
-                                    op.d_part_far, op.cg, s0, nb_far)) != hipSuccess)
+        if ((e = launch_cg_rowblock(CG_UPDATE_UR, dm, op.d_p, op.d_Ap, op.d_d, op.d_r, nullptr, op.d_part2, pc3,
+                                    op.d_part_far, op.cg, s0, nb_far, op.d_dinv)) != hipSuccess)
             return e;
         return launch_cg_rowblock(CG_UPDATE_P, dm, op.d_r, nullptr, nullptr, nullptr, op.d_p, nullptr, nullptr,
-                                  op.d_part2, op.cg, s0);
+                                  op.d_part2, op.cg, s0, -1, op.d_dinv, pc3);
     }
     e = enqueue_apply(op, parts, FPDE_F64, op.d_p, op.d_Ap, R, s0, s1, op.ev_fork, op.ev_join, nullptr);
     if (e != hipSuccess) return e;
     if ((e = launch_cg_rowblock(CG_DOT, dm, op.d_p, op.d_Ap, nullptr, nullptr, nullptr, op.d_part1, nullptr, nullptr,
                                 op.cg, s0)) != hipSuccess)
         return e;
-    if ((e = launch_cg_rowblock(CG_UPDATE_UR, dm, op.d_p, op.d_Ap, op.d_d, op.d_r, nullptr, op.d_part2, nullptr,
-                                op.d_part1, op.cg, s0)) != hipSuccess)
+    if ((e = launch_cg_rowblock(CG_UPDATE_UR, dm, op.d_p, op.d_Ap, op.d_d, op.d_r, nullptr, op.d_part2, pc3,
+                                op.d_part1, op.cg, s0, -1, op.d_dinv)) != hipSuccess)
         return e;
     return launch_cg_rowblock(CG_UPDATE_P, dm, op.d_r, nullptr, nullptr, nullptr, op.d_p, nullptr, nullptr, op.d_part2,
-                              op.cg, s0);
+                              op.cg, s0, -1, op.d_dinv, pc3);
 }
 
 // CG on A d = rout from d = 0 until |r_s| <= max(tau_in |rout_s|, rtol_abs_s) for every
 // system s (rtol_abs_s = rtol |b_s|, |b_s|^2 in d_bb).  Returns the largest
 // per-system iteration count; *breakdown is set if a system lost positivity.
 int cg_run(fpde_op& op, bool mixed, int64_t R, double tau_in, double rtol, int maxit, hipStream_t st,
-           bool* breakdown) {
+           bool* breakdown, double* cond) {
     const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
     const int64_t S = (int64_t)op.F * R;
-    hipck(launch_cg_rowblock(CG_COPY_RP, dm, nullptr, op.d_rout, op.d_d, op.d_r, op.d_p, op.d_part1, nullptr, nullptr,
-                             op.cg, st), "cg start");
-    hipck(launch_cg_start(dm, op.d_part1, op.d_bb, tau_in, rtol, op.cg, st), "cg start");
+    op.cg.hist_a = cond ? op.d_hist_a : nullptr;   // the Lanczos coefficients, when an estimate is asked
+    op.cg.hist_b = cond ? op.d_hist_b : nullptr;
+    op.cg.hist_cap = cond ? kHist : 0;
+    hipck(launch_cg_rowblock(CG_COPY_RP, dm, nullptr, op.d_rout, op.d_d, op.d_r, op.d_p, op.d_part1,
+                             op.d_dinv ? op.d_part3 : nullptr, nullptr, op.cg, st, -1, op.d_dinv), "cg start");
+    hipck(launch_cg_start(dm, op.d_part1, op.d_bb, tau_in, rtol, op.cg, st, op.d_dinv ? op.d_part3 : nullptr),
+          "cg start");
     hipck(hipMemcpyAsync(op.h_nact, op.cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
     hipck(hipStreamSynchronize(st), "sync");
     *breakdown = false;
-    if (*op.h_nact == 0) return 0;
+    if (*op.h_nact == 0) {
+        op.cg.hist_a = op.cg.hist_b = nullptr;
+        op.cg.hist_cap = 0;
+        return 0;
+    }
     int it = 0, chunk = 4;
     while (it < maxit) {
         const int n = std::min(chunk, maxit - it);
@@ -1535,7 +1614,26 @@ int cg_run(fpde_op& op, bool mixed, int64_t R, double tau_in, double rtol, int m
     hipck(hipMemcpy(iters.data(), op.cg.iters, sizeof(int) * S, hipMemcpyDeviceToHost), "copy");
     hipck(hipMemcpy(flags.data(), op.cg.flags, sizeof(int) * S, hipMemcpyDeviceToHost), "copy");
     for (int f : flags) if (f) *breakdown = true;
-    return *std::max_element(iters.begin(), iters.end());
+    const int itmax = *std::max_element(iters.begin(), iters.end());
+    if (cond && itmax > 1) {   // the largest estimate over the systems
+        const int m = std::min(itmax, kHist);
+        std::vector<double> ha((size_t)m * S), hb((size_t)m * S), a(m), b(m);
+        hipck(hipMemcpy(ha.data(), op.d_hist_a, sizeof(double) * m * S, hipMemcpyDeviceToHost), "copy");
+        hipck(hipMemcpy(hb.data(), op.d_hist_b, sizeof(double) * m * S, hipMemcpyDeviceToHost), "copy");
+        for (int64_t sy = 0; sy < S; ++sy) {
+            const int ms = std::min(iters[sy], kHist);
+            if (ms < 2) continue;
+            for (int k = 0; k < ms; ++k) {
+                a[k] = ha[(size_t)k * S + sy];
+                b[k] = hb[(size_t)k * S + sy];
+            }
+            const auto ex = lanczos_extremes(a.data(), b.data(), ms);
+            if (ex.first > 0.0) *cond = std::max(*cond, ex.second / ex.first);
+        }
+    }
+    op.cg.hist_a = op.cg.hist_b = nullptr;
+    op.cg.hist_cap = 0;
+    return itmax;
 }
 
 // rout = b - A_fp64 u, per-system |rout|^2 (d_rro) and |b|^2 (d_bb); returns max_s |rout_s| / |b_s|
@@ -1576,10 +1674,11 @@ void solve_impl(fpde_op& op, const double* b, double* u, int64_t R, double rtol,
     bool breakdown = false;
     double worst = outer_residual(op, b, u, R, st), best = worst;
     int stalls = 0;
+    double cond = 0.0;
     while (worst > rtol && total < maxit && outer < kMaxRefinements) {
         const double tau = op.mixed ? mixed_inner_tol(rtol) : 0.0;
         bool bd = false;
-        total += cg_run(op, op.mixed, R, tau, 0.5 * rtol, maxit - total, st, &bd);
+        total += cg_run(op, op.mixed, R, tau, 0.5 * rtol, maxit - total, st, &bd, outer == 0 ? &cond : nullptr);
         breakdown = breakdown || bd;
         hipck(launch_vec_add(n, op.d_d, u, st), "update");
         worst = outer_residual(op, b, u, R, st);
@@ -1596,6 +1695,7 @@ void solve_impl(fpde_op& op, const double* b, double* u, int64_t R, double rtol,
         info->rel_residual = worst;
         info->converged = worst <= rtol ? 1 : 0;
         info->refinements = outer;
+        info->cond_estimate = cond;
     }
     if (!(worst <= rtol))
         fail(FPDE_ENOCONV, breakdown ? "fpde_solve: CG breakdown (operator not positive definite in working precision)"

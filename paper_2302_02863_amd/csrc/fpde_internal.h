@@ -360,8 +360,13 @@ struct CgDims {
     int64_t nb;     // row blocks of the reductions (cg_row_blocks)
 };
 struct CgScalars {  // device arrays of S entries (n_active: one int)
+    // rr: r . z of the committed iteration (z = D^-1 r with the Jacobi preconditioner, else r)
     double *rr, *rr_next, *alpha, *beta, *tol2;
     int *active, *active_next, *iters, *flags, *n_active;
+    // Lanczos coefficients of the run: hist_a[k * S + s] = alpha_k, hist_b[k * S + s] = beta_k
+    // for k < hist_cap (null: not recorded)
+    double *hist_a = nullptr, *hist_b = nullptr;
+    int hist_cap = 0;
 };
 enum { CG_DOT = 0, CG_UPDATE_UR = 1, CG_RESID = 2, CG_COPY_RP = 3, CG_UPDATE_P = 4 };
 int64_t cg_row_blocks(int64_t N, int R);
@@ -370,11 +375,21 @@ int64_t cg_row_blocks(int64_t N, int R);
 // part2 = b.b; CG_COPY_RP r = p = b, u = 0, part1 = b.b.  part_in: the partials the
 // coefficient of CG_UPDATE_UR / CG_UPDATE_P is summed from.
 // nb_in: partials per system in part_in (default: the pass's own block count)
+// dinv [F][N] (null: no preconditioner): the Jacobi preconditioner z = D^-1 r.  With it
+// CG_UPDATE_UR also stores r . r in part2 and CG_UPDATE_P stops on the r . r partials part_in2;
+// CG_COPY_RP stores b . z in part1 and b . b in part2.
 hipError_t launch_cg_rowblock(int op, const CgDims& d, const double* a, const double* b, double* u, double* r,
                               double* p, double* part1, double* part2, const double* part_in, const CgScalars& c,
-                              hipStream_t st, int64_t nb_in = -1);
+                              hipStream_t st, int64_t nb_in = -1, const double* dinv = nullptr,
+                              const double* part_in2 = nullptr);
+// part: b . z partials (rr of the first iteration); part_rr: b . b partials for the stopping
+// threshold (null: part)
 hipError_t launch_cg_start(const CgDims& d, const double* part, const double* bb0, double tau_in, double rtol,
-                           const CgScalars& c, hipStream_t st);
+                           const CgScalars& c, hipStream_t st, const double* part_rr = nullptr);
+// dinv[f][i] = 1 / (diagonal of A_h) from the B + M diagonal entries and the panel entries of
+// the leaf self-blocks: diag[f][i] = bm[f * nnz + bm_idx[i]] + panel[f * ptot + p_idx[i]]
+hipError_t launch_jacobi_diag(int64_t N, int F, int64_t nnz, const int64_t* bm_idx, const double* bm, int64_t ptot,
+                              const int64_t* p_idx, const double* panel, double* dinv, hipStream_t st);
 hipError_t launch_cg_sum2(const CgDims& d, const double* part1, const double* part2, double* o1, double* o2,
                           hipStream_t st);
 hipError_t launch_vec_add(int64_t n, const double* d, double* u, hipStream_t st);

@@ -72,12 +72,18 @@ __device__ inline double sum_parts(const double* part, int64_t nb, int R, int64_
 //                 count, active_next and adds its field's active systems to n_active
 //   CG_RESID:     r = b - Ap, part1 = r . r, part2 = b . b              (a=Ap, b=b)
 //   CG_COPY_RP:   r = b, p = b, u = 0, part1 = b . b                    (b=b)
+//   with the Jacobi preconditioner (dinv, z = D^-1 r): CG_UPDATE_UR part1 = r . z and
+//   part2 = r . r; CG_UPDATE_P p = z + beta p with beta from the r . z partials and the
+//   stopping test on the r . r partials part_in2; CG_COPY_RP p = D^-1 b, part1 = b . z,
+//   part2 = b . b.  The Lanczos coefficients alpha_k, beta_k are recorded when asked.
 template <int OP>
 __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb, const double* __restrict__ a,
                                                   const double* __restrict__ b, double* __restrict__ u,
                                                   double* __restrict__ r, double* __restrict__ p,
                                                   double* __restrict__ part1, double* __restrict__ part2,
-                                                  const double* __restrict__ part_in, int64_t nb_in, CgScalars c) {
+                                                  const double* __restrict__ part_in, int64_t nb_in, CgScalars c,
+                                                  const double* __restrict__ dinv,
+                                                  const double* __restrict__ part_in2) {
     __shared__ double red[kBS];
     __shared__ double coef[kBS];
     __shared__ int nact;
@@ -114,10 +120,29 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
                 if (rl < s) red[t] += red[t + s * RC];
                 __syncthreads();
             }
+            double v2 = 0.0;   // r . r of the new residual (preconditioned CG_UPDATE_P)
+            if (OP == CG_UPDATE_P && part_in2) {
+                const double v1 = red[cl];
+                __syncthreads();
+                double pw = 0.0;
+                if (col < R)
+                    for (int64_t b = rl; b < nb_in; b += nrl) pw += part_in2[((int64_t)f * nb_in + b) * R + col];
+                red[t] = pw;
+                __syncthreads();
+                for (int s = nrl / 2; s >= 1; s >>= 1) {
+                    if (rl < s) red[t] += red[t + s * RC];
+                    __syncthreads();
+                }
+                v2 = red[cl];
+                __syncthreads();
+                if (rl == 0) red[cl] = v1;
+                __syncthreads();
+            }
             if (rl == 0) {   // per-system coefficient, once per column
                 double cf = 0.0;
                 if (col < R) {
                     const double v = red[cl];
+                    const double vs = (OP == CG_UPDATE_P && part_in2) ? v2 : v;
                     const bool act = c.active[sys] != 0;
                     if (OP == CG_UPDATE_UR) {
                         const bool ok = act && v > 0.0 && v == v;
@@ -125,6 +150,8 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
                         if (first) {
                             c.alpha[sys] = cf;
                             if (act && !ok) c.flags[sys] = 1;
+                            const int k = c.iters[sys];
+                            if (act && c.hist_a && k < c.hist_cap) c.hist_a[(int64_t)k * gridDim.y * R + sys] = cf;
                         }
                     } else {
                         const bool moved = act && c.alpha[sys] != 0.0;
@@ -132,8 +159,10 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
                         if (first) {
                             c.beta[sys] = cf;
                             c.rr_next[sys] = moved ? v : c.rr[sys];
+                            const int k = c.iters[sys];
+                            if (moved && c.hist_b && k < c.hist_cap) c.hist_b[(int64_t)k * gridDim.y * R + sys] = cf;
                             if (moved) c.iters[sys] += 1;
-                            const int still = (moved && v > c.tol2[sys]) ? 1 : 0;
+                            const int still = (moved && vs > c.tol2[sys]) ? 1 : 0;
                             c.active_next[sys] = still;
                             atomicAdd(&nact, still);
                         }
@@ -154,9 +183,14 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
                     u[i] += cf * a[i];
                     const double rn = r[i] - cf * b[i];
                     r[i] = rn;
-                    acc1 += rn * rn;
+                    if (dinv) {
+                        acc1 += rn * rn * dinv[(int64_t)f * N + row];
+                        acc2 += rn * rn;
+                    } else {
+                        acc1 += rn * rn;
+                    }
                 } else if (OP == CG_UPDATE_P) {
-                    p[i] = a[i] + cf * p[i];
+                    p[i] = (dinv ? a[i] * dinv[(int64_t)f * N + row] : a[i]) + cf * p[i];
                 } else if (OP == CG_RESID) {
                     const double rn = b[i] - a[i];
                     r[i] = rn;
@@ -164,10 +198,12 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
                     acc2 += b[i] * b[i];
                 } else {
                     const double bv = b[i];
+                    const double zv = dinv ? bv * dinv[(int64_t)f * N + row] : bv;
                     r[i] = bv;
-                    p[i] = bv;
+                    p[i] = zv;
                     u[i] = 0.0;
-                    acc1 += bv * bv;
+                    acc1 += bv * zv;
+                    acc2 += bv * bv;
                 }
             }
         }
@@ -175,7 +211,8 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
             __syncthreads();   // coef[] is rewritten by the next column chunk
         } else {
             reduce_store(red, acc1, RC, col, R, part1 + ((int64_t)f * nb + blockIdx.x) * R);
-            if (OP == CG_RESID) reduce_store(red, acc2, RC, col, R, part2 + ((int64_t)f * nb + blockIdx.x) * R);
+            if (OP == CG_RESID || ((OP == CG_UPDATE_UR || OP == CG_COPY_RP) && part2))
+                reduce_store(red, acc2, RC, col, R, part2 + ((int64_t)f * nb + blockIdx.x) * R);
         }
     }
     if (OP == CG_UPDATE_P && first && t == 0) atomicAdd(c.n_active, nact);
@@ -185,18 +222,19 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
 // stopping threshold tol2_s = max(tau_in^2 |r_s|^2, rtol^2 |b0_s|^2), where bb0
 // holds |b0|^2 of the outer system; the committed and the next state agree.
 __global__ __launch_bounds__(kBS) void k_cg_start(int64_t S, int64_t nb, int R, const double* part, const double* bb0,
-                                                   double tau_in, double rtol, CgScalars c) {
+                                                   double tau_in, double rtol, CgScalars c, const double* part_rr) {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     int mine = 0;
     for (int64_t s = threadIdx.x; s < S; s += blockDim.x) {
-        const double rn = sum_parts(part, nb, R, s);
+        const double rz = sum_parts(part, nb, R, s);
+        const double rn = part_rr ? sum_parts(part_rr, nb, R, s) : rz;
         const double t_in = tau_in * tau_in * rn, t_out = rtol * rtol * bb0[s];
         const double tol2 = t_in > t_out ? t_in : t_out;
         const int act = rn > tol2 ? 1 : 0;
-        c.rr[s] = rn;
-        c.rr_next[s] = rn;
+        c.rr[s] = rz;
+        c.rr_next[s] = rz;
         c.tol2[s] = tol2;
         c.active[s] = act;
         c.active_next[s] = act;
@@ -244,13 +282,13 @@ int64_t cg_row_blocks(int64_t N, int R) {
 
 hipError_t launch_cg_rowblock(int op, const CgDims& d, const double* a, const double* b, double* u, double* r,
                               double* p, double* part1, double* part2, const double* part_in, const CgScalars& c,
-                              hipStream_t st, int64_t nb_in) {
+                              hipStream_t st, int64_t nb_in, const double* dinv, const double* part_in2) {
     const int64_t rpb = (d.N + d.nb - 1) / d.nb;
     if (nb_in < 0) nb_in = d.nb;
     const dim3 g((unsigned)d.nb, (unsigned)d.F);
 #define FPDE_ROWBLOCK(OPV)                                                                                          \
     hipLaunchKernelGGL(k_rowblock<OPV>, g, dim3(kBS), 0, st, d.N, d.R, rpb, a, b, u, r, p, part1, part2, part_in, \
-                       nb_in, c)
+                       nb_in, c, dinv, part_in2)
     switch (op) {
         case CG_DOT: FPDE_ROWBLOCK(CG_DOT); break;
         case CG_UPDATE_UR: FPDE_ROWBLOCK(CG_UPDATE_UR); break;
@@ -264,9 +302,9 @@ hipError_t launch_cg_rowblock(int op, const CgDims& d, const double* a, const do
 }
 
 hipError_t launch_cg_start(const CgDims& d, const double* part, const double* bb0, double tau_in, double rtol,
-                           const CgScalars& c, hipStream_t st) {
+                           const CgScalars& c, hipStream_t st, const double* part_rr) {
     const int64_t S = (int64_t)d.F * d.R;
-    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kBS), 0, st, S, d.nb, d.R, part, bb0, tau_in, rtol, c);
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kBS), 0, st, S, d.nb, d.R, part, bb0, tau_in, rtol, c, part_rr);
     return hipGetLastError();
 }
 
@@ -274,6 +312,25 @@ hipError_t launch_cg_sum2(const CgDims& d, const double* part1, const double* pa
                           hipStream_t st) {
     const int64_t S = (int64_t)d.F * d.R;
     hipLaunchKernelGGL(k_sum2, dim3(grid_of(S)), dim3(kBS), 0, st, S, d.nb, d.R, part1, part2, o1, o2);
+    return hipGetLastError();
+}
+
+// 1 / diag(A_h) per field and dof
+__global__ __launch_bounds__(kBS) void k_jacobi_diag(int64_t N, int F, int64_t nnz, const int64_t* bm_idx,
+                                                      const double* bm, int64_t ptot, const int64_t* p_idx,
+                                                      const double* panel, double* dinv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int f = 0; f < F; ++f) {
+        const double d = bm[(int64_t)f * nnz + bm_idx[i]] + (p_idx[i] >= 0 ? panel[(int64_t)f * ptot + p_idx[i]] : 0.0);
+        dinv[(int64_t)f * N + i] = 1.0 / d;
+    }
+}
+
+hipError_t launch_jacobi_diag(int64_t N, int F, int64_t nnz, const int64_t* bm_idx, const double* bm, int64_t ptot,
+                              const int64_t* p_idx, const double* panel, double* dinv, hipStream_t st) {
+    hipLaunchKernelGGL(k_jacobi_diag, dim3(grid_of(N)), dim3(kBS), 0, st, N, F, nnz, bm_idx, bm, ptot, p_idx, panel,
+                       dinv);
     return hipGetLastError();
 }
 

@@ -19,6 +19,9 @@ def opts_struct(opts: dict | None = None, plan_only: bool = False) -> _abi.Opts:
     for key, val in (opts or {}).items():
         if key == "precision":
             o.precision = _abi.PREC_MIXED if val in ("mixed", _abi.PREC_MIXED) else _abi.PREC_FP64
+        elif key == "jacobi":
+            if val:
+                o.flags |= _abi.FLAG_JACOBI
         elif hasattr(o, key):
             setattr(o, key, val)
     if plan_only:
@@ -136,7 +139,8 @@ class Operator:
         st = lib().fpde_solve(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(u.data_ptr()), F.shape[2], rtol,
                               maxit, C.byref(info), _stream_handle(stream))
         out = {"iterations": info.iterations, "rel_residual": info.rel_residual,
-               "converged": bool(info.converged), "refinements": info.refinements}
+               "converged": bool(info.converged), "refinements": info.refinements,
+               "cond_estimate": info.cond_estimate}
         if st != _abi.FPDE_OK and (raise_on_noconv or st != _abi.FPDE_ENOCONV):
             check(st, "fpde_solve")
         return u, out
