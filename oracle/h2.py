@@ -13,8 +13,12 @@ Admissibility, centre form used in the paper's experiments (Sec. 7):
   * for K~: boxes extended to the supports of the cluster's basis functions
     (omega^e, Sec. 5.1) and dist(omega^e, omega^e') > 0, so no far block
     contains a touching element pair;
-  * for the density: plain point boxes and dist > 2 h_max, so gamma_T = gamma
-    on far blocks (the assumption stated with eq. i:addmi-q).
+  * for the density: plain point boxes and dist > h_sigma + h_sigma', h_sigma
+    the largest diameter of the cells that hold the cluster's points, so no far
+    block pairs points of touching cells and gamma_T = gamma on it (the
+    assumption stated with eq. i:addmi-q; two points of touching cells are at
+    most diam + diam' apart).  On a quasi-uniform mesh this is the bound
+    2 h_max; on a graded exterior it stays local.
 
 Far blocks (eq. eq:interpolant, eq:triple_product): tensor Lagrange
 interpolation at p first-kind Chebyshev points per dimension on the box,
@@ -110,11 +114,37 @@ def _admissible(lo_a, hi_a, lo_b, hi_b, eta, min_dist):
     return (eta * dcent >= 0.5 * (Da + Db)) and (math.sqrt(g2) > min_dist)
 
 
-def partition(tree, lo, hi, eta, min_dist):
+def cell_diameters(mesh):
+    """Largest edge length of every cell."""
+    X = mesh.coords[:, mesh.cells]                 # (dim, dim+1, nc)
+    k = mesh.dim + 1
+    h = np.zeros(mesh.cells.shape[1])
+    for a in range(k):
+        for b in range(a + 1, k):
+            h = np.maximum(h, np.sqrt(((X[:, a] - X[:, b]) ** 2).sum(axis=0)))
+    return h
+
+
+def cluster_h(tree, h_point):
+    """Per cluster: the largest of h_point over its members (h_point: the diameter of
+    each point's cell)."""
+    out = np.zeros(tree.n_clusters)
+    for c in range(tree.n_clusters - 1, -1, -1):
+        if tree.is_leaf(c):
+            out[c] = h_point[tree.members[c]].max() if tree.members[c].size else 0.0
+        else:
+            out[c] = max(out[2 * c + 1], out[2 * c + 2])
+    return out
+
+
+def partition(tree, lo, hi, eta, hc=None):
+    """Dual traversal from (root, root); ``hc``: per-cluster separation, a pair is far
+    only if its boxes are more than hc[a] + hc[b] apart (None: more than 0)."""
     far, near = [], []
     stack = [(0, 0)]
     while stack:
         a, b = stack.pop()
+        min_dist = 0.0 if hc is None else hc[a] + hc[b]
         if _admissible(lo[a], hi[a], lo[b], hi[b], eta, min_dist):
             far.append((a, b))
         elif tree.is_leaf(a):
@@ -209,7 +239,7 @@ def assemble_K_h2(mesh, s, kappa, opts, K_exact=None, return_parts=False):
     N = mesh.n_dofs
     p = opts["cheb_p"]
     tree, lo, hi, node_cells = node_tree(mesh, opts)
-    far, near = partition(tree, lo, hi, opts["eta"], 0.0)
+    far, near = partition(tree, lo, hi, opts["eta"])
     Q = _qdata(mesh, s, kappa, opts["nq_reg"])
     if K_exact is None:
         from .assembly import assemble_split
@@ -255,7 +285,8 @@ def rho_h2(mesh, s, kappa, opts, Q=None, return_parts=False):
     hi = np.zeros((tree.n_clusters, mesh.dim))
     for c in range(tree.n_clusters):
         lo[c], hi[c] = box_of(Q["x"][:, tree.members[c]])
-    far, near = partition(tree, lo, hi, opts["eta"], 2.0 * mesh.h_max())
+    hc = cluster_h(tree, cell_diameters(mesh)[Q["cell"]])
+    far, near = partition(tree, lo, hi, opts["eta"], hc)
     T = touching_cells(mesh)
     is_int = mesh.cell_interior[Q["cell"]] > 0
     rho = np.zeros(nq, dtype=np.result_type(s, kappa, np.float64))

@@ -29,7 +29,7 @@ import numpy as np
 
 from .assembly import _qdata, rho_exterior_at
 from .fields import gamma
-from .h2 import ClusterTree, box_of, cheb_nodes, lagrange, _admissible
+from .h2 import ClusterTree, box_of, cheb_nodes, cluster_h, cell_diameters, lagrange, _admissible
 from .singular import canonical_pair, pair_local_dofs, pair_matrix
 
 
@@ -66,24 +66,27 @@ class _Locator:
 
     def value(self, field, p, tol=1e-12):
         m = self.m
-        for c in self._candidates(p):
-            X = m.coords[:, m.cells[:, c]]
+        c = self._candidates(p)
+        if c.size:
+            X = m.coords[:, m.cells[:, c]]                 # (d, d+1, ncand)
             if m.dim == 1:
                 t = (p[0] - X[0, 0]) / (X[0, 1] - X[0, 0])
-                L = (1.0 - t, t)
+                L = np.stack([1.0 - t, t])
             else:
-                P0, P1, P2 = X[:, 0], X[:, 1], X[:, 2]
-                e1 = P1 - P0
-                e2 = P2 - P0
+                P0 = X[:, 0]
+                e1 = X[:, 1] - P0
+                e2 = X[:, 2] - P0
                 den = e1[0] * e2[1] - e1[1] * e2[0]
-                dx = p - P0
+                dx = p[:, None] - P0
                 b1 = (dx[0] * e2[1] - dx[1] * e2[0]) / den
                 b2 = (e1[0] * dx[1] - e1[1] * dx[0]) / den
-                L = (1.0 - b1 - b2, b1, b2)
-            if all(l >= -tol for l in L):
-                v = field[m.cells[0, c]] * L[0]
+                L = np.stack([1.0 - b1 - b2, b1, b2])
+            hit = np.flatnonzero((L >= -tol).all(axis=0))
+            if hit.size:                                   # candidates are sorted: lowest cell id
+                j = hit[0]
+                v = field[m.cells[0, c[j]]] * L[0, j]
                 for a in range(1, m.dim + 1):
-                    v = v + field[m.cells[a, c]] * L[a]
+                    v = v + field[m.cells[a, c[j]]] * L[a, j]
                 return v
         d2 = ((m.coords - p[:, None]) ** 2).sum(axis=0)
         return field[int(np.argmin(d2))]
@@ -137,7 +140,7 @@ class SampledOracle:
         self.leaf_of_q = np.empty(self.Q["w"].size, dtype=np.int64)
         for c in rt.leaves():
             self.leaf_of_q[rt.members[c]] = c
-        self.hmax = m.h_max()
+        self.rh = cluster_h(rt, cell_diameters(m)[self.Q["cell"]])
         self._xhat = {}
         self._xhat_of = None      # the vector the cached coefficients belong to
         self._mom = {}
@@ -295,7 +298,8 @@ class SampledOracle:
         eta = self.o["eta"]
         while stack:
             a, b = stack.pop()
-            if _admissible(self.rlo[a], self.rhi[a], self.rlo[b], self.rhi[b], eta, 2.0 * self.hmax):
+            if _admissible(self.rlo[a], self.rhi[a], self.rlo[b], self.rhi[b], eta,
+                           self.rh[a] + self.rh[b]):
                 na, axa, sa, ka = self._cluster_nodes(("r", a), self.rlo[a], self.rhi[a])
                 nb, axb, sb, kb = self._cluster_nodes(("r", b), self.rlo[b], self.rhi[b])
                 S = gamma(m.dim, self.o["a_scale"], na[:, :, None], nb[:, None, :], sa[:, None], sb[None, :],

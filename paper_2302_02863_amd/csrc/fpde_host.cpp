@@ -117,7 +117,6 @@ struct fpde_op {
     // density tree
     Tree rt;
     std::vector<std::pair<int64_t, int64_t>> rfar, rnear;
-    double hmax = 0.0;
     // CSR in tree order
     std::vector<int64_t> csr_ptr;
     std::vector<int32_t> csr_col;
@@ -389,7 +388,6 @@ void plan(fpde_op& op) {
     op.Q = quad_points(m, op.er);
     op.ncs = node_cells(m);
     op.pairs = touching_pairs(m, op.ncs);
-    op.hmax = h_max(m);
     // device order of pairs: by kind (uniform waves), pair order kept within a kind
     {
         int64_t start[4] = {0, 0, 0, 0};
@@ -421,7 +419,7 @@ void plan(fpde_op& op) {
             kt.lo[c * d + kk] = std::min(kt.lo[(2 * c + 1) * d + kk], kt.lo[(2 * c + 2) * d + kk]);
             kt.hi[c * d + kk] = std::max(kt.hi[(2 * c + 1) * d + kk], kt.hi[(2 * c + 2) * d + kk]);
         }
-    partition(kt, op.opts.eta, 0.0, nullptr, op.kfar, op.knear);
+    partition(kt, op.opts.eta, nullptr, nullptr, op.kfar, op.knear);
     op.pos_of_dof.assign(m.N, -1);
     for (int64_t j = 0; j < m.N; ++j) op.pos_of_dof[kt.perm[j]] = j;
     // density tree over all quadrature points; prune targets without interior points
@@ -434,7 +432,15 @@ void plan(fpde_op& op) {
                 skip[c] = 0;
                 break;
             }
-    partition(op.rt, op.opts.eta, 2.0 * op.hmax, &skip, op.rfar, op.rnear);
+    // far only beyond the diameters of the cells holding either cluster's points, so no
+    // far pair lies in touching cells (gamma_T = gamma there)
+    {
+        const std::vector<double> hcell = cell_diameters(m);
+        std::vector<double> hq(op.Q.nq);
+        for (int64_t q = 0; q < op.Q.nq; ++q) hq[q] = hcell[q / op.Q.nqe];
+        const std::vector<double> hc = cluster_h(op.rt, hq.data());
+        partition(op.rt, op.opts.eta, &hc, &skip, op.rfar, op.rnear);
+    }
     // CSR pattern of B (and M) in tree order: the (row, column) entries of every pair,
     // bucketed by row, then each row's columns sorted and made unique
     {

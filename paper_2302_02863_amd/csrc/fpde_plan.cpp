@@ -314,7 +314,7 @@ bool admissible(int dim, const double* lo_a, const double* hi_a, const double* l
     return (eta * dcent >= 0.5 * (Da + Db)) && (std::sqrt(g2) > min_dist);
 }
 
-void partition(const Tree& t, double eta, double min_dist, const std::vector<uint8_t>* skip,
+void partition(const Tree& t, double eta, const std::vector<double>* hc, const std::vector<uint8_t>* skip,
                std::vector<std::pair<int64_t, int64_t>>& far,
                std::vector<std::pair<int64_t, int64_t>>& near) {
     far.clear();
@@ -325,6 +325,7 @@ void partition(const Tree& t, double eta, double min_dist, const std::vector<uin
         auto [a, b] = stack.back();
         stack.pop_back();
         if (skip && (*skip)[a]) continue;
+        const double min_dist = hc ? (*hc)[a] + (*hc)[b] : 0.0;
         if (admissible(d, &t.lo[a * d], &t.hi[a * d], &t.lo[b * d], &t.hi[b * d], eta, min_dist)) {
             far.push_back({a, b});
         } else if (a >= t.first_leaf()) {
@@ -352,8 +353,8 @@ void cheb_axes(int dim, const double* lo, const double* hi, int p, double* out) 
     }
 }
 
-double h_max(const HostMesh& m) {
-    double best = 0.0;
+std::vector<double> cell_diameters(const HostMesh& m) {
+    std::vector<double> h(m.nc, 0.0);
     const int k = m.dim + 1;
     for (int64_t c = 0; c < m.nc; ++c)
         for (int a = 0; a < k; ++a)
@@ -363,9 +364,21 @@ double h_max(const HostMesh& m) {
                     double dx = m.x(d, m.v(a, c)) - m.x(d, m.v(b, c));
                     s = s + dx * dx;
                 }
-                best = std::max(best, std::sqrt(s));
+                h[c] = std::max(h[c], std::sqrt(s));
             }
-    return best;
+    return h;
+}
+
+std::vector<double> cluster_h(const Tree& t, const double* h_point) {
+    std::vector<double> out(t.ncl, 0.0);
+    for (int64_t c = t.ncl - 1; c >= 0; --c) {
+        if (c >= t.first_leaf()) {
+            for (int64_t i = t.beg[c]; i < t.end[c]; ++i) out[c] = std::max(out[c], h_point[t.perm[i]]);
+        } else {
+            out[c] = std::max(out[2 * c + 1], out[2 * c + 2]);
+        }
+    }
+    return out;
 }
 
 // ------------------------------------------------------------------ locator
@@ -379,7 +392,11 @@ void Locator::build(const HostMesh& mesh) {
             glo[k] = std::min(glo[k], mesh.x(k, v));
             ghi[k] = std::max(ghi[k], mesh.x(k, v));
         }
-    double h = std::max(h_max(mesh), 1e-300);
+    // bins about two mean cell widths wide (a graded mesh's few large cells go into
+    // every bin they overlap)
+    double vol = 1.0;
+    for (int k = 0; k < d; ++k) vol *= std::max(ghi[k] - glo[k], 1e-300);
+    double h = std::max(std::pow(vol / (double)std::max<int64_t>(mesh.nc, 1), 1.0 / d), 1e-300);
     for (int k = 0; k < 2; ++k) {
         if (k < d) {
             lo[k] = glo[k] - h;

@@ -75,8 +75,10 @@ void point_boxes(Tree& t, const double* pts, int64_t stride);
 bool admissible(int dim, const double* lo_a, const double* hi_a, const double* lo_b,
                 const double* hi_b, double eta, double min_dist);
 
-// dual-tree partition; skip_target[c] != 0 prunes target clusters
-void partition(const Tree& t, double eta, double min_dist, const std::vector<uint8_t>* skip_target,
+// dual-tree partition; a pair is far only if admissible and its boxes are more than
+// hc[a] + hc[b] apart (hc == nullptr: more than 0); skip_target[c] != 0 prunes targets
+void partition(const Tree& t, double eta, const std::vector<double>* hc,
+               const std::vector<uint8_t>* skip_target,
                std::vector<std::pair<int64_t, int64_t>>& far,
                std::vector<std::pair<int64_t, int64_t>>& near);
 
@@ -96,6 +98,9 @@ struct Locator {
     double interp(const double* field, const double* p) const;
 };
 
-double h_max(const HostMesh& m);
+// largest edge length of every cell
+std::vector<double> cell_diameters(const HostMesh& m);
+// per cluster: the largest h_point[i] over its member points i
+std::vector<double> cluster_h(const Tree& t, const double* h_point);
 
 }  // namespace fpde

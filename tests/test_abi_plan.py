@@ -17,7 +17,7 @@ import pytest
 from fpde_inputs import configs
 from oracle.rules import gauss01
 from oracle.singular import touching_pairs
-from oracle.h2 import ClusterTree, node_tree, partition, box_of
+from oracle.h2 import ClusterTree, box_of, cell_diameters, cluster_h, node_tree, partition
 from oracle.fields import quad_points
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -94,7 +94,7 @@ def test_k_tree_and_partition_match_oracle(fp, case):
     assert _leaf_sets(perm, leafptr) == ref_leaves
     boxes = op.export("K_BOXES").reshape(tree.n_clusters, 2, P.mesh.dim)
     assert np.array_equal(boxes[:, 0], lo) and np.array_equal(boxes[:, 1], hi)
-    far, near = partition(tree, lo, hi, P.opts["eta"], 0.0)
+    far, near = partition(tree, lo, hi, P.opts["eta"])
     gf = {tuple(p) for p in op.export("K_FAR").reshape(-1, 2)}
     gn = {tuple(p) for p in op.export("K_NEAR").reshape(-1, 2)}
     assert gf == set(far) and gn == set(near)
@@ -119,7 +119,7 @@ def test_rho_tree_and_partition_match_oracle(fp, case):
         pass
     lo = boxes[:, 0]
     hi = boxes[:, 1]
-    far, near = partition(tree, lo, hi, P.opts["eta"], 2.0 * m.h_max())
+    far, near = partition(tree, lo, hi, P.opts["eta"], cluster_h(tree, cell_diameters(m)[Q["cell"]]))
     is_int = m.cell_interior[Q["cell"]] > 0
     has_int = [bool(is_int[tree.members[c]].any()) for c in range(tree.n_clusters)]
     gf = {tuple(p) for p in op.export("RHO_FAR").reshape(-1, 2)}

@@ -14,7 +14,9 @@ import pytest
 
 from fpde_inputs import configs
 from oracle.assembly import assemble_split, touching_cells, rho_direct
-from oracle.h2 import ClusterTree, node_tree, partition, assemble_K_h2, rho_h2, cheb_nodes, lagrange
+from oracle.fields import quad_points
+from oracle.h2 import (ClusterTree, assemble_K_h2, cell_diameters, cheb_nodes, cluster_h, lagrange,
+                       node_tree, partition, rho_h2)
 
 
 @pytest.fixture(scope="module")
@@ -41,7 +43,7 @@ def test_tree_uniform_depth_and_median():
 def test_partition_covers_once(prob):
     P, s, k, sp = prob
     tree, lo, hi, node_cells = node_tree(P.mesh, P.opts)
-    far, near = partition(tree, lo, hi, P.opts["eta"], 0.0)
+    far, near = partition(tree, lo, hi, P.opts["eta"])
     N = P.mesh.n_dofs
     cnt = np.zeros((N, N), dtype=int)
     for a, b in far + near:
@@ -105,3 +107,40 @@ def test_rho_direct_1d_closed_form():
         ref = ((x - a) ** (-2 * s) - (x + L) ** (-2 * s) + (b - x) ** (-2 * s) - (L - x) ** (-2 * s)) / (2 * s)
         errs.append(np.abs(rho - ref).max() / ref.max())
     assert errs[1] < errs[0] and errs[2] < errs[1] and errs[2] < 1e-6, errs
+
+
+@pytest.mark.parametrize("n,graded", [(8, 0.0), (16, 1.5)])
+def test_density_partition_local_guard(n, graded):
+    # Sec. 6.2: gamma_T = gamma must hold on every far density block, i.e. no far pair of
+    # clusters holds points of touching cells.  The guard dist > h_a + h_b uses the cells of
+    # each cluster's own points; on a graded exterior it is much smaller than 2 h_max for the
+    # interior clusters, and the partition still covers every point pair once.
+    P = configs.square(n, n // 2, graded=graded, leaf_size_rho=32)
+    m = P.mesh
+    Q = quad_points(m, P.opts["nq_reg"])
+    nq = Q["w"].size
+    tree = ClusterTree(Q["x"], np.arange(nq), P.opts["leaf_size_rho"])
+    lo = np.array([Q["x"][:, tree.members[c]].min(axis=1) for c in range(tree.n_clusters)])
+    hi = np.array([Q["x"][:, tree.members[c]].max(axis=1) for c in range(tree.n_clusters)])
+    hq = cell_diameters(m)[Q["cell"]]
+    hc = cluster_h(tree, hq)
+    # the diameters are the longest edges, brute force per cell
+    X = m.coords[:, m.cells]
+    hb = np.array([max(np.linalg.norm(X[:, a, c] - X[:, b, c]) for a in range(3) for b in range(a + 1, 3))
+                   for c in range(m.n_cells)])
+    assert np.allclose(cell_diameters(m), hb, rtol=1e-15, atol=0)
+    for c in range(tree.n_clusters):
+        assert hc[c] == hq[tree.members[c]].max()
+    far, near = partition(tree, lo, hi, P.opts["eta"], hc)
+    cnt = np.zeros((nq, nq), dtype=np.int8)
+    for a, b in far + near:
+        cnt[np.ix_(tree.members[a], tree.members[b])] += 1
+    assert (cnt == 1).all()
+    assert len(far) > 0
+    T = touching_cells(m)
+    for a, b in far:
+        assert T[Q["cell"][tree.members[a]]][:, Q["cell"][tree.members[b]]].nnz == 0
+    if graded:
+        # interior clusters keep a separation near the interior cells' size
+        inner = [c for c in tree.leaves() if (m.cell_interior[Q["cell"][tree.members[c]]] > 0).all()]
+        assert inner and max(hc[c] for c in inner) < 0.4 * hb.max()
