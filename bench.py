@@ -225,9 +225,17 @@ def square128(steps, warmup):
     el_m = time_applies(opm, x, ym, stream, steps, warmup)
     out["mixed"] = {"value": N * steps / el_m, "ms_per_step": el_m / steps * 1e3,
                     "max_rel_err_vs_fp64": per_vector_rel_err(ym, y), "speedup_vs_fp64": el / el_m}
-    # one-vector solve of the load vector of f = 1
+    # one-vector solve of the load vector of f = 1, plain and Jacobi-preconditioned CG
     Fv = op.load_vector(torch.ones(P.mesh.n_nodes, dtype=torch.float64, device=x.device)).reshape(1, -1, 1)
     out["solve"] = solve_pair(op, opm, Fv, rtol=1e-10)
+    oj = dict(P.opts)
+    oj["jacobi"] = True
+    opj = fp.Operator(P.mesh, P.s, P.kappa, oj)
+    oj["precision"] = "mixed"
+    opjm = fp.Operator(P.mesh, P.s, P.kappa, oj)
+    out["solve_jacobi"] = solve_pair(opj, opjm, Fv, rtol=1e-10)
+    opj.close()
+    opjm.close()
     # adjoint: gradient of w^T A u in every nodal s and kappa
     out["adjoint_ms"] = time_adjoint(op, x, x)
     opm.close()
@@ -252,7 +260,8 @@ def solve_pair(op64, opm, Fv, rtol, maxit=50000, ref_rtol=None):
         u, info = op.solve(Fv, rtol=rtol, maxit=maxit)
         torch.cuda.synchronize()
         res[name] = {"ms": (time.perf_counter() - t0) * 1e3, "iterations": info["iterations"],
-                     "refinements": info["refinements"], "rel_residual": info["rel_residual"]}
+                     "refinements": info["refinements"], "rel_residual": info["rel_residual"],
+                     "cond_estimate": info["cond_estimate"]}
         if uref is not None:
             res[name]["solution_rel_err"] = per_vector_rel_err(u, uref)
         res[name]["_u"] = u
@@ -300,6 +309,14 @@ def disk_solve():
            "solve": solve_pair(op, opm, Fv, rtol=1e-10, ref_rtol=1e-12)}
     opm.close()
     op.close()
+    oj = dict(P.opts)
+    oj["jacobi"] = True
+    opj = fp.Operator(P.mesh, P.s, P.kappa, oj)
+    oj["precision"] = "mixed"
+    opjm = fp.Operator(P.mesh, P.s, P.kappa, oj)
+    out["solve_jacobi"] = solve_pair(opj, opjm, Fv, rtol=1e-10, ref_rtol=1e-12)
+    opj.close()
+    opjm.close()
     return out
 
 

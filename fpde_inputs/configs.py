@@ -32,7 +32,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .meshes import Mesh, interval_mesh, square_mesh, disk_mesh
+from .meshes import Mesh, interval_mesh, square_mesh, square_mesh_graded, disk_mesh
 
 
 DEFAULT_OPTS = dict(
@@ -109,10 +109,16 @@ def interval_const(n_int: int = 512, n_ext: int | None = None, s: float = 0.5, *
     return Problem("interval_const", m, sv, kappa, o, np.ones(m.n_nodes), vec, {"s": s})
 
 
-def square(n: int = 128, pad: int | None = None, jitter: float = 0.1, nrhs: int = 1, **kw) -> Problem:
+def square(n: int = 128, pad: int | None = None, jitter: float = 0.1, nrhs: int = 1, graded: float = 0.0,
+           **kw) -> Problem:
+    """``graded`` > 1: the exterior band (-0.5, 1.5)^2 \\ [0,1]^2 graded geometrically with that ratio
+    (same interior grid, jitter, fields and vectors)."""
     if pad is None:
         pad = n // 2
-    m = square_mesh(n, pad, jitter=jitter, seed=0)
+    if graded > 1.0:
+        m = square_mesh_graded(n, 0.5, graded, jitter=jitter, seed=0)
+    else:
+        m = square_mesh(n, pad, jitter=jitter, seed=0)
     x1, x2 = m.coords
     # range [0.1, 0.9] on (-0.5, 1.5)^2; the clip only removes rounding of the grid coordinates
     s = np.clip(0.3 + 0.2 * (x1 + x2), 0.1, 0.9)[None, :]

@@ -112,6 +112,62 @@ def square_mesh(n: int, pad: int, jitter: float = 0.0, seed: int = 0,
                 {"h": h, "kind": "square", "n": n, "pad": pad, "jitter": jitter, "seed": seed})
 
 
+def graded_band(h: float, width: float, q: float) -> np.ndarray:
+    """Offsets 0 < t_1 < ... < t_m = width of the exterior grid lines beyond an interface:
+    the first layer has the interior spacing h, each next one q times the previous, and the
+    graded part is scaled so that the last line lands on ``width``."""
+    w = [h]
+    while sum(w) < width:
+        w.append(w[-1] * q)
+    t = np.cumsum(w)
+    if len(w) > 1:   # keep the first layer at h, stretch the others to end at width
+        t[1:] = h + (t[1:] - h) * (width - h) / (t[-1] - h)
+    else:
+        t[:] = width
+    return t
+
+
+def square_mesh_graded(n: int, width: float, q: float, jitter: float = 0.0, seed: int = 0,
+                       lo: float = 0.0, hi: float = 1.0) -> Mesh:
+    """Interior (lo,hi)^2 with n x n squares inside a band of the given width whose grid lines
+    are graded geometrically away from the interface (``graded_band``), so that the exterior
+    has O(log) instead of O(n) layers.  Squares are split along the same diagonal as in
+    ``square_mesh``; interior nodes are jittered the same way."""
+    h = (hi - lo) / n
+    t = graded_band(h, width, q)
+    g = np.concatenate([lo - t[::-1], lo + h * np.arange(n + 1), hi + t])
+    m = g.size - 1
+    pad = t.size
+    i, j = np.meshgrid(np.arange(m + 1), np.arange(m + 1), indexing="ij")
+    i = i.ravel()
+    j = j.ravel()
+    xy = np.stack([g[i], g[j]]).astype(np.float64)
+    is_dof = (i > pad) & (i < pad + n) & (j > pad) & (j < pad + n)
+    order, new = _renumber(is_dof)
+    coords = xy[:, order].copy()
+    n_dofs = int(is_dof.sum())
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        coords[:, :n_dofs] += rng.uniform(-jitter * h, jitter * h, size=(n_dofs, 2)).T
+
+    def nid(a, b):
+        return new[a * (m + 1) + b]
+
+    si, sj = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    si = si.ravel()
+    sj = sj.ravel()
+    t1 = np.stack([nid(si, sj), nid(si + 1, sj), nid(si + 1, sj + 1)])
+    t2 = np.stack([nid(si, sj), nid(si + 1, sj + 1), nid(si, sj + 1)])
+    cells = np.empty((3, 2 * si.size), dtype=np.int32)
+    cells[:, 0::2] = t1
+    cells[:, 1::2] = t2
+    sq_int = (si >= pad) & (si < pad + n) & (sj >= pad) & (sj < pad + n)
+    interior = np.repeat(sq_int, 2).astype(np.uint8)
+    return Mesh(2, coords, cells, interior, n_dofs, 0.0,
+                {"h": h, "kind": "square_graded", "n": n, "layers": pad, "q": q, "width": width,
+                 "jitter": jitter, "seed": seed})
+
+
 def disk_mesh(n: int, layers: int, radius_out: float, exterior_radius: float = 0.0) -> Mesh:
     """Unit disk from the elliptical square-to-disk map of an n x n grid, plus an annulus.
 
