@@ -184,6 +184,7 @@ def headline(steps, warmup):
                                         / yn).max()),
         "far_part_norm_over_y": float((torch.linalg.vector_norm(yk64.double(), dim=1) / yn).max()),
         "near_panel_norm_over_y": float((torch.linalg.vector_norm(ynear64.double(), dim=1) / yn).max())}
+    out["_y_fp64"] = ys["fp64"]
     return P, x, ops, out
 
 
@@ -317,6 +318,31 @@ def disk_solve():
     out["solve_jacobi"] = solve_pair(opj, opjm, Fv, rtol=1e-10, ref_rtol=1e-12)
     opj.close()
     opjm.close()
+    return out
+
+
+def recompression(P, x, y64, tols=(1e-2, 1e-3, 3e-4)):
+    """The headline workload's mixed apply with the far field's bases recompressed
+    algebraically (closing remark of Sec. 5.3) at several tolerances: cluster ranks,
+    far-chain and apply times, build cost and the error against the FP64 apply."""
+    import torch
+    import paper_2302_02863_amd as fp
+    out = []
+    for tol in tols:
+        o = dict(P.opts)
+        o["precision"] = "mixed"
+        o["recompress_tol"] = tol
+        op = fp.Operator(P.mesh, P.s, P.kappa, o)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            op.apply(x, y)
+        ph = profiled(op, x, y)
+        st = op.stats()
+        out.append({"tol": tol, "rank": st["k_rank_rc"], "rank_mean": st["k_rank_rc_mean"],
+                    "chebyshev_rank": st["k_rank"], "build_ms": st["t_recompress_ms"],
+                    "far_chain_ms": ph["ms_far"], "apply_ms": ph["ms_total"],
+                    "max_rel_err_vs_fp64": per_vector_rel_err(y, y64)})
+        op.close()
     return out
 
 
@@ -559,6 +585,7 @@ def main():
         sys.exit(1)
 
     P, x, ops, hl = headline(args.steps, args.warmup)
+    ys_fp64 = hl.pop("_y_fp64")
     print("[bench] headline done", file=sys.stderr, flush=True)
     F, N, R = P.x.shape
     mixed = hl["mixed"]
@@ -599,6 +626,8 @@ def main():
             extras[name] = {"error": f"{type(exc).__name__}: {exc}"}
         print(f"[bench] {name} done", file=sys.stderr, flush=True)
 
+    if not args.no_extras:
+        extra("recompression", recompression, P, x, ys_fp64)
     if not args.no_extras and not args.no_solve:
         extra("batched_solve_adjoint", batched_solve_and_adjoint, P, x, ops)
     for op in ops.values():

@@ -92,6 +92,14 @@ typedef struct {
     double  a_scale;        /* a(x,y) = a_scale sqrt(kappa(x) kappa(y)) [1]                            */
     uint64_t flags;         /* FPDE_FLAG_* [0]                                                         */
     uint64_t max_device_bytes; /* 0 = unlimited [0]                                                    */
+    double  recompress_tol; /* > 0: algebraic recompression of the far field's nested bases (closing
+                               remark of Sec. 5.3) at this relative tolerance: the Chebyshev bases are
+                               orthogonalised, and each cluster keeps the directions of its total far
+                               weight whose eigenvalues exceed tol^2 times the largest one in the tree,
+                               padded to one rank r <= p^dim.  Needs p^dim <= 32.  Applies (any nrhs)
+                               and solves then run the several-right-hand-side kernels with rank r;
+                               fpde_apply_noalloc rejects such an operator, and fpde_apply_adjoint
+                               differentiates the operator without recompression.  [0 = off]      */
 } fpde_opts;
 
 typedef struct {
@@ -105,6 +113,10 @@ typedef struct {
     double t_plan_ms, t_singular_ms, t_near_blocks_ms, t_bases_ms, t_rho_ms, t_mass_ms, t_total_ms;
     /* bytes streamed by one apply with one right-hand side (dominant arrays) */
     int64_t apply_bytes_near, apply_bytes_csr, apply_bytes_bases;
+    /* algebraic recompression (recompress_tol > 0): uniform rank r (0 if off), the smallest
+       and mean cluster rank before padding, and its build time */
+    int64_t k_rank_rc, k_rank_rc_min;
+    double k_rank_rc_mean, t_recompress_ms;
 } fpde_stats_t;
 
 typedef struct {

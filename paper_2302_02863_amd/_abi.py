@@ -36,7 +36,7 @@ class Opts(C.Structure):
                 ("cheb_p", C.c_int32), ("eta", C.c_double), ("nq_sing", C.c_int32), ("nq_reg", C.c_int32),
                 ("s_bar", C.c_double), ("s_exterior", C.c_double), ("kappa_exterior", C.c_double),
                 ("n_theta", C.c_int32), ("a_scale", C.c_double), ("flags", C.c_uint64),
-                ("max_device_bytes", C.c_uint64)]
+                ("max_device_bytes", C.c_uint64), ("recompress_tol", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -46,7 +46,9 @@ class Stats(C.Structure):
         "rho_points", "rho_clusters", "rho_levels", "rho_far", "rho_near", "device_bytes")] + \
         [(n, C.c_double) for n in ("t_plan_ms", "t_singular_ms", "t_near_blocks_ms", "t_bases_ms", "t_rho_ms",
                                     "t_mass_ms", "t_total_ms")] + \
-        [(n, C.c_int64) for n in ("apply_bytes_near", "apply_bytes_csr", "apply_bytes_bases")]
+        [(n, C.c_int64) for n in ("apply_bytes_near", "apply_bytes_csr", "apply_bytes_bases",
+                                  "k_rank_rc", "k_rank_rc_min")] + \
+        [(n, C.c_double) for n in ("k_rank_rc_mean", "t_recompress_ms")]
 
 
 class Profile(C.Structure):

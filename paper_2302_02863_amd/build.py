@@ -34,8 +34,10 @@ SOURCES = [
     ("fpde_solve.hip", HIP_FLAGS),
     ("fpde_adjoint.hip", HIP_FLAGS),
     ("fpde_noalloc.hip", HIP_FLAGS),
+    ("fpde_recompress.hip", HIP_FLAGS),
     ("fpde_host.cpp", HOST_FLAGS),
     ("fpde_plan.cpp", HOST_FLAGS),
+    ("fpde_recompress.cpp", HOST_FLAGS),
 ]
 
 

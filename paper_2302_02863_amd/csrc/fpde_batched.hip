@@ -186,6 +186,54 @@ __global__ __launch_bounds__(256) void k_blevel(H2Tree t, int64_t c0, int F, int
     }
 }
 
+// One level of dense transfers (recompressed bases, K <= 32), per (parent cluster, rhs
+// chunk, field), Ed[c][b][a] = E_c[b][a] (child index b, parent index a):
+//   up:   X^_p[a] = sum_c sum_b E_c[b][a] X^_c[b]
+//   down: Y^_c[b] += sum_a E_c[b][a] Y^_p[a]
+template <typename T, bool UP>
+__global__ __launch_bounds__(256) void k_blevel_dense(H2Tree t, int64_t c0, int F, int R, const T* Ed, T* xh) {
+    constexpr int KP = 32, ES = KP + 1, XS = kRC + 1;
+    __shared__ T sE[2 * KP * ES];
+    __shared__ T sA[(UP ? 2 : 1) * KP * XS];   // up: both children; down: the parent
+    const int K = t.k;
+    const int64_t nrc = (R + kRC - 1) / kRC;
+    const int64_t c = c0 + blockIdx.x / nrc;
+    const int r0 = (int)(blockIdx.x % nrc) * kRC;
+    const int f = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int64_t ch[2] = {2 * c + 1, 2 * c + 2};
+    T* xf = xh + (int64_t)f * t.ncl * K * R;
+    for (int i = tid; i < 2 * K * K; i += 256) {
+        const int s = i / (K * K), q = i % (K * K);
+        sE[s * KP * ES + (q / K) * ES + q % K] = Ed[ch[s] * K * K + q];
+    }
+    constexpr int nin = UP ? 2 : 1;
+    for (int i = tid; i < nin * K * kRC; i += 256) {
+        const int s = i / (K * kRC), al = (i / kRC) % K, rr = i % kRC;
+        const int64_t src = UP ? ch[s] : c;
+        sA[s * KP * XS + al * XS + rr] = r0 + rr < R ? xf[(src * K + al) * R + r0 + rr] : T(0);
+    }
+    __syncthreads();
+    if (UP) {
+        for (int i = tid; i < K * kRC; i += 256) {
+            const int a = i / kRC, rr = i % kRC;
+            if (r0 + rr >= R) continue;
+            T acc = 0;
+            for (int s = 0; s < 2; ++s)
+                for (int b = 0; b < K; ++b) acc += sE[s * KP * ES + b * ES + a] * sA[s * KP * XS + b * XS + rr];
+            xf[(c * K + a) * R + r0 + rr] = acc;
+        }
+    } else {
+        for (int i = tid; i < 2 * K * kRC; i += 256) {
+            const int s = i / (K * kRC), b = (i / kRC) % K, rr = i % kRC;
+            if (r0 + rr >= R) continue;
+            T acc = 0;
+            for (int a = 0; a < K; ++a) acc += sE[s * KP * ES + b * ES + a] * sA[a * XS + rr];
+            xf[(ch[s] * K + b) * R + r0 + rr] += acc;
+        }
+    }
+}
+
 // Y^_S[alpha][r] = sum_{e in far(S)} sum_beta S_e[alpha][beta] X^_src(e)[beta][r],
 // St[f][e][beta][alpha] = S_e[alpha][beta].  One block (two waves, 32 rhs each) per
 // (target cluster, rhs chunk, field); S_e and X^_src(e) are staged in LDS per pair.
@@ -334,14 +382,31 @@ struct Batched {
 };
 
 template <typename T>
+void dense_levels(const H2Tree& t, int F, int R, const T* Ed, T* xh, bool up, hipStream_t st) {
+    const int64_t nrc = (R + kRC - 1) / kRC;
+    for (int i = 0; i < t.L; ++i) {
+        const int lev = up ? t.L - 1 - i : i;   // parents at lev
+        const int64_t c0 = (int64_t(1) << lev) - 1, n = int64_t(1) << lev;
+        if (up)
+            hipLaunchKernelGGL((k_blevel_dense<T, true>), dim3((unsigned)(n * nrc), F), dim3(256), 0, st, t, c0, F, R,
+                               Ed, xh);
+        else
+            hipLaunchKernelGGL((k_blevel_dense<T, false>), dim3((unsigned)(n * nrc), F), dim3(256), 0, st, t, c0, F,
+                               R, Ed, xh);
+    }
+}
+
+template <typename T>
 hipError_t far_batched_t(const ApplyPlan& a, const H2Tree& t, int F, int R, const OpData<T>& od, int dtype,
                          const void* x, T* xh, T* yh, hipStream_t st) {
     const int64_t nrc = (R + kRC - 1) / kRC;
     hipLaunchKernelGGL(k_bup_leaf<T>, dim3((unsigned)(a.nleaf * nrc), F), dim3(128), 0, st, a, t, F, R, od.U, dtype, x,
                        xh);
-    FPDE_DISPATCH_DP(t.dim, t.p, Batched<T>::template up, t, F, R, od.E, xh, st);
+    if (od.Ed) dense_levels<T>(t, F, R, od.Ed, xh, true, st);
+    else FPDE_DISPATCH_DP(t.dim, t.p, Batched<T>::template up, t, F, R, od.E, xh, st);
     hipLaunchKernelGGL(k_bcoupling<T>, dim3((unsigned)(t.ncl * nrc), F), dim3(128), 0, st, t, F, R, od.St, xh, yh);
-    FPDE_DISPATCH_DP(t.dim, t.p, Batched<T>::template down, t, F, R, od.E, yh, st);
+    if (od.Ed) dense_levels<T>(t, F, R, od.Ed, yh, false, st);
+    else FPDE_DISPATCH_DP(t.dim, t.p, Batched<T>::template down, t, F, R, od.E, yh, st);
     return hipGetLastError();
 }
 
@@ -358,7 +423,7 @@ hipError_t apply_batched_t(const ApplyPlan& a, const H2Tree& t, const PanelPlan&
     if (far && (e = far_batched_t<T>(a, t, F, R, od, dtype, x, xh, yh, st)) != hipSuccess) return e;
     if (ev) (void)hipEventRecord(ev[1], st);
     MmFar<T> fo{};
-    if (far) fo = MmFar<T>{yh, od.Upad, t.ncl, t.first_leaf, t.k};
+    if (far) fo = MmFar<T>{yh, od.Upad, t.ncl, t.first_leaf, t.k};   // t.k: the (recompressed) rank
     e = launch_near_mm(a, pp, od.panel, (parts & 4) != 0, csr_val, F, R, dtype, x, y, st, ev ? ev[2] : nullptr,
                        ev ? ev[3] : nullptr, fo);
     if (e != hipSuccess) return e;

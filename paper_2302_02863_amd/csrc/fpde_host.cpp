@@ -20,6 +20,7 @@
 #include "../../include/fpde.h"
 #include "fpde_internal.h"
 #include "fpde_plan.h"
+#include "fpde_recompress.h"
 
 namespace fpde {
 hipError_t launch_basis_n(const H2Tree& t, int64_t N, const int64_t* perm, const int64_t* nc_ptr,
@@ -174,6 +175,12 @@ struct fpde_op {
         float *xhR = nullptr, *yhR = nullptr;  // workspace [F][ncl][K][R]
     } f32;
     bool mixed = false;                    // built with FPDE_PREC_MIXED
+    struct {                               // recompressed far field (opts.recompress_tol > 0)
+        bool on = false;
+        int r = 0;                         // uniform rank
+        double *U = nullptr, *Upad = nullptr, *E = nullptr, *St = nullptr;   // [N][r], [nleaf cap][r],
+        float *U32 = nullptr, *Upad32 = nullptr, *E32 = nullptr, *St32 = nullptr;   // [ncl][r][r], [F][nfar][r][r]
+    } rc;
     // apply workspace
     int64_t ws_R = 0;
     double* d_xt = nullptr;
@@ -238,6 +245,12 @@ void validate(const fpde_mesh* m, int F, const double* s, const double* kap, con
     if (o.leaf_size < 1 || o.leaf_size > 256 || o.leaf_size_rho < 1 || o.leaf_size_rho > 64)
         fail(FPDE_EINVAL, "leaf_size in [1,256], leaf_size_rho in [1,64]");
     if (!(o.eta > 0.0)) fail(FPDE_EINVAL, "eta must be > 0");
+    if (!(o.recompress_tol >= 0.0 && o.recompress_tol < 1.0)) fail(FPDE_EINVAL, "recompress_tol must be in [0,1)");
+    if (o.recompress_tol > 0.0) {
+        int kk = 1;
+        for (int i = 0; i < m->dim; ++i) kk *= o.cheb_p;
+        if (kk > 32) fail(FPDE_EINVAL, "recompression needs a Chebyshev rank p^dim <= 32");
+    }
     if (!(o.a_scale > 0.0)) fail(FPDE_EDOMAIN, "a_scale must be > 0");
     if (m->exterior_radius < 0.0) fail(FPDE_EINVAL, "exterior_radius < 0");
     if (m->exterior_radius > 0.0 && (o.n_theta < 1 || !(o.kappa_exterior > 0.0) ||
@@ -519,6 +532,83 @@ struct Timer {
         return ms;
     }
 };
+
+// Algebraic recompression of the far field (closing remark of Sec. 5.3): host QR and
+// eigen-decompositions of the cluster weights, device weights and coupling projections.
+void recompress(fpde_op& op, hipStream_t st) {
+    auto t0 = std::chrono::steady_clock::now();
+    const HostMesh& m = op.mesh;
+    const int d = m.dim, p = op.opts.cheb_p, K = d == 2 ? p * p : p, F = op.F;
+    const Tree& kt = op.kt;
+    const int64_t N = m.N, ncl = kt.ncl, nfar = (int64_t)op.kfar.size(), nleaf = kt.nleaf();
+    Arena& A = op.arena;
+    std::vector<double> U((size_t)N * K), Es((size_t)ncl * d * p * p);
+    hipck(hipMemcpyAsync(U.data(), op.d_U, U.size() * sizeof(double), hipMemcpyDeviceToHost, st), "U");
+    hipck(hipMemcpyAsync(Es.data(), op.kdev.E, Es.size() * sizeof(double), hipMemcpyDeviceToHost, st), "E");
+    hipck(hipStreamSynchronize(st), "rc download");
+    const RcTree t{N, ncl, kt.first_leaf(), K, kt.beg.data(), kt.end.data()};
+    std::vector<double> Ed;
+    rc_dense_transfers(t, d, p, Es.data(), Ed);
+    RcOrth o;
+    rc_orthogonalize(t, U.data(), Ed, o);
+    // C_s = R_s^T R_s per cluster; H_t on the device
+    const size_t KK = (size_t)K * K;
+    std::vector<double> C((size_t)ncl * KK, 0.0), H((size_t)ncl * KK);
+    for (int64_t c = 0; c < ncl; ++c)
+        for (int i = 0; i < K; ++i)
+            for (int j = 0; j < K; ++j) {
+                double v = 0.0;
+                for (int l = 0; l < K; ++l) v += o.R[c * KK + (size_t)l * K + i] * o.R[c * KK + (size_t)l * K + j];
+                C[c * KK + (size_t)i * K + j] = v;
+            }
+    double* d_Cw = A.upload(C, st);
+    double* d_H = A.alloc<double>((int64_t)ncl * KK);
+    hipck(launch_rc_weights(ncl, K, F, nfar, op.kdev.far_ptr, op.kdev.far_src, op.d_St, d_Cw, d_H, st), "rc weights");
+    hipck(hipMemcpyAsync(H.data(), d_H, H.size() * sizeof(double), hipMemcpyDeviceToHost, st), "H");
+    hipck(hipStreamSynchronize(st), "rc weights sync");
+    RcOut out;
+    const int r = rc_truncate(t, o, H, op.opts.recompress_tol, out);
+    // new bases, transfers and coupling matrices
+    op.rc.U = A.upload(out.U, st);
+    op.rc.E = A.upload(out.E, st);
+    double* d_P = A.upload(out.P, st);
+    std::vector<int64_t> ftgt;
+    ftgt.reserve(nfar);
+    for (auto& pr : op.kfar) ftgt.push_back(pr.first);
+    int64_t* d_ftgt = A.upload(ftgt, st);
+    op.rc.St = A.alloc<double>((int64_t)F * nfar * r * r);
+    hipck(launch_rc_project(ncl, K, r, F, nfar, d_ftgt, op.kdev.far_src, op.d_St, d_P, op.rc.St, st), "rc project");
+    op.rc.Upad = A.alloc<double>(nleaf * op.cap * r);
+    hipck(launch_pad_rows(nleaf, op.cap, r, op.d_leaf_beg, op.rc.U, op.kdev.perm, op.rc.Upad, op.d_perm_pad, st),
+          "rc leaf slots");
+    if (op.mixed) {
+        op.rc.U32 = A.alloc<float>(N * r);
+        op.rc.E32 = A.alloc<float>(ncl * r * r);
+        op.rc.St32 = A.alloc<float>((int64_t)F * nfar * r * r);
+        op.rc.Upad32 = A.alloc<float>(nleaf * op.cap * r);
+        hipck(launch_to_float(N * r, op.rc.U, op.rc.U32, st), "to float");
+        hipck(launch_to_float(ncl * r * r, op.rc.E, op.rc.E32, st), "to float");
+        hipck(launch_to_float((int64_t)F * nfar * r * r, op.rc.St, op.rc.St32, st), "to float");
+        hipck(launch_to_float(nleaf * op.cap * r, op.rc.Upad, op.rc.Upad32, st), "to float");
+    }
+    hipck(hipStreamSynchronize(st), "rc sync");   // host vectors of the uploads end with this scope
+    A.release(d_Cw);
+    A.release(d_H);
+    A.release(d_P);
+    A.release(d_ftgt);
+    op.rc.on = true;
+    op.rc.r = r;
+    int rmin = K;
+    double rsum = 0.0;
+    for (int v : out.ranks) {
+        rmin = std::min(rmin, v);
+        rsum += v;
+    }
+    op.stats.k_rank_rc = r;
+    op.stats.k_rank_rc_min = rmin;
+    op.stats.k_rank_rc_mean = rsum / std::max<size_t>(1, out.ranks.size());
+    op.stats.t_recompress_ms = ms_since(t0);
+}
 
 void build_device(fpde_op& op) {
     const HostMesh& m = op.mesh;
@@ -1115,6 +1205,7 @@ void build_device(fpde_op& op) {
             hipck(launch_to_float((int64_t)F * op.panel_total, op.d_panel, op.f32.panel, st), "to float");
         }
         hipck(hipStreamSynchronize(st), "tickets sync");
+        if (op.opts.recompress_tol > 0.0 && !op.kfar.empty()) recompress(op, st);
     }
     // keep only what apply / load / export need
     // quadrature points and fields stay for the adjoint
@@ -1206,7 +1297,7 @@ ApplyPlan make_apply_plan(const fpde_op& op, const H2Tree& h) {
 // The one-vector kernels run this apply (the operator's precision pr: 0 FP64, 1 FP32 data)
 bool single_path(const fpde_op& op, int pr, int64_t R) {
     const size_t esz = pr ? sizeof(float) : sizeof(double);
-    return R == 1 && op.up[pr].ok && op.panel_max_stride * (int64_t)esz <= 64 * 1024;
+    return R == 1 && !op.rc.on && op.up[pr].ok && op.panel_max_stride * (int64_t)esz <= 64 * 1024;
 }
 
 // Enqueue one apply on s0 (far chain forked to s1 through fk/jn when s1 != s0).
@@ -1251,6 +1342,18 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
     }
     // several right-hand sides: near panels as MFMA GEMMs and the far field as
     // batched products in the operator's precision (FP32 data for a mixed operator)
+    if (op.rc.on) {   // recompressed far field: rank r, dense transfers
+        H2Tree hr = h;
+        hr.k = op.rc.r;
+        if (f32) {
+            OpData<float> od{op.rc.U32, nullptr, op.rc.St32, op.f32.panel, nullptr, nullptr, nullptr, op.rc.Upad32,
+                             op.rc.E32};
+            return launch_apply_batched(a, hr, pp, parts, F, (int)R, cv, od, op.f32.xhR, op.f32.yhR, dtype, x, y, s0,
+                                        ev);
+        }
+        OpData<double> od{op.rc.U, nullptr, op.rc.St, op.d_panel, nullptr, nullptr, nullptr, op.rc.Upad, op.rc.E};
+        return launch_apply_batched(a, hr, pp, parts, F, (int)R, cv, od, op.d_xh, op.d_yh, dtype, x, y, s0, ev);
+    }
     if (batched_fits(h, op.cap, pr)) {
         if (f32) {
             OpData<float> od{op.f32.U,  op.f32.E, op.f32.St, op.f32.panel, nullptr,

@@ -210,6 +210,8 @@ struct OpData {
     T* zh;            // [F][ncl][K] coupling sums z^ per target cluster, zero for the others
     T* zp;            // [F][nchunks][K] partial sums of targets split in several coupling chunks
     const T* Upad;    // [nleaf * cap][K] bases by leaf slot (rows of leaf li at li * cap, zero padded)
+    const T* Ed = nullptr;   // [ncl][K][K] dense transfers (child index, parent index) of
+                             // recompressed bases; nullptr: the Kronecker transfers E
 };
 // One-launch upsweep: leaf-stage subtree depth d0, upper-stage depth ds
 struct UpPlan {

@@ -157,6 +157,9 @@ def test_validation_errors(fp):
     cells[0, 0] = m.n_nodes + 5
     assert _bad(fp, P, mesh=Mesh(2, m.coords, cells, m.cell_interior, m.n_dofs)) == fp._abi.FPDE_EINVAL
     assert _bad(fp, P, cheb_p=20) == fp._abi.FPDE_EINVAL
+    assert _bad(fp, P, recompress_tol=-1e-3) == fp._abi.FPDE_EINVAL
+    assert _bad(fp, P, recompress_tol=1.0) == fp._abi.FPDE_EINVAL
+    assert _bad(fp, P, recompress_tol=1e-3, cheb_p=6) == fp._abi.FPDE_EINVAL   # rank 36 > 32
 
 
 def test_plan_only_rejects_apply(fp):
