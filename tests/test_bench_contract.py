@@ -57,3 +57,30 @@ def test_algorithmic_flops_formula():
     fl, ne = bench.algorithmic_flops_near_mm(FakeOp(), st, F, R)
     assert ne == 9 + 6 + 6 + 4
     assert fl == 2.0 * ne * F * R + 2.0 * 5 * 4 * F * R
+
+
+def test_oracle_only_in_cpu_baseline():
+    """bench.py may run the oracle only in its CPU-baseline leg."""
+    import ast
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    for fn in ast.walk(tree):
+        if not isinstance(fn, ast.FunctionDef):
+            continue
+        for node in ast.walk(fn):
+            mods = []
+            if isinstance(node, ast.ImportFrom):
+                mods = [node.module or ""]
+            elif isinstance(node, ast.Import):
+                mods = [a.name for a in node.names]
+            if any(m == "oracle" or m.startswith("oracle.") for m in mods):
+                assert fn.name == "cpu_baseline", (fn.name, mods)
+
+
+def test_bench_l2_norm_matches_oracle():
+    import numpy as np
+    import bench
+    from fpde_inputs import configs
+    from oracle.solve import l2_norm
+    for P in (configs.bump(3), configs.interval(n_int=16, n_ext=4)):
+        u = np.random.default_rng(0).standard_normal(P.mesh.n_dofs)
+        assert abs(bench.p1_l2_norm(P.mesh, u) - l2_norm(P.mesh, u)) < 1e-13 * l2_norm(P.mesh, u)
