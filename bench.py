@@ -322,7 +322,7 @@ def disk_solve():
     return out
 
 
-def recompression(P, x, y64, tols=(1e-2, 1e-3, 3e-4)):
+def recompression(P, x, y64, tols=(1e-2, 1e-3, 1e-4)):
     """The headline workload's mixed apply with the far field's bases recompressed
     algebraically (closing remark of Sec. 5.3) at several tolerances: cluster ranks,
     far-chain and apply times, build cost and the error against the FP64 apply."""

@@ -51,6 +51,12 @@ typedef enum {
     FPDE_ESTATE = -6    /* call not valid for this operator (e.g. plan-only)     */
 } fpde_status;
 
+/* Operator precision.  FPDE_PREC_MIXED keeps FP32 copies of the near panels, bases,
+ * transfers and coupling matrices next to the FP64 data and applies with them
+ * (products accumulated in FP32, added in FP64): with one right-hand side the rows of
+ * B + M stay FP64; with several, B + M is added into the FP32 near panels and the
+ * whole near field runs as one FP32 MFMA product (about 5e-7 relative to the FP64
+ * apply on the square 256 workload). */
 enum { FPDE_PREC_FP64 = 0, FPDE_PREC_MIXED = 1 };
 enum { FPDE_F64 = 0, FPDE_F32 = 1 };
 

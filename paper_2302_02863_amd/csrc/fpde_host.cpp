@@ -171,6 +171,7 @@ struct fpde_op {
     FarPlan far_plan{};                    // far targets of the one-vector output kernel
     struct {                               // FP32 operator data of a mixed-precision operator
         float *U = nullptr, *E = nullptr, *St = nullptr, *St1 = nullptr, *panel = nullptr, *Upad = nullptr;
+        float* panel_bm = nullptr;   // panels with B + M added (several right-hand sides)
         float *xh = nullptr, *zh = nullptr, *zp = nullptr;   // workspace, one right-hand side
         float *xhR = nullptr, *yhR = nullptr;  // workspace [F][ncl][K][R]
     } f32;
@@ -1058,6 +1059,23 @@ void build_device(fpde_op& op) {
                 A.release(d_esrc);
             }
         }
+        // mixed precision: the panel offset of every entry of B + M (touching pairs are near
+        // pairs, so each lies in its row's panel); the several-rhs FP32 panels hold B + M too
+        std::vector<int64_t> bm_off;
+        if (op.mixed) {
+            bm_off.assign(nnz, -1);
+            std::vector<int64_t> colmap(m.N, -1);
+            for (int64_t li = 0; li < nleaf; ++li) {
+                for (int64_t c = pcols_ptr[li]; c < pcols_ptr[li + 1]; ++c) colmap[pcols[c]] = c - pcols_ptr[li];
+                for (int64_t t = leaf_beg[li]; t < leaf_beg[li + 1]; ++t)
+                    for (int64_t e = op.csr_ptr[t]; e < op.csr_ptr[t + 1]; ++e) {
+                        const int64_t cp = colmap[kt.perm[op.csr_col[e]]];
+                        if (cp < 0) fail(FPDE_EINVAL, "an entry of B + M outside its row's near panel");
+                        bm_off[e] = poff[li] + (t - leaf_beg[li]) * pstride[li] + cp;
+                    }
+                for (int64_t c = pcols_ptr[li]; c < pcols_ptr[li + 1]; ++c) colmap[pcols[c]] = -1;
+            }
+        }
         if (op.opts.flags & FPDE_FLAG_JACOBI) {
             // 1 / diag(A_h): the diagonal entry of B + M plus the leaf self-block entry of the
             // near panel (far blocks never hold a diagonal entry)
@@ -1203,6 +1221,14 @@ void build_device(fpde_op& op) {
             if (op.nfar1 > 0)
                 hipck(launch_to_float((int64_t)F * op.nfar1 * k * k, op.d_St1, op.f32.St1, st), "to float");
             hipck(launch_to_float((int64_t)F * op.panel_total, op.d_panel, op.f32.panel, st), "to float");
+            // K_near + B + M in FP32 for the several-rhs apply (the epilogue's FP64 gathers go away)
+            op.f32.panel_bm = A.alloc<float>((int64_t)F * op.panel_total);
+            hipck(launch_to_float((int64_t)F * op.panel_total, op.d_panel, op.f32.panel_bm, st), "to float");
+            int64_t* d_off = A.upload(bm_off, st);
+            hipck(launch_panel_add_csr(nnz, F, op.panel_total, d_off, op.d_BM, op.d_panel, op.f32.panel_bm, st),
+                  "panel B + M");
+            hipck(hipStreamSynchronize(st), "panel B + M sync");   // bm_off ends with this scope
+            A.release(d_off);
         }
         hipck(hipStreamSynchronize(st), "tickets sync");
         if (op.opts.recompress_tol > 0.0 && !op.kfar.empty()) recompress(op, st);
@@ -1342,11 +1368,21 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
     }
     // several right-hand sides: near panels as MFMA GEMMs and the far field as
     // batched products in the operator's precision (FP32 data for a mixed operator)
+    // FP32 data, several right-hand sides, B + M and the near panels together: the panels
+    // that hold B + M, no row gathers
+    const float* panel32 = op.f32.panel;
+    const int bmk = FPDE_PART_B | FPDE_PART_M | FPDE_PART_KNEAR;
+    if (f32 && op.f32.panel_bm && (parts & bmk) == bmk) {
+        panel32 = op.f32.panel_bm;
+        cv = nullptr;
+        pp.ell_col = nullptr;
+        pp.ell_val = nullptr;
+    }
     if (op.rc.on) {   // recompressed far field: rank r, dense transfers
         H2Tree hr = h;
         hr.k = op.rc.r;
         if (f32) {
-            OpData<float> od{op.rc.U32, nullptr, op.rc.St32, op.f32.panel, nullptr, nullptr, nullptr, op.rc.Upad32,
+            OpData<float> od{op.rc.U32, nullptr, op.rc.St32, panel32, nullptr, nullptr, nullptr, op.rc.Upad32,
                              op.rc.E32};
             return launch_apply_batched(a, hr, pp, parts, F, (int)R, cv, od, op.f32.xhR, op.f32.yhR, dtype, x, y, s0,
                                         ev);
@@ -1356,7 +1392,7 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
     }
     if (batched_fits(h, op.cap, pr)) {
         if (f32) {
-            OpData<float> od{op.f32.U,  op.f32.E, op.f32.St, op.f32.panel, nullptr,
+            OpData<float> od{op.f32.U,  op.f32.E, op.f32.St, panel32, nullptr,
                              nullptr,   nullptr,  op.f32.Upad};
             return launch_apply_batched(a, h, pp, parts, F, (int)R, cv, od, op.f32.xhR, op.f32.yhR, dtype, x, y, s0,
                                         ev);

@@ -280,6 +280,9 @@ hipError_t launch_apply_single(const ApplyPlan& a, const H2Tree& t, const PanelP
                                hipEvent_t* ev);
 
 // leaf-slot copies of the bases and the output indices (fpde_far1.hip)
+// p32[f][off[e]] = p64[f][off[e]] + val[f][e] (B + M added into the FP32 near panels)
+hipError_t launch_panel_add_csr(int64_t nnz, int F, int64_t total, const int64_t* off, const double* val,
+                                const double* p64, float* p32, hipStream_t st);
 hipError_t launch_ell_values(int64_t n, int F, int64_t nnz, const int64_t* src, const double* val, double* out,
                              hipStream_t st);
 hipError_t launch_pad_rows(int64_t nleaf, int64_t cap, int k, const int64_t* leaf_beg, const double* U,

@@ -465,6 +465,25 @@ hipError_t launch_near_mm(const ApplyPlan& a, const PanelPlan& pp, const float* 
     return near_mm_t<float>(a, pp, panel, use_near, csr_val, F, R, dtype, x, y, st, e0, e1, fo);
 }
 
+// FP32 panels with B + M added: p32[f][off[e]] = p64[f][off[e]] + val[f][e] for every
+// nonzero e of B + M (off: its position in its row's panel; the positions are distinct)
+FPDE_KERNEL void k_panel_add_csr(int64_t nnz, int F, int64_t total, const int64_t* off, const double* val,
+                                 const double* p64, float* p32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)F * nnz) return;
+    const int64_t f = i / nnz, e = i % nnz;
+    const int64_t o = f * total + off[e];
+    p32[o] = (float)(p64[o] + val[i]);
+}
+
+hipError_t launch_panel_add_csr(int64_t nnz, int F, int64_t total, const int64_t* off, const double* val,
+                                const double* p64, float* p32, hipStream_t st) {
+    const int64_t n = (int64_t)F * nnz;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_panel_add_csr, dim3(grid1(n)), dim3(256), 0, st, nnz, F, total, off, val, p64, p32);
+    return hipGetLastError();
+}
+
 // FP32 copy of FP64 operator data (mixed precision)
 FPDE_KERNEL void k_to_float(int64_t n, const double* src, float* dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
