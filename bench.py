@@ -176,6 +176,9 @@ def headline(steps, warmup):
     yk64 = ops["mixed"].apply(x, parts=fp.PART_KFAR | fp.PART_FP64)
     ynear = ops["mixed"].apply(x, parts=fp.PART_KNEAR)
     ynear64 = ops["mixed"].apply(x, parts=fp.PART_KNEAR | fp.PART_FP64)
+    nb = fp.PART_KNEAR | fp.PART_B | fp.PART_M   # with several rhs, B + M ride in the FP32 panels
+    ynb = ops["mixed"].apply(x, parts=nb)
+    ynb64 = ops["mixed"].apply(x, parts=nb | fp.PART_FP64)
     torch.cuda.synchronize()
     yref = ys["fp64"].double()
     yn = torch.linalg.vector_norm(yref, dim=1)
@@ -184,7 +187,9 @@ def headline(steps, warmup):
         "near_panel_err_over_y": float((torch.linalg.vector_norm(ynear.double() - ynear64.double(), dim=1)
                                         / yn).max()),
         "far_part_norm_over_y": float((torch.linalg.vector_norm(yk64.double(), dim=1) / yn).max()),
-        "near_panel_norm_over_y": float((torch.linalg.vector_norm(ynear64.double(), dim=1) / yn).max())}
+        "near_panel_norm_over_y": float((torch.linalg.vector_norm(ynear64.double(), dim=1) / yn).max()),
+        "near_panels_with_b_m_err_over_y": float((torch.linalg.vector_norm(ynb.double() - ynb64.double(), dim=1)
+                                                  / yn).max())}
     out["_y_fp64"] = ys["fp64"]
     return P, x, ops, out
 
