@@ -144,6 +144,18 @@ __global__ __launch_bounds__(256) void k_blevel(H2Tree t, int64_t c0, int F, int
         const int64_t src = UP ? ch[s < 2 ? s : 1] : c;
         va[m] = (i < nin * K * kRC && r0 + rr < R) ? xf[(src * K + al) * R + r0 + rr] : T(0);
     }
+    // down: the children's current coefficients, read now so that the final
+    // read-modify-write costs no round trip after the sums
+    constexpr int NO = UP ? 1 : (2 * K * kRC + 255) / 256;
+    T vo[NO];
+    if constexpr (!UP) {
+#pragma unroll
+        for (int m = 0; m < NO; ++m) {
+            const int i = tid + 256 * m;
+            const int s = i / (K * kRC), q = (i / kRC) % K, rr = i % kRC;
+            vo[m] = (i < 2 * K * kRC && r0 + rr < R) ? xf[(ch[s < 2 ? s : 1] * K + q) * R + r0 + rr] : T(0);
+        }
+    }
 #pragma unroll
     for (int m = 0; m < NE; ++m)
         if (tid + 256 * m < 2 * EP) sE[tid + 256 * m] = ve[m];
@@ -165,7 +177,10 @@ __global__ __launch_bounds__(256) void k_blevel(H2Tree t, int64_t c0, int F, int
     }
     __syncthreads();
     // second dimension (2D), then store
-    for (int i = tid; i < (UP ? 1 : 2) * K * kRC; i += blockDim.x) {
+#pragma unroll
+    for (int m = 0; m < (UP ? (K * kRC + 255) / 256 : NO); ++m) {
+        const int i = tid + 256 * m;
+        if (i >= (UP ? 1 : 2) * K * kRC) break;
         const int s = i / (K * kRC), q = (i / kRC) % K, rr = i % kRC;
         if (r0 + rr >= R) continue;
         const int i0 = q % P, i1 = q / P;
@@ -181,8 +196,8 @@ __global__ __launch_bounds__(256) void k_blevel(H2Tree t, int64_t c0, int F, int
                     acc += (UP ? Ed[m * P + i1] : Ed[i1 * P + m]) * sT[(s2 * K + i0 + P * m) * kRC + rr];
             }
         }
-        if (UP) xf[(c * K + q) * R + r0 + rr] = acc;
-        else xf[(ch[s] * K + q) * R + r0 + rr] += acc;
+        if constexpr (UP) xf[(c * K + q) * R + r0 + rr] = acc;
+        else xf[(ch[s] * K + q) * R + r0 + rr] = vo[m] + acc;
     }
 }
 

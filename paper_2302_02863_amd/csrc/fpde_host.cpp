@@ -1370,13 +1370,16 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
     // batched products in the operator's precision (FP32 data for a mixed operator)
     // FP32 data, several right-hand sides, B + M and the near panels together: the panels
     // that hold B + M, no row gathers
+    // (the several-rhs batched kernels only; the K > 32 fallbacks below read the plain panels)
     const float* panel32 = op.f32.panel;
+    const double* cvb = cv;
+    PanelPlan ppb = pp;
     const int bmk = FPDE_PART_B | FPDE_PART_M | FPDE_PART_KNEAR;
     if (f32 && op.f32.panel_bm && (parts & bmk) == bmk) {
         panel32 = op.f32.panel_bm;
-        cv = nullptr;
-        pp.ell_col = nullptr;
-        pp.ell_val = nullptr;
+        cvb = nullptr;
+        ppb.ell_col = nullptr;
+        ppb.ell_val = nullptr;
     }
     if (op.rc.on) {   // recompressed far field: rank r, dense transfers
         H2Tree hr = h;
@@ -1384,21 +1387,21 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
         if (f32) {
             OpData<float> od{op.rc.U32, nullptr, op.rc.St32, panel32, nullptr, nullptr, nullptr, op.rc.Upad32,
                              op.rc.E32};
-            return launch_apply_batched(a, hr, pp, parts, F, (int)R, cv, od, op.f32.xhR, op.f32.yhR, dtype, x, y, s0,
+            return launch_apply_batched(a, hr, ppb, parts, F, (int)R, cvb, od, op.f32.xhR, op.f32.yhR, dtype, x, y, s0,
                                         ev);
         }
         OpData<double> od{op.rc.U, nullptr, op.rc.St, op.d_panel, nullptr, nullptr, nullptr, op.rc.Upad, op.rc.E};
-        return launch_apply_batched(a, hr, pp, parts, F, (int)R, cv, od, op.d_xh, op.d_yh, dtype, x, y, s0, ev);
+        return launch_apply_batched(a, hr, ppb, parts, F, (int)R, cvb, od, op.d_xh, op.d_yh, dtype, x, y, s0, ev);
     }
     if (batched_fits(h, op.cap, pr)) {
         if (f32) {
             OpData<float> od{op.f32.U,  op.f32.E, op.f32.St, panel32, nullptr,
                              nullptr,   nullptr,  op.f32.Upad};
-            return launch_apply_batched(a, h, pp, parts, F, (int)R, cv, od, op.f32.xhR, op.f32.yhR, dtype, x, y, s0,
+            return launch_apply_batched(a, h, ppb, parts, F, (int)R, cvb, od, op.f32.xhR, op.f32.yhR, dtype, x, y, s0,
                                         ev);
         }
         OpData<double> od{op.d_U, op.kdev.E, op.d_St, op.d_panel, nullptr, nullptr, nullptr, op.d_Upad};
-        return launch_apply_batched(a, h, pp, parts, F, (int)R, cv, od, op.d_xh, op.d_yh, dtype, x, y, s0, ev);
+        return launch_apply_batched(a, h, ppb, parts, F, (int)R, cvb, od, op.d_xh, op.d_yh, dtype, x, y, s0, ev);
     }
     // otherwise (K > 32): FP64 far field with LDS-resident subtrees, or per-level sweeps
     const void* panel = f32 ? (const void*)op.f32.panel : (const void*)op.d_panel;
