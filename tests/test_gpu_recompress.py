@@ -149,3 +149,24 @@ def test_batched256_recompressed_mixed_within_budget():
               flush=True)
         op.close()
         assert st["k_rank_rc"] <= rmax and err < emax, (tol, st["k_rank_rc"], err)
+
+
+def test_interval_recompressed():
+    """1D (rank p = 8): the recompressed operator against the oracle's H2 matrix."""
+    import paper_2302_02863_amd as fp
+    P = configs.interval(n_int=256, n_ext=32, leaf_size=8, leaf_size_rho=16, cheb_p=8)
+    m = P.mesh
+    ref = assemble_h2(m, P.s[0], P.kappa[0], P.opts)
+    A = ref["B"] + ref["K"] + ref["M"]
+    rng = np.random.default_rng(41)
+    x = rng.standard_normal((1, m.n_dofs, 3))
+    for tol in (1e-3, 1e-8):
+        op = _op(P, recompress_tol=tol)
+        st = op.stats()
+        assert st["k_far"] > 0 and st["k_rank"] == 8
+        y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy()[0]
+        op.close()
+        yr = A @ x[0]
+        err = (np.linalg.norm(y - yr, axis=0) / np.linalg.norm(yr, axis=0)).max()
+        print(f"[recompress] interval 256, tol {tol:.0e}: rank {st['k_rank_rc']} of 8, rel err {err:.2e}", flush=True)
+        assert st["k_rank_rc"] <= 8 and err < 10 * tol
