@@ -1,5 +1,6 @@
 """Full-size parity on sampled rows that the oracle computes one by one
-(oracle.sampled): the 128 x 128 square workload (16129 dofs, 131072 cells) in the
+(oracle.sampled, on CPU worker processes): the 128 x 128 square workload (16129 dofs,
+131072 cells; 64 random rows and 32 next to the interface) in the
 launch configuration the benchmark times, the batched 256 x 256 workload
 (16 fields x 64 right-hand sides) and the 512 x 512 disk workload (261121 dofs),
 at 1e-10 of the output's max norm (1e-6 for the mixed-precision operator)."""
@@ -10,7 +11,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from fpde_inputs import configs  # noqa: E402
-from oracle.sampled import SampledOracle  # noqa: E402
+from sampled_pool import sampled_rows  # noqa: E402
 
 TOL = 1e-10
 
@@ -29,14 +30,14 @@ def test_square128_sampled_rows():
     y = y.cpu().numpy()[0, :, 0]
     parts = {k: v.cpu().numpy()[0, :, 0] for k, v in parts.items()}
     rng = np.random.default_rng(17)
-    # random rows plus rows next to the interface (first/last grid lines of the interior)
-    rows = list(rng.choice(m.n_dofs, size=4, replace=False))
+    # 64 random rows plus 32 rows next to the interface (first/last grid lines of the interior)
+    rows = [int(i) for i in rng.choice(m.n_dofs, size=64, replace=False)]
     xy = m.coords[:, :m.n_dofs]
     h = m.info["h"]
     near_bdry = np.flatnonzero((xy.min(axis=0) < 1.6 * h) | (xy.max(axis=0) > 1 - 1.6 * h))
-    rows += list(rng.choice(near_bdry, size=2, replace=False))
-    so = SampledOracle(m, P.s[0], P.kappa[0], P.opts)
-    out = so.row_apply(rows, P.x[0, :, 0])
+    rows += [int(i) for i in rng.choice(near_bdry, size=32, replace=False)]
+    print(f"[fullsize] square 128: oracle rows {len(rows)} on worker processes", flush=True)
+    out = {k: v[0] for k, v in sampled_rows("square", {"n": 128}, 0, rows).items()}
     scale = np.abs(y).max()
     for key in ("B", "M", "K"):
         err = np.abs(parts[key][rows] - out[key]).max() / scale
@@ -50,8 +51,9 @@ def test_square128_sampled_rows():
 def test_batched256_sampled_rows():
     """The batched workload at full size (256 x 256 squares, 65025 dofs, 16 order fields
     x 64 right-hand sides, values rounded to FP32): FP64 operator at 1e-10 and the
-    mixed-precision operator at 1e-6 of the output's max norm on sampled (field, rhs,
-    row) entries, with FP64 vectors; FP32 vectors agree with them to FP32 rounding."""
+    mixed-precision operator at 1e-6 of the output's max norm on sampled entries (fields
+    0 and 15, 16 rows x 2 right-hand sides each), with FP64 vectors; FP32 vectors agree
+    with them to FP32 rounding."""
     import paper_2302_02863_amd as fp
     P = configs.batched(256, n_fields=16, nrhs=64)
     m = P.mesh
@@ -71,13 +73,14 @@ def test_batched256_sampled_rows():
         op.close()
     rng = np.random.default_rng(23)
     for f in (0, 15):
-        so = SampledOracle(m, P.s[f], P.kappa[f], P.opts)
-        rows = list(rng.choice(m.n_dofs, size=2, replace=False))
-        for r in rng.choice(64, size=2, replace=False):
-            out = so.row_apply(rows, P.x[f, :, r])
+        rows = [int(i) for i in rng.choice(m.n_dofs, size=16, replace=False)]
+        vecs = [int(v) for v in rng.choice(64, size=2, replace=False)]
+        print(f"[fullsize] batched field {f}: oracle rows {len(rows)} x rhs {vecs} on worker processes", flush=True)
+        out = sampled_rows("batched", {"n": 256, "n_fields": 16, "nrhs": 64}, f, rows, vecs)["total"]
+        for j, r in enumerate(vecs):
             for precision, tol in (("fp64", TOL), ("mixed", 1e-6)):
                 y = ys[precision][f, :, r]
-                err = np.abs(y[rows] - out["total"]).max() / np.abs(y).max()
+                err = np.abs(y[rows] - out[j]).max() / np.abs(y).max()
                 print(f"[fullsize] batched {precision} field {f} rhs {r}: {err:.2e}", flush=True)
                 assert err < tol, (precision, f, r, err)
 
@@ -116,10 +119,10 @@ def test_disk512_sampled_rows_mixed_and_solve():
     assert d < 1e-8
     rng = np.random.default_rng(29)
     radius = np.hypot(m.coords[0, :m.n_dofs], m.coords[1, :m.n_dofs])
-    rows = [int(rng.integers(m.n_dofs)), int(rng.choice(np.flatnonzero(radius > 1 - 1.6 * m.info["h"])))]
-    print(f"[fullsize] disk oracle rows {rows}", flush=True)
-    so = SampledOracle(m, P.s[0], P.kappa[0], P.opts)
-    out = so.row_apply(rows, P.x[0, :, 0])
+    rows = [int(i) for i in rng.choice(m.n_dofs, size=12, replace=False)]
+    rows += [int(i) for i in rng.choice(np.flatnonzero(radius > 1 - 1.6 * m.info["h"]), size=4, replace=False)]
+    print(f"[fullsize] disk oracle rows {len(rows)} on worker processes", flush=True)
+    out = {k: v[0] for k, v in sampled_rows("disk", {"n": 512}, 0, rows).items()}
     y = ys["fp64"]
     err = np.abs(y[rows] - out["total"]).max() / np.abs(y).max()
     print(f"[fullsize] disk sampled rows: {err:.2e}", flush=True)
@@ -156,13 +159,10 @@ def test_square128_graded_exterior():
     torch.cuda.synchronize()
     y = y.cpu().numpy()[0, :, 0]
     rng = np.random.default_rng(23)
-    rows = list(rng.choice(m.n_dofs, size=3, replace=False))
-    so = SampledOracle(m, G.s[0], G.kappa[0], G.opts)
-    ref = []
-    for r in rows:
-        ref.append(so.row_apply([r], G.x[0, :, 0])["total"][0])
-        print(f"[fullsize] graded: oracle row {r} done", flush=True)
-    err = np.abs(y[rows] - np.array(ref)).max() / np.abs(y).max()
+    rows = [int(i) for i in rng.choice(m.n_dofs, size=24, replace=False)]
+    print(f"[fullsize] graded: oracle rows {len(rows)} on worker processes", flush=True)
+    ref = sampled_rows("square", {"n": 128, "graded": 1.25}, 0, rows)["total"][0]
+    err = np.abs(y[rows] - ref).max() / np.abs(y).max()
     print(f"[fullsize] graded sampled rows: {err:.2e}", flush=True)
     assert err < TOL
     d = np.linalg.norm(sols["graded"] - sols["uniform"]) / np.linalg.norm(sols["uniform"])
