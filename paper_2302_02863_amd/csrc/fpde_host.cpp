@@ -1660,7 +1660,7 @@ void ensure_solve_ws(fpde_op& op, int64_t R) {
                     (void*)op.cg.n_active, (void*)op.d_hist_a, (void*)op.d_hist_b})
         if (q) A.release(q);
     const int64_t n = (int64_t)op.F * op.mesh.N * R, S = (int64_t)op.F * R;
-    const int64_t nb = cg_row_blocks(op.mesh.N, (int)R);
+    const int64_t nb = cg_row_blocks(op.mesh.N, (int)R, op.F);
     op.d_r = A.alloc<double>(n);
     op.d_p = A.alloc<double>(n);
     op.d_Ap = A.alloc<double>(n);
@@ -1697,7 +1697,7 @@ bool cg_fusable(const fpde_op& op, bool mixed, int64_t R) {
 }
 
 hipError_t enqueue_cg_iteration(fpde_op& op, bool mixed, int64_t R, hipStream_t s0, hipStream_t s1) {
-    const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
+    const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R, op.F)};
     double* pc3 = op.d_dinv ? op.d_part3 : nullptr;   // r . r partials of the preconditioned iteration
     const int parts = mixed ? FPDE_PART_ALL : (FPDE_PART_ALL | FPDE_PART_FP64);
     hipError_t e;
@@ -1731,7 +1731,7 @@ hipError_t enqueue_cg_iteration(fpde_op& op, bool mixed, int64_t R, hipStream_t 
 // per-system iteration count; *breakdown is set if a system lost positivity.
 int cg_run(fpde_op& op, bool mixed, int64_t R, double tau_in, double rtol, int maxit, hipStream_t st,
            bool* breakdown, double* cond) {
-    const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
+    const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R, op.F)};
     const int64_t S = (int64_t)op.F * R;
     op.cg.hist_a = cond ? op.d_hist_a : nullptr;   // the Lanczos coefficients, when an estimate is asked
     op.cg.hist_b = cond ? op.d_hist_b : nullptr;
@@ -1786,7 +1786,7 @@ int cg_run(fpde_op& op, bool mixed, int64_t R, double tau_in, double rtol, int m
 
 // rout = b - A_fp64 u, per-system |rout|^2 (d_rro) and |b|^2 (d_bb); returns max_s |rout_s| / |b_s|
 double outer_residual(fpde_op& op, const double* b, double* u, int64_t R, hipStream_t st) {
-    const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R)};
+    const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R, op.F)};
     const int64_t S = (int64_t)op.F * R;
     apply_impl(op, FPDE_PART_ALL | FPDE_PART_FP64, FPDE_F64, u, op.d_Ap, R, st);
     hipck(launch_cg_rowblock(CG_RESID, dm, op.d_Ap, b, nullptr, op.d_rout, nullptr, op.d_part1, op.d_part2, nullptr,

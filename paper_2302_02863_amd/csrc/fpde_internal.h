@@ -374,7 +374,7 @@ struct CgScalars {  // device arrays of S entries (n_active: one int)
     int hist_cap = 0;
 };
 enum { CG_DOT = 0, CG_UPDATE_UR = 1, CG_RESID = 2, CG_COPY_RP = 3, CG_UPDATE_P = 4 };
-int64_t cg_row_blocks(int64_t N, int R);
+int64_t cg_row_blocks(int64_t N, int R, int F);
 // One row-block pass (see fpde_solve.hip): CG_DOT part1 = a.b; CG_UPDATE_UR u += alpha a,
 // r -= alpha b, part1 = r.r; CG_UPDATE_P p = a + beta p; CG_RESID r = b - a, part1 = r.r,
 // part2 = b.b; CG_COPY_RP r = p = b, u = 0, part1 = b.b.  part_in: the partials the

@@ -270,13 +270,16 @@ unsigned grid_of(int64_t n) {
 
 }  // namespace
 
-int64_t cg_row_blocks(int64_t N, int R) {
-    // one element per thread: N * R / 256 blocks, between 1 and 1024 per field
-    // (the partials of a pass are summed by every block of the next one)
+int64_t cg_row_blocks(int64_t N, int R, int F) {
+    // one element per thread, N * R / 256 blocks per field, but about 2048 blocks in all:
+    // every block of a pass sums all the partials of the previous one (F * nb^2 * R
+    // loads), so many fields or right-hand sides take fewer, larger blocks
     int64_t nb = (N * (int64_t)R + kBS - 1) / kBS;
-    if (nb < 1) nb = 1;
+    const int64_t cap = F > 0 ? (2048 + F - 1) / F : 2048;
+    if (nb > cap) nb = cap;
     if (nb > 1024) nb = 1024;
     if (nb > N) nb = N;
+    if (nb < 1) nb = 1;
     return nb;
 }
 
