@@ -1696,6 +1696,12 @@ bool cg_fusable(const fpde_op& op, bool mixed, int64_t R) {
     return single_path(op, mixed ? 1 : 0, R) && op.far_plan.ntgt > 0 && op.d_part_far;
 }
 
+// The inner CG of a mixed-precision solve keeps its vectors (r, p, Ap, d) in FP32, half
+// the bytes of every pass and of the apply's x and y; it only has to reduce its residual
+// by sqrt(rtol) >= 1e-7 (mixed_inner_tol), and the refinement's FP64 residual corrects
+// the rest.  The one-vector path with the fused dot product keeps FP64 vectors.
+bool cg_vec32(const fpde_op& op, bool mixed, int64_t R) { return mixed && !cg_fusable(op, mixed, R); }
+
 hipError_t enqueue_cg_iteration(fpde_op& op, bool mixed, int64_t R, hipStream_t s0, hipStream_t s1) {
     const CgDims dm{op.mesh.N, (int)R, op.F, cg_row_blocks(op.mesh.N, (int)R, op.F)};
     double* pc3 = op.d_dinv ? op.d_part3 : nullptr;   // r . r partials of the preconditioned iteration
@@ -1714,16 +1720,18 @@ hipError_t enqueue_cg_iteration(fpde_op& op, bool mixed, int64_t R, hipStream_t 
         return launch_cg_rowblock(CG_UPDATE_P, dm, op.d_r, nullptr, nullptr, nullptr, op.d_p, nullptr, nullptr,
                                   op.d_part2, op.cg, s0, -1, op.d_dinv, pc3);
     }
-    e = enqueue_apply(op, parts, FPDE_F64, op.d_p, op.d_Ap, R, s0, s1, op.ev_fork, op.ev_join, nullptr);
+    const bool v32 = cg_vec32(op, mixed, R);
+    e = enqueue_apply(op, parts, v32 ? FPDE_F32 : FPDE_F64, op.d_p, op.d_Ap, R, s0, s1, op.ev_fork, op.ev_join,
+                      nullptr);
     if (e != hipSuccess) return e;
     if ((e = launch_cg_rowblock(CG_DOT, dm, op.d_p, op.d_Ap, nullptr, nullptr, nullptr, op.d_part1, nullptr, nullptr,
-                                op.cg, s0)) != hipSuccess)
+                                op.cg, s0, -1, nullptr, nullptr, v32)) != hipSuccess)
         return e;
     if ((e = launch_cg_rowblock(CG_UPDATE_UR, dm, op.d_p, op.d_Ap, op.d_d, op.d_r, nullptr, op.d_part2, pc3,
-                                op.d_part1, op.cg, s0, -1, op.d_dinv)) != hipSuccess)
+                                op.d_part1, op.cg, s0, -1, op.d_dinv, nullptr, v32)) != hipSuccess)
         return e;
     return launch_cg_rowblock(CG_UPDATE_P, dm, op.d_r, nullptr, nullptr, nullptr, op.d_p, nullptr, nullptr, op.d_part2,
-                              op.cg, s0, -1, op.d_dinv, pc3);
+                              op.cg, s0, -1, op.d_dinv, pc3, v32);
 }
 
 // CG on A d = rout from d = 0 until |r_s| <= max(tau_in |rout_s|, rtol_abs_s) for every
@@ -1737,7 +1745,9 @@ int cg_run(fpde_op& op, bool mixed, int64_t R, double tau_in, double rtol, int m
     op.cg.hist_b = cond ? op.d_hist_b : nullptr;
     op.cg.hist_cap = cond ? kHist : 0;
     hipck(launch_cg_rowblock(CG_COPY_RP, dm, nullptr, op.d_rout, op.d_d, op.d_r, op.d_p, op.d_part1,
-                             op.d_dinv ? op.d_part3 : nullptr, nullptr, op.cg, st, -1, op.d_dinv), "cg start");
+                             op.d_dinv ? op.d_part3 : nullptr, nullptr, op.cg, st, -1, op.d_dinv, nullptr,
+                             cg_vec32(op, mixed, R)),
+          "cg start");
     hipck(launch_cg_start(dm, op.d_part1, op.d_bb, tau_in, rtol, op.cg, st, op.d_dinv ? op.d_part3 : nullptr),
           "cg start");
     hipck(hipMemcpyAsync(op.h_nact, op.cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
@@ -1828,7 +1838,7 @@ void solve_impl(fpde_op& op, const double* b, double* u, int64_t R, double rtol,
         bool bd = false;
         total += cg_run(op, op.mixed, R, tau, 0.5 * rtol, maxit - total, st, &bd, outer == 0 ? &cond : nullptr);
         breakdown = breakdown || bd;
-        hipck(launch_vec_add(n, op.d_d, u, st), "update");
+        hipck(launch_vec_add(n, op.d_d, u, st, cg_vec32(op, op.mixed, R)), "update");
         worst = outer_residual(op, b, u, R, st);
         ++outer;
         if (worst < 0.5 * best) {

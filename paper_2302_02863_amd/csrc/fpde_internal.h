@@ -383,10 +383,12 @@ int64_t cg_row_blocks(int64_t N, int R, int F);
 // dinv [F][N] (null: no preconditioner): the Jacobi preconditioner z = D^-1 r.  With it
 // CG_UPDATE_UR also stores r . r in part2 and CG_UPDATE_P stops on the r . r partials part_in2;
 // CG_COPY_RP stores b . z in part1 and b . b in part2.
-hipError_t launch_cg_rowblock(int op, const CgDims& d, const double* a, const double* b, double* u, double* r,
-                              double* p, double* part1, double* part2, const double* part_in, const CgScalars& c,
-                              hipStream_t st, int64_t nb_in = -1, const double* dinv = nullptr,
-                              const double* part_in2 = nullptr);
+// v32: the CG vectors (a, b, u, r, p; not CG_COPY_RP's b) are FP32, the inner CG of a
+// mixed-precision solve; CG_RESID always works on FP64 vectors.
+hipError_t launch_cg_rowblock(int op, const CgDims& d, const void* a, const void* b, void* u, void* r, void* p,
+                              double* part1, double* part2, const double* part_in, const CgScalars& c, hipStream_t st,
+                              int64_t nb_in = -1, const double* dinv = nullptr, const double* part_in2 = nullptr,
+                              bool v32 = false);
 // part: b . z partials (rr of the first iteration); part_rr: b . b partials for the stopping
 // threshold (null: part)
 hipError_t launch_cg_start(const CgDims& d, const double* part, const double* bb0, double tau_in, double rtol,
@@ -397,7 +399,8 @@ hipError_t launch_jacobi_diag(int64_t N, int F, int64_t nnz, const int64_t* bm_i
                               const int64_t* p_idx, const double* panel, double* dinv, hipStream_t st);
 hipError_t launch_cg_sum2(const CgDims& d, const double* part1, const double* part2, double* o1, double* o2,
                           hipStream_t st);
-hipError_t launch_vec_add(int64_t n, const double* d, double* u, hipStream_t st);
+// u += d (d FP64, or FP32 with v32)
+hipError_t launch_vec_add(int64_t n, const void* d, double* u, hipStream_t st, bool v32 = false);
 
 // ---------------------------------------------------------------- static scratch (fpde_noalloc.hip)
 

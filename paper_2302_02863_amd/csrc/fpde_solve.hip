@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fpde_internal.h"
 
@@ -76,14 +77,25 @@ __device__ inline double sum_parts(const double* part, int64_t nb, int R, int64_
 //   part2 = r . r; CG_UPDATE_P p = z + beta p with beta from the r . z partials and the
 //   stopping test on the r . r partials part_in2; CG_COPY_RP p = D^-1 b, part1 = b . z,
 //   part2 = b . b.  The Lanczos coefficients alpha_k, beta_k are recorded when asked.
-template <int OP>
-__global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb, const double* __restrict__ a,
-                                                  const double* __restrict__ b, double* __restrict__ u,
-                                                  double* __restrict__ r, double* __restrict__ p,
+//   V: the type of the CG vectors (FP64, or FP32 for the inner CG of a mixed-precision
+//   solve); CG_RESID works on the outer FP64 vectors and CG_COPY_RP reads the FP64 outer
+//   residual.  Values are read into FP64 and the dot products use the stored values.
+template <int OP, typename V>
+__global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb, const void* __restrict__ a_,
+                                                  const void* __restrict__ b_, void* __restrict__ u_,
+                                                  void* __restrict__ r_, void* __restrict__ p_,
                                                   double* __restrict__ part1, double* __restrict__ part2,
                                                   const double* __restrict__ part_in, int64_t nb_in, CgScalars c,
                                                   const double* __restrict__ dinv,
                                                   const double* __restrict__ part_in2) {
+    using TA = std::conditional_t<OP == CG_RESID, double, V>;
+    using TB = std::conditional_t<OP == CG_RESID || OP == CG_COPY_RP, double, V>;
+    using TR = std::conditional_t<OP == CG_RESID, double, V>;
+    const TA* a = (const TA*)a_;
+    const TB* b = (const TB*)b_;
+    V* u = (V*)u_;
+    TR* r = (TR*)r_;
+    V* p = (V*)p_;
     __shared__ double red[kBS];
     __shared__ double coef[kBS];
     __shared__ int nact;
@@ -178,11 +190,11 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
             for (int64_t row = r0 + rl; row < r1; row += nrl) {
                 const int64_t i = ((int64_t)f * N + row) * R + col;
                 if (OP == CG_DOT) {
-                    acc1 += a[i] * b[i];
+                    acc1 += (double)a[i] * (double)b[i];
                 } else if (OP == CG_UPDATE_UR) {
-                    u[i] += cf * a[i];
-                    const double rn = r[i] - cf * b[i];
-                    r[i] = rn;
+                    u[i] = (V)((double)u[i] + cf * (double)a[i]);
+                    const double rn = (double)(V)((double)r[i] - cf * (double)b[i]);   // as stored
+                    r[i] = (V)rn;
                     if (dinv) {
                         acc1 += rn * rn * dinv[(int64_t)f * N + row];
                         acc2 += rn * rn;
@@ -190,19 +202,20 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
                         acc1 += rn * rn;
                     }
                 } else if (OP == CG_UPDATE_P) {
-                    p[i] = (dinv ? a[i] * dinv[(int64_t)f * N + row] : a[i]) + cf * p[i];
+                    const double av = (double)a[i];
+                    p[i] = (V)((dinv ? av * dinv[(int64_t)f * N + row] : av) + cf * (double)p[i]);
                 } else if (OP == CG_RESID) {
                     const double rn = b[i] - a[i];
                     r[i] = rn;
                     acc1 += rn * rn;
                     acc2 += b[i] * b[i];
                 } else {
-                    const double bv = b[i];
-                    const double zv = dinv ? bv * dinv[(int64_t)f * N + row] : bv;
-                    r[i] = bv;
-                    p[i] = zv;
-                    u[i] = 0.0;
-                    acc1 += bv * zv;
+                    const double bv = (double)(V)b[i];   // as stored in r
+                    const double di = dinv ? dinv[(int64_t)f * N + row] : 1.0;
+                    r[i] = (V)bv;
+                    p[i] = (V)(bv * di);
+                    u[i] = (V)0;
+                    acc1 += bv * (double)(V)(bv * di);
                     acc2 += bv * bv;
                 }
             }
@@ -258,9 +271,10 @@ __global__ __launch_bounds__(kBS) void k_sum2(int64_t S, int64_t nb, int R, cons
     if (o2) o2[s] = sum_parts(part2, nb, R, s);
 }
 
-__global__ __launch_bounds__(kBS) void k_add(int64_t n, const double* d, double* u) {
+template <typename V>
+__global__ __launch_bounds__(kBS) void k_add(int64_t n, const V* d, double* u) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) u[i] += d[i];
+    if (i < n) u[i] += (double)d[i];
 }
 
 unsigned grid_of(int64_t n) {
@@ -283,15 +297,22 @@ int64_t cg_row_blocks(int64_t N, int R, int F) {
     return nb;
 }
 
-hipError_t launch_cg_rowblock(int op, const CgDims& d, const double* a, const double* b, double* u, double* r,
-                              double* p, double* part1, double* part2, const double* part_in, const CgScalars& c,
-                              hipStream_t st, int64_t nb_in, const double* dinv, const double* part_in2) {
+hipError_t launch_cg_rowblock(int op, const CgDims& d, const void* a, const void* b, void* u, void* r, void* p,
+                              double* part1, double* part2, const double* part_in, const CgScalars& c, hipStream_t st,
+                              int64_t nb_in, const double* dinv, const double* part_in2, bool v32) {
     const int64_t rpb = (d.N + d.nb - 1) / d.nb;
     if (nb_in < 0) nb_in = d.nb;
     const dim3 g((unsigned)d.nb, (unsigned)d.F);
+    if (v32 && op == CG_RESID) return hipErrorInvalidValue;   // the outer residual is FP64
 #define FPDE_ROWBLOCK(OPV)                                                                                          \
-    hipLaunchKernelGGL(k_rowblock<OPV>, g, dim3(kBS), 0, st, d.N, d.R, rpb, a, b, u, r, p, part1, part2, part_in, \
-                       nb_in, c, dinv, part_in2)
+    do {                                                                                                            \
+        if (v32)                                                                                                    \
+            hipLaunchKernelGGL((k_rowblock<OPV, float>), g, dim3(kBS), 0, st, d.N, d.R, rpb, a, b, u, r, p, part1,  \
+                               part2, part_in, nb_in, c, dinv, part_in2);                                          \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_rowblock<OPV, double>), g, dim3(kBS), 0, st, d.N, d.R, rpb, a, b, u, r, p, part1, \
+                               part2, part_in, nb_in, c, dinv, part_in2);                                          \
+    } while (0)
     switch (op) {
         case CG_DOT: FPDE_ROWBLOCK(CG_DOT); break;
         case CG_UPDATE_UR: FPDE_ROWBLOCK(CG_UPDATE_UR); break;
@@ -337,8 +358,9 @@ hipError_t launch_jacobi_diag(int64_t N, int F, int64_t nnz, const int64_t* bm_i
     return hipGetLastError();
 }
 
-hipError_t launch_vec_add(int64_t n, const double* d, double* u, hipStream_t st) {
-    hipLaunchKernelGGL(k_add, dim3(grid_of(n)), dim3(kBS), 0, st, n, d, u);
+hipError_t launch_vec_add(int64_t n, const void* d, double* u, hipStream_t st, bool v32) {
+    if (v32) hipLaunchKernelGGL(k_add<float>, dim3(grid_of(n)), dim3(kBS), 0, st, n, (const float*)d, u);
+    else hipLaunchKernelGGL(k_add<double>, dim3(grid_of(n)), dim3(kBS), 0, st, n, (const double*)d, u);
     return hipGetLastError();
 }
 
