@@ -223,7 +223,9 @@ fpde_status fpde_load_vector(fpde_op *op, const double *f_nodal, double *F, void
  * drift of the recursive residual); with FPDE_FLAG_JACOBI each pass is CG
  * preconditioned by the diagonal D of A_h (stopping still on ||r||); an FPDE_PREC_MIXED operator's CG uses the
  * mixed-precision apply and stops each pass at a relative reduction of
- * sqrt(rtol), clamped to [1e-7, 1e-2].  CG iterations are launched back to
+ * sqrt(rtol), clamped to [1e-7, 1e-2], and keeps its CG vectors in FP32 (dot
+ * products in FP64) unless each field has one right-hand side on the fused
+ * one-vector path.  CG iterations are launched back to
  * back on hip_stream; the host polls convergence every few iterations.  Synchronises hip_stream.  info (host, may be NULL): total
  * CG iterations of the worst system summed over passes, final worst relative
  * residual, converged flag, number of refinement passes.
