@@ -11,6 +11,8 @@
   refinement against the oracle's Cholesky solution, and the constant-order
   s = 1/2 run against the closed form sqrt(1 - x^2) (Sec. 7.1), with the
   same L2 error as the oracle's own solution.
+* The ends of the admissible orders: s = 0, s just below s_bar, and a jump
+  from 0 to 0.85, applied and solved against the oracle.
 """
 import numpy as np
 import pytest
@@ -133,3 +135,36 @@ def test_interval512_closed_form():
     assert abs(e_gpu - e_ref) < 1e-6 * e_ref + 1e-12
     assert e_gpu < 2.5e-3
     op.close()
+
+
+def _with_order(P, s):
+    from dataclasses import replace
+    return replace(P, s=np.asarray(s, dtype=np.float64)[None, :])
+
+
+@pytest.mark.parametrize("order", ["zero", "near_s_bar", "jump"])
+def test_extreme_orders(order):
+    """The ends of the admissible orders: s = 0 everywhere (kernel |x - y|^-d), s just
+    below s_bar = 0.9, and a jump from 0 to 0.85 across x1 = 0.5: FP64 apply within
+    1e-10 of the oracle, mixed within 1e-6, Jacobi PCG within 1e-8 of its Cholesky
+    solution."""
+    base = configs.square(12, 6, leaf_size=16, leaf_size_rho=32, cheb_p=4)
+    x1 = base.mesh.coords[0]
+    s = {"zero": np.zeros_like(x1), "near_s_bar": np.full_like(x1, 0.899),
+         "jump": np.where(x1 < 0.5, 0.0, 0.85)}[order]
+    P, ref = _oracle(f"order_{order}", lambda: _with_order(base, s))
+    A = ref["B"] + ref["K"] + ref["M"]
+    x = np.random.default_rng(51).standard_normal((1, P.mesh.n_dofs, 3))
+    for precision, tol in (("fp64", TOL), ("mixed", MIXED_TOL)):
+        op = _op(P, precision=precision, jacobi=True)
+        y = _apply(op, x)[0]
+        yr = A @ x[0]
+        err = (np.linalg.norm(y - yr, axis=0) / np.linalg.norm(yr, axis=0)).max()
+        F = op.load_vector(torch.tensor(P.f, device="cuda")).reshape(1, -1, 1)
+        u, info = op.solve(F, rtol=1e-12, maxit=20000)
+        u = u.cpu().numpy()[0, :, 0]
+        op.close()
+        uref = solve_dense(A, load_vector(P.mesh, P.f, P.opts))
+        eu = np.linalg.norm(u - uref) / np.linalg.norm(uref)
+        print(f"[configs] s {order} {precision}: apply {err:.2e}, solve {eu:.2e} ({info['iterations']} it)", flush=True)
+        assert err < tol and eu < SOL_TOL, (precision, err, eu)
