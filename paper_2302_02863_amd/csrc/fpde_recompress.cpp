@@ -21,6 +21,8 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <exception>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -125,7 +127,8 @@ void eig_sym(int n, const double* S, double* lam, double* V) {
     std::copy(Vs.begin(), Vs.end(), V);
 }
 
-// fn(i) for i in [0, n) on up to 16 host threads (each i independent)
+// fn(i) for i in [0, n) on up to 16 host threads (each i independent); an exception in
+// a worker stops the others and is rethrown here after the join
 template <typename Fn>
 void parallel_for(int64_t n, Fn fn) {
     const unsigned hc = std::thread::hardware_concurrency();
@@ -135,12 +138,21 @@ void parallel_for(int64_t n, Fn fn) {
         return;
     }
     std::atomic<int64_t> next(0);
+    std::exception_ptr err;
+    std::mutex mu;
     std::vector<std::thread> th;
     for (unsigned k = 0; k < nt; ++k)
         th.emplace_back([&]() {
-            for (int64_t i = next++; i < n; i = next++) fn(i);
+            try {
+                for (int64_t i = next++; i < n; i = next++) fn(i);
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (!err) err = std::current_exception();
+                next = n;
+            }
         });
     for (auto& x : th) x.join();
+    if (err) std::rethrow_exception(err);
 }
 
 // C (m x n) = A (m x k) B (k x n), all row-major; tA / tB: use the transpose
