@@ -934,6 +934,28 @@ void build_device(fpde_op& op) {
         np.nc_ptr = op.d_nc_ptr;
         np.nc_cell = op.d_nc_cell;
         np.nc_slot = op.d_nc_slot;
+        std::vector<int64_t> own, mirror;
+        if (symmetric_pairs(op.knear)) {
+            std::vector<std::pair<std::pair<int64_t, int64_t>, int64_t>> key(op.knear.size());
+            for (size_t e = 0; e < op.knear.size(); ++e) key[e] = {op.knear[e], (int64_t)e};
+            std::sort(key.begin(), key.end());
+            for (size_t e = 0; e < op.knear.size(); ++e) {
+                const auto& pr = op.knear[e];
+                if (pr.first > pr.second) continue;
+                auto it = std::lower_bound(key.begin(), key.end(),
+                                           std::make_pair(std::make_pair(pr.second, pr.first), (int64_t)-1));
+                own.push_back((int64_t)e);
+                mirror.push_back(it->second);
+            }
+        } else {
+            for (size_t e = 0; e < op.knear.size(); ++e) {
+                own.push_back((int64_t)e);
+                mirror.push_back((int64_t)e);
+            }
+        }
+        np.nown = (int64_t)own.size();
+        np.own = A.upload(own, st);
+        np.mirror = A.upload(mirror, st);
         op.d_near = A.alloc<double>((int64_t)F * np.npairs * op.cap * op.cap);
         hipck(launch_near_blocks_lds(h, np, max_patch, td.perm, op.d_C, nqe, m.nc, d_qx, op.d_qw, d_qs, d_qk,
                                      op.d_lam, nq, F, op.opts.a_scale, op.d_near, st), "near blocks");
@@ -979,7 +1001,8 @@ void build_device(fpde_op& op) {
             A.release(op.d_near);   // every apply reads the panels
             op.d_near = nullptr;
         }
-        for (void* q : {(void*)np.tgt, (void*)np.src, (void*)np.row_ptr, (void*)np.row_lcell, (void*)np.row_slot})
+        for (void* q : {(void*)np.tgt, (void*)np.src, (void*)np.row_ptr, (void*)np.row_lcell, (void*)np.row_slot,
+                        (void*)np.own, (void*)np.mirror})
             A.release(q);
         {   // adjoint of the near blocks: patches, leaf of every dof, leaves whose patch holds a cell
             op.adj.patch_ptr = (int64_t*)np.patch_ptr;

@@ -102,6 +102,12 @@ struct NearPlan {
     const int64_t* nc_ptr;     // node -> cells (global)
     const int64_t* nc_cell;
     const int8_t* nc_slot;
+    // the blocks computed: every pair, or, when the pair list is closed under
+    // transposition, the pairs (t, s) with t <= s, each also stored transposed as
+    // the block of (s, t) (the kernel of K is symmetric in x and y)
+    int64_t nown;
+    const int64_t* own;        // [nown] pair index
+    const int64_t* mirror;     // [nown] index of the pair (s, t), or the pair itself
 };
 hipError_t launch_near_blocks_lds(const H2Tree& t, const NearPlan& np, int64_t max_patch,
                                   const int64_t* perm, const int32_t* cells, int nqe, int64_t nc,

@@ -961,10 +961,13 @@ hipError_t launch_basis_n(const H2Tree& t, int64_t N, const int64_t* perm, const
 
 // ============================================================ near leaf blocks of K~
 
-// Block per (near pair, chunk of JC source columns).
+// Block per (computed near pair, chunk of JC source columns).
 // Phase A: R[lc][a][jj] = sum_{tau' in S_j, tau' not touching tau_lc} sum_q sum_q'
 //                         w w' gamma(q,q') lam_a(q) psi_j(q')
-// Phase B: blk[it][j] = -2 sum_{(lc,slot) around row node} R[lc][slot][jj]
+// Phase B: blk[it][j] = -2 sum_{(lc,slot) around row node} R[lc][slot][jj], stored
+//          also as entry [j][it] of the mirrored pair's block when there is one
+//          (gamma is symmetric and so is the touching test, so both blocks hold the
+//          same integrals)
 constexpr int kJC = 8;
 
 FPDE_KERNEL void k_near_blocks(H2Tree t, NearPlan P, const int64_t* perm, const int32_t* cells, int nqe,
@@ -973,7 +976,7 @@ FPDE_KERNEL void k_near_blocks(H2Tree t, NearPlan P, const int64_t* perm, const 
                                double* nb) {
     extern __shared__ double R[];
     const int64_t nchunk = (P.cap + kJC - 1) / kJC;
-    const int64_t pr = blockIdx.x / nchunk;
+    const int64_t pr = P.own[blockIdx.x / nchunk], pm = P.mirror[blockIdx.x / nchunk];
     const int j0 = (int)(blockIdx.x % nchunk) * kJC;
     const int64_t ct = P.tgt[pr], cs = P.src[pr];
     const int64_t lt = ct - t.first_leaf;
@@ -1022,6 +1025,7 @@ FPDE_KERNEL void k_near_blocks(H2Tree t, NearPlan P, const int64_t* perm, const 
     // phase B
     const int64_t tb = t.beg[ct], nt = t.end[ct] - t.beg[ct];
     double* out = nb + (((int64_t)f * P.npairs + pr) * P.cap) * P.cap;
+    double* outm = nb + (((int64_t)f * P.npairs + pm) * P.cap) * P.cap;
     for (int64_t item = threadIdx.x; item < P.cap * kJC; item += blockDim.x) {
         const int64_t it = item / kJC;
         const int jj = (int)(item % kJC);
@@ -1034,6 +1038,7 @@ FPDE_KERNEL void k_near_blocks(H2Tree t, NearPlan P, const int64_t* perm, const 
             v *= -2.0 * a_scale;
         }
         out[it * P.cap + j0 + jj] = v;
+        if (pm != pr) outm[(j0 + jj) * P.cap + it] = v;
     }
 }
 
@@ -1042,12 +1047,12 @@ hipError_t launch_near_blocks_lds(const H2Tree& t, const NearPlan& np, int64_t m
                                   const double* qx, const double* qw, const double* qs,
                                   const double* qk, const double* lam, int64_t nq_all, int F,
                                   double a_scale, double* nb, hipStream_t st) {
-    if (np.npairs == 0) return hipSuccess;
+    if (np.npairs == 0 || np.nown == 0) return hipSuccess;
     const size_t lds = (size_t)max_patch * 3 * kJC * sizeof(double);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     const int64_t nchunk = (np.cap + kJC - 1) / kJC;
     for (int f = 0; f < F; ++f)
-        hipLaunchKernelGGL(k_near_blocks, dim3((unsigned)(np.npairs * nchunk)), dim3(256), lds, st, t, np,
+        hipLaunchKernelGGL(k_near_blocks, dim3((unsigned)(np.nown * nchunk)), dim3(256), lds, st, t, np,
                            perm, cells, nqe, nc, qx, qw, qs, qk, lam, nq_all, f, a_scale, nb);
     return hipGetLastError();
 }
