@@ -21,6 +21,7 @@
 #include "fpde_internal.h"
 #include "fpde_plan.h"
 #include "fpde_recompress.h"
+#include "fpde_threads.h"
 
 namespace fpde {
 hipError_t launch_basis_n(const H2Tree& t, int64_t N, const int64_t* perm, const int64_t* nc_ptr,
@@ -313,7 +314,7 @@ void cluster_nodes(const fpde_op& op, const Tree& t, const Locator& loc, std::ve
     if (st_node) st_node->assign(t.ncl * k * 3, -1);
     if (st_w) st_w->assign(t.ncl * k * 3, 0.0);
     const int64_t M = op.mesh.M;
-    for (int64_t c = 0; c < t.ncl; ++c) {
+    parallel_for(t.ncl, [&](int64_t c) {
         double* ax = &axes[c * d * p];
         cheb_axes(d, &t.lo[c * d], &t.hi[c * d], p, ax);
         for (int al = 0; al < k; ++al) {
@@ -353,24 +354,26 @@ void cluster_nodes(const fpde_op& op, const Tree& t, const Locator& loc, std::ve
                 nk[((int64_t)f * t.ncl + c) * k + al] = std::sqrt(kv);
             }
         }
-    }
+    });
 }
 
-// node -> list of (index, weight), entries sorted by (node, index)
+// node -> list of (index, weight), entries sorted by (node, index): a stable counting
+// sort on the node (entries i come in increasing index i / per, and no (node, index)
+// repeats: the nodes of one stencil are distinct)
 void node_csr(int64_t M, const std::vector<int64_t>& st_node, const std::vector<double>& st_w, int per,
               std::vector<int64_t>& ptr, std::vector<int64_t>& idx, std::vector<double>& wts) {
-    std::vector<std::tuple<int64_t, int64_t, double>> e;
-    for (size_t i = 0; i < st_node.size(); ++i)
-        if (st_node[i] >= 0) e.emplace_back(st_node[i], (int64_t)(i / per), st_w[i]);
-    std::sort(e.begin(), e.end());
     ptr.assign(M + 1, 0);
-    for (auto& x : e) ptr[std::get<0>(x) + 1]++;
+    for (int64_t v : st_node)
+        if (v >= 0) ptr[v + 1]++;
     for (int64_t i = 0; i < M; ++i) ptr[i + 1] += ptr[i];
-    idx.resize(e.size());
-    wts.resize(e.size());
-    for (size_t i = 0; i < e.size(); ++i) {
-        idx[i] = std::get<1>(e[i]);
-        wts[i] = std::get<2>(e[i]);
+    idx.resize(ptr[M]);
+    wts.resize(ptr[M]);
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t i = 0; i < st_node.size(); ++i) {
+        const int64_t v = st_node[i];
+        if (v < 0) continue;
+        idx[fill[v]] = (int64_t)(i / per);
+        wts[fill[v]++] = st_w[i];
     }
 }
 
@@ -503,7 +506,7 @@ int64_t csr_slot(const fpde_op& op, int64_t row, int64_t col) {
 // contributions (slot, source index) sorted by slot -> ptr/idx
 void contrib_csr(int64_t nslots, std::vector<std::pair<int64_t, int64_t>>& c, std::vector<int64_t>& ptr,
                  std::vector<int64_t>& idx) {
-    std::sort(c.begin(), c.end());
+    sort_pairs(c, nslots);
     ptr.assign(nslots + 1, 0);
     idx.resize(c.size());
     for (size_t e = 0; e < c.size(); ++e) {
@@ -648,26 +651,46 @@ void build_device(fpde_op& op) {
         Timer tm(st);
         const int64_t np = (int64_t)op.pairs.size();
         std::vector<int32_t> prow(np * 8, 0);
+        // every pair's (CSR slot of B, local entry) contributions, at offsets counted first
+        std::vector<int64_t> coff(np + 1, 0);
         std::vector<std::pair<int64_t, int64_t>> contrib;
-        int32_t dofs[5];
-        for (int64_t gp = 0; gp < np; ++gp) {
-            const Pair& pr = op.pairs[op.pair_order[gp]];
-            prow[gp * 8] = pr.kind;
-            for (int a = 0; a < 6; ++a) prow[gp * 8 + 1 + a] = pr.v[a];
-            if (d == 1) {   // 1D rows: cell0 (v0, v1), cell1 (v3, v4) -> layout slots 1,2 and 4,5
-                prow[gp * 8 + 1] = pr.v[0];
-                prow[gp * 8 + 2] = pr.v[1];
-                prow[gp * 8 + 4] = pr.v[3];
-                prow[gp * 8 + 5] = pr.v[4];
-            }
-            int nd = pair_dofs(m, pr, dofs);
-            for (int a = 0; a < nd; ++a) {
-                if (dofs[a] >= m.N) continue;
-                for (int b = 0; b < nd; ++b) {
-                    if (dofs[b] >= m.N) continue;
-                    int lo = std::min(a, b), hi = std::max(a, b);
-                    contrib.push_back({csr_slot(op, op.pos_of_dof[dofs[a]], op.pos_of_dof[dofs[b]]), gp * 25 + lo * 5 + hi});
+        constexpr int64_t kBlk = 4096;
+        const int64_t nblk = (np + kBlk - 1) / kBlk;
+        for (int pass = 0; pass < 2; ++pass) {
+            parallel_for(nblk, [&](int64_t blk) {
+                int32_t dofs[5];
+                for (int64_t gp = blk * kBlk; gp < std::min(np, (blk + 1) * kBlk); ++gp) {
+                    const Pair& pr = op.pairs[op.pair_order[gp]];
+                    const int nd = pair_dofs(m, pr, dofs);
+                    if (pass == 0) {
+                        prow[gp * 8] = pr.kind;
+                        for (int a = 0; a < 6; ++a) prow[gp * 8 + 1 + a] = pr.v[a];
+                        if (d == 1) {   // 1D rows: cell0 (v0, v1), cell1 (v3, v4) -> layout slots 1,2 and 4,5
+                            prow[gp * 8 + 1] = pr.v[0];
+                            prow[gp * 8 + 2] = pr.v[1];
+                            prow[gp * 8 + 4] = pr.v[3];
+                            prow[gp * 8 + 5] = pr.v[4];
+                        }
+                        int ni = 0;
+                        for (int a = 0; a < nd; ++a) ni += dofs[a] < m.N;
+                        coff[gp + 1] = (int64_t)ni * ni;
+                        continue;
+                    }
+                    int64_t o = coff[gp];
+                    for (int a = 0; a < nd; ++a) {
+                        if (dofs[a] >= m.N) continue;
+                        for (int b = 0; b < nd; ++b) {
+                            if (dofs[b] >= m.N) continue;
+                            int lo = std::min(a, b), hi = std::max(a, b);
+                            contrib[o++] = {csr_slot(op, op.pos_of_dof[dofs[a]], op.pos_of_dof[dofs[b]]),
+                                            gp * 25 + lo * 5 + hi};
+                        }
+                    }
                 }
+            });
+            if (pass == 0) {
+                for (int64_t gp = 0; gp < np; ++gp) coff[gp + 1] += coff[gp];
+                contrib.resize(coff[np]);
             }
         }
         std::vector<double> g(op.opts.nq_sing), w(op.opts.nq_sing);
@@ -773,10 +796,10 @@ void build_device(fpde_op& op) {
         // the adjoint's target-major sums need those pairs too
         op.adj.rdev = td;
         {
-            auto closure = [](std::vector<std::pair<int64_t, int64_t>> v) {
+            auto closure = [&rt](std::vector<std::pair<int64_t, int64_t>> v) {
                 const size_t n = v.size();
                 for (size_t i = 0; i < n; ++i) v.push_back({v[i].second, v[i].first});
-                std::sort(v.begin(), v.end());
+                sort_pairs(v, rt.ncl);
                 v.erase(std::unique(v.begin(), v.end()), v.end());
                 return v;
             };

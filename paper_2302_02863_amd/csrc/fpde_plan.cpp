@@ -2,6 +2,7 @@
 // admissibility and partitions, point location.  Compiled with
 // -ffp-contract=off so that the structure-deciding arithmetic is reproducible.
 #include "fpde_plan.h"
+#include "fpde_threads.h"
 
 #include <algorithm>
 #include <cmath>
@@ -237,7 +238,8 @@ Tree kd_tree(int dim, const double* pts, int64_t stride, int64_t n, int leaf) {
     t.end.assign(t.ncl, 0);
     t.beg[0] = 0;
     t.end[0] = n;
-    for (int64_t c = 0; c < (int64_t(1) << L) - 1; ++c) {
+    // level by level; the clusters of one level split disjoint ranges of perm
+    auto split = [&](int64_t c) {
         int64_t b = t.beg[c], e = t.end[c];
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
         for (int64_t i = b; i < e; ++i)
@@ -266,6 +268,10 @@ Tree kd_tree(int dim, const double* pts, int64_t stride, int64_t n, int leaf) {
         t.end[2 * c + 1] = b + half;
         t.beg[2 * c + 2] = b + half;
         t.end[2 * c + 2] = e;
+    };
+    for (int lev = 0; lev < L; ++lev) {
+        const int64_t c0 = (int64_t(1) << lev) - 1;
+        parallel_for(int64_t(1) << lev, [&](int64_t i) { split(c0 + i); }, n >= 65536 ? 2 : 1 << 30);
     }
     return t;
 }
@@ -314,29 +320,64 @@ bool admissible(int dim, const double* lo_a, const double* hi_a, const double* l
     return (eta * dcent >= 0.5 * (Da + Db)) && (std::sqrt(g2) > min_dist);
 }
 
+void sort_pairs(std::vector<std::pair<int64_t, int64_t>>& v, int64_t ncl) {
+    std::vector<int64_t> ptr(ncl + 1, 0);
+    for (auto& x : v) ++ptr[x.first + 1];
+    for (int64_t c = 0; c < ncl; ++c) ptr[c + 1] += ptr[c];
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1), b(v.size());
+    for (auto& x : v) b[fill[x.first]++] = x.second;
+    parallel_for((ncl + 4095) / 4096, [&](int64_t blk) {
+        const int64_t c1 = std::min(ncl, (blk + 1) * 4096);
+        for (int64_t c = blk * 4096; c < c1; ++c) {
+            std::sort(b.begin() + ptr[c], b.begin() + ptr[c + 1]);
+            for (int64_t e = ptr[c]; e < ptr[c + 1]; ++e) v[e] = {c, b[e]};
+        }
+    });
+}
+
 void partition(const Tree& t, double eta, const std::vector<double>* hc, const std::vector<uint8_t>* skip,
                std::vector<std::pair<int64_t, int64_t>>& far,
                std::vector<std::pair<int64_t, int64_t>>& near) {
     far.clear();
     near.clear();
-    std::vector<std::pair<int64_t, int64_t>> stack{{0, 0}};
     const int d = t.dim;
-    while (!stack.empty()) {
-        auto [a, b] = stack.back();
-        stack.pop_back();
-        if (skip && (*skip)[a]) continue;
+    // one step of the dual-tree recursion: far, near (leaf pairs), or the four child pairs
+    auto visit = [&](int64_t a, int64_t b, std::vector<std::pair<int64_t, int64_t>>& stack,
+                     std::vector<std::pair<int64_t, int64_t>>& fo, std::vector<std::pair<int64_t, int64_t>>& no) {
+        if (skip && (*skip)[a]) return;
         const double min_dist = hc ? (*hc)[a] + (*hc)[b] : 0.0;
         if (admissible(d, &t.lo[a * d], &t.hi[a * d], &t.lo[b * d], &t.hi[b * d], eta, min_dist)) {
-            far.push_back({a, b});
+            fo.push_back({a, b});
         } else if (a >= t.first_leaf()) {
-            near.push_back({a, b});
+            no.push_back({a, b});
         } else {
             for (int64_t ca : {2 * a + 1, 2 * a + 2})
                 for (int64_t cb : {2 * b + 1, 2 * b + 2}) stack.push_back({ca, cb});
         }
+    };
+    // breadth first until there are enough independent subproblems, then each on its own
+    std::vector<std::pair<int64_t, int64_t>> front{{0, 0}};
+    while (!front.empty() && front.size() < 1024) {
+        std::vector<std::pair<int64_t, int64_t>> next;
+        for (auto& pr : front) visit(pr.first, pr.second, next, far, near);
+        front.swap(next);
     }
-    std::sort(far.begin(), far.end());
-    std::sort(near.begin(), near.end());
+    const int64_t nf = (int64_t)front.size();
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> fo(nf), no(nf);
+    parallel_for(nf, [&](int64_t i) {
+        std::vector<std::pair<int64_t, int64_t>> stack{front[i]};
+        while (!stack.empty()) {
+            auto pr = stack.back();
+            stack.pop_back();
+            visit(pr.first, pr.second, stack, fo[i], no[i]);
+        }
+    });
+    for (int64_t i = 0; i < nf; ++i) {
+        far.insert(far.end(), fo[i].begin(), fo[i].end());
+        near.insert(near.end(), no[i].begin(), no[i].end());
+    }
+    sort_pairs(far, t.ncl);
+    sort_pairs(near, t.ncl);
 }
 
 void cheb_axes(int dim, const double* lo, const double* hi, int p, double* out) {

@@ -75,6 +75,10 @@ void point_boxes(Tree& t, const double* pts, int64_t stride);
 bool admissible(int dim, const double* lo_a, const double* hi_a, const double* lo_b,
                 const double* hi_b, double eta, double min_dist);
 
+// sorts (a, b) pairs with 0 <= a < ncl by a, then b (a counting sort on a, then
+// each bucket by b)
+void sort_pairs(std::vector<std::pair<int64_t, int64_t>>& v, int64_t ncl);
+
 // dual-tree partition; a pair is far only if admissible and its boxes are more than
 // hc[a] + hc[b] apart (hc == nullptr: more than 0); skip_target[c] != 0 prunes targets
 void partition(const Tree& t, double eta, const std::vector<double>* hc,

@@ -18,15 +18,12 @@
 // Every rank is padded with zeros to the largest one, r, so the apply kernels
 // see one uniform rank.
 #include <algorithm>
-#include <atomic>
 #include <cmath>
 #include <cstdint>
-#include <exception>
-#include <mutex>
-#include <thread>
 #include <vector>
 
 #include "fpde_recompress.h"
+#include "fpde_threads.h"
 
 namespace fpde {
 
@@ -125,34 +122,6 @@ void eig_sym(int n, const double* S, double* lam, double* V) {
         for (int i = 0; i < n; ++i) Vs[(size_t)i * n + j] = V[(size_t)i * n + ord[j]];
     }
     std::copy(Vs.begin(), Vs.end(), V);
-}
-
-// fn(i) for i in [0, n) on up to 16 host threads (each i independent); an exception in
-// a worker stops the others and is rethrown here after the join
-template <typename Fn>
-void parallel_for(int64_t n, Fn fn) {
-    const unsigned hc = std::thread::hardware_concurrency();
-    const unsigned nt = std::min<unsigned>(16, hc ? hc : 1);
-    if (n < 32 || nt == 1) {
-        for (int64_t i = 0; i < n; ++i) fn(i);
-        return;
-    }
-    std::atomic<int64_t> next(0);
-    std::exception_ptr err;
-    std::mutex mu;
-    std::vector<std::thread> th;
-    for (unsigned k = 0; k < nt; ++k)
-        th.emplace_back([&]() {
-            try {
-                for (int64_t i = next++; i < n; i = next++) fn(i);
-            } catch (...) {
-                std::lock_guard<std::mutex> lk(mu);
-                if (!err) err = std::current_exception();
-                next = n;
-            }
-        });
-    for (auto& x : th) x.join();
-    if (err) std::rethrow_exception(err);
 }
 
 // C (m x n) = A (m x k) B (k x n), all row-major; tA / tB: use the transpose
