@@ -970,6 +970,10 @@ hipError_t launch_basis_n(const H2Tree& t, int64_t N, const int64_t* perm, const
 //          same integrals)
 constexpr int kJC = 8;
 
+// NQE > 0: the NQE points of the target cell stay in registers and each source point
+// is loaded once per cell pair; the sums over the target points close the item.
+// NQE = 0: any rule size, the points reloaded in the inner loops.
+template <int NQE>
 FPDE_KERNEL void k_near_blocks(H2Tree t, NearPlan P, const int64_t* perm, const int32_t* cells, int nqe,
                                int64_t nc, const double* qx, const double* qw, const double* qs,
                                const double* qk, const double* lam, int64_t nq, int f, double a_scale,
@@ -995,27 +999,63 @@ FPDE_KERNEL void k_near_blocks(H2Tree t, NearPlan P, const int64_t* perm, const 
             const int64_t jn = perm[sb + j0 + jj];
             int tv[3];
             for (int a = 0; a < nv; ++a) tv[a] = cells[a * nc + cell];
-            for (int64_t e = P.nc_ptr[jn]; e < P.nc_ptr[jn + 1]; ++e) {
-                const int64_t c2 = P.nc_cell[e];
-                const int slot = P.nc_slot[e];
-                bool touch = false;
-                for (int a = 0; a < nv; ++a)
-                    for (int b = 0; b < nv; ++b) touch |= (tv[a] == cells[b * nc + c2]);
-                if (touch) continue;
-                for (int l = 0; l < nqe; ++l) {
-                    const int64_t q = cell * nqe + l;
-                    const double x0 = qx[q], x1 = t.dim == 2 ? qx[nq + q] : 0.0;
-                    const double s0 = qsf[q], k0 = qkf[q];
-                    double g = 0.0;
-                    for (int l2 = 0; l2 < nqe; ++l2) {
-                        const int64_t q2 = c2 * nqe + l2;
-                        const double d0 = x0 - qx[q2];
-                        const double d1 = t.dim == 2 ? x1 - qx[nq + q2] : 0.0;
-                        g += qw[q2] * lam[slot * nqe + l2] * qkf[q2] *
-                             rpow(d0 * d0 + d1 * d1, (double)t.dim + s0 + qsf[q2]);
+            if constexpr (NQE > 0) {
+                double tx0[NQE], tx1[NQE], te[NQE], g[NQE];
+#pragma unroll
+                for (int l = 0; l < NQE; ++l) {
+                    const int64_t q = cell * NQE + l;
+                    tx0[l] = qx[q];
+                    tx1[l] = t.dim == 2 ? qx[nq + q] : 0.0;
+                    te[l] = (double)t.dim + qsf[q];
+                    g[l] = 0.0;
+                }
+                for (int64_t e = P.nc_ptr[jn]; e < P.nc_ptr[jn + 1]; ++e) {
+                    const int64_t c2 = P.nc_cell[e];
+                    const int slot = P.nc_slot[e];
+                    bool touch = false;
+                    for (int a = 0; a < nv; ++a)
+                        for (int b = 0; b < nv; ++b) touch |= (tv[a] == cells[b * nc + c2]);
+                    if (touch) continue;
+                    for (int l2 = 0; l2 < NQE; ++l2) {
+                        const int64_t q2 = c2 * NQE + l2;
+                        const double y0 = qx[q2], y1 = t.dim == 2 ? qx[nq + q2] : 0.0;
+                        const double w2 = qw[q2] * lam[slot * NQE + l2] * qkf[q2], s2 = qsf[q2];
+#pragma unroll
+                        for (int l = 0; l < NQE; ++l) {
+                            const double d0 = tx0[l] - y0, d1 = tx1[l] - y1;
+                            g[l] += w2 * rpow(d0 * d0 + d1 * d1, te[l] + s2);
+                        }
                     }
-                    g *= qw[q] * k0;
-                    for (int a = 0; a < nv; ++a) acc[a] += g * lam[a * nqe + l];
+                }
+#pragma unroll
+                for (int l = 0; l < NQE; ++l) {
+                    const int64_t q = cell * NQE + l;
+                    const double gl = g[l] * (qw[q] * qkf[q]);
+                    for (int a = 0; a < nv; ++a) acc[a] += gl * lam[a * NQE + l];
+                }
+            } else {
+                for (int64_t e = P.nc_ptr[jn]; e < P.nc_ptr[jn + 1]; ++e) {
+                    const int64_t c2 = P.nc_cell[e];
+                    const int slot = P.nc_slot[e];
+                    bool touch = false;
+                    for (int a = 0; a < nv; ++a)
+                        for (int b = 0; b < nv; ++b) touch |= (tv[a] == cells[b * nc + c2]);
+                    if (touch) continue;
+                    for (int l = 0; l < nqe; ++l) {
+                        const int64_t q = cell * nqe + l;
+                        const double x0 = qx[q], x1 = t.dim == 2 ? qx[nq + q] : 0.0;
+                        const double s0 = qsf[q], k0 = qkf[q];
+                        double g = 0.0;
+                        for (int l2 = 0; l2 < nqe; ++l2) {
+                            const int64_t q2 = c2 * nqe + l2;
+                            const double d0 = x0 - qx[q2];
+                            const double d1 = t.dim == 2 ? x1 - qx[nq + q2] : 0.0;
+                            g += qw[q2] * lam[slot * nqe + l2] * qkf[q2] *
+                                 rpow(d0 * d0 + d1 * d1, (double)t.dim + s0 + qsf[q2]);
+                        }
+                        g *= qw[q] * k0;
+                        for (int a = 0; a < nv; ++a) acc[a] += g * lam[a * nqe + l];
+                    }
                 }
             }
         }
@@ -1051,9 +1091,10 @@ hipError_t launch_near_blocks_lds(const H2Tree& t, const NearPlan& np, int64_t m
     const size_t lds = (size_t)max_patch * 3 * kJC * sizeof(double);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     const int64_t nchunk = (np.cap + kJC - 1) / kJC;
+    auto kern = nqe == 9 ? k_near_blocks<9> : nqe == 3 ? k_near_blocks<3> : k_near_blocks<0>;
     for (int f = 0; f < F; ++f)
-        hipLaunchKernelGGL(k_near_blocks, dim3((unsigned)(np.nown * nchunk)), dim3(256), lds, st, t, np,
-                           perm, cells, nqe, nc, qx, qw, qs, qk, lam, nq_all, f, a_scale, nb);
+        hipLaunchKernelGGL(kern, dim3((unsigned)(np.nown * nchunk)), dim3(256), lds, st, t, np, perm, cells, nqe, nc,
+                           qx, qw, qs, qk, lam, nq_all, f, a_scale, nb);
     return hipGetLastError();
 }
 
