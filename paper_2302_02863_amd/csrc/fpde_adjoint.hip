@@ -71,15 +71,19 @@ FPDE_KERNEL void k_adj_c(int dim, int64_t nc, int nqe, const int32_t* cells, con
 // near relation: for q in an interior cell tau,
 //   D(q) = sum_{S: tau in P(S)} sum_{S' near S} sum_{q'} -2 omega omega' gamma
 //          [W_S(q) U_S'(q') + U_S(q) W_S'(q')] x {-ln r | 1 / (2 kappa(q))}.
-// One block per interior cell, one right-hand side r per launch; threads
-// stride over the source cells.
+// One block per interior cell, one right-hand side r per launch; the threads
+// take the (source leaf, patch cell) items of a target leaf in turn, so every
+// lane has work however small each patch is.  NQE > 0 fixes the rule size at
+// compile time (the accumulators then take NQE registers, not kMaxQE).
 
+template <int NQE>
 FPDE_KERNEL void k_adj_knear(AdjKnear P, int f, double* Ds, double* Dk) {
+    constexpr int NL = NQE > 0 ? NQE : kMaxQE;
     __shared__ double tx[kMaxQE], ty[kMaxQE], ts[kMaxQE], tk[kMaxQE], tw[kMaxQE], tW[kMaxQE], tU[kMaxQE];
     __shared__ double red[256];
     const int64_t ci = blockIdx.x;
     const int64_t cell = P.icells[ci];
-    const int nqe = P.nqe, nv = P.dim + 1;
+    const int nqe = NQE > 0 ? NQE : P.nqe, nv = P.dim + 1;
     const int tid = threadIdx.x;
     const double* qs = P.qs + (int64_t)f * P.nq;
     const double* qk = P.qk + (int64_t)f * P.nq;
@@ -98,9 +102,9 @@ FPDE_KERNEL void k_adj_knear(AdjKnear P, int f, double* Ds, double* Dk) {
         tk[tid] = qk[q];
         tw[tid] = P.qw[q];
     }
-    double accS[kMaxQE], accK[kMaxQE];
+    double accS[NL], accK[NL];
 #pragma unroll
-    for (int l = 0; l < kMaxQE; ++l) accS[l] = accK[l] = 0.0;
+    for (int l = 0; l < NL; ++l) accS[l] = accK[l] = 0.0;
     const double dd = (double)P.dim;
     for (int64_t e0 = P.cell_leaf_ptr[ci]; e0 < P.cell_leaf_ptr[ci + 1]; ++e0) {
         const int S = P.cell_leaf[e0];
@@ -118,10 +122,13 @@ FPDE_KERNEL void k_adj_knear(AdjKnear P, int f, double* Ds, double* Dk) {
             tU[tid] = U;
         }
         __syncthreads();
+        int64_t base = 0;   // items of the earlier source leaves
         for (int64_t e = P.near_ptr[S]; e < P.near_ptr[S + 1]; ++e) {
             const int64_t S2 = P.near_src[e];
             const int64_t pb = P.patch_ptr[S2], pn = P.patch_ptr[S2 + 1] - pb;
-            for (int64_t k = tid; k < pn; k += blockDim.x) {
+            const int64_t k0 = ((tid - base) % blockDim.x + blockDim.x) % blockDim.x;   // (base + k0) % nt == tid
+            base += pn;
+            for (int64_t k = k0; k < pn; k += blockDim.x) {
                 const int64_t c2 = P.patch_cell[pb + k];
                 int sv[3] = {-2, -2, -2}, sl[3] = {-1, -1, -1};
                 bool touch = false;
@@ -153,8 +160,8 @@ FPDE_KERNEL void k_adj_knear(AdjKnear P, int f, double* Ds, double* Dk) {
                     const double x2 = P.qx[q2], y2 = P.dim == 2 ? P.qx[P.nq + q2] : 0.0;
                     const double s2 = qs[q2], k2 = qk[q2], w2 = P.qw[q2];
 #pragma unroll
-                    for (int l = 0; l < kMaxQE; ++l) {
-                        if (l >= nqe) break;
+                    for (int l = 0; l < NL; ++l) {
+                        if (NQE == 0 && l >= nqe) break;
                         const double d0 = tx[l] - x2, d1 = ty[l] - y2;
                         const double r2 = d0 * d0 + d1 * d1;
                         const double lr2 = log(r2);
@@ -169,8 +176,8 @@ FPDE_KERNEL void k_adj_knear(AdjKnear P, int f, double* Ds, double* Dk) {
     }
     // block sums in a fixed order
 #pragma unroll
-    for (int l = 0; l < kMaxQE; ++l) {
-        if (l >= nqe) break;
+    for (int l = 0; l < NL; ++l) {
+        if (NQE == 0 && l >= nqe) break;
         for (int pass = 0; pass < 2; ++pass) {
             red[tid] = pass == 0 ? accS[l] : accK[l];
             __syncthreads();
@@ -192,8 +199,8 @@ FPDE_KERNEL void k_adj_knear(AdjKnear P, int f, double* Ds, double* Dk) {
 hipError_t launch_adj_knear(const AdjKnear& P, int64_t n_icells, int F, double* Ds, double* Dk, hipStream_t st) {
     if (P.nqe > kMaxQE) return hipErrorInvalidValue;
     if (n_icells == 0) return hipSuccess;
-    for (int f = 0; f < F; ++f)
-        hipLaunchKernelGGL(k_adj_knear, dim3((unsigned)n_icells), dim3(256), 0, st, P, f, Ds, Dk);
+    auto kern = P.nqe == 9 ? k_adj_knear<9> : P.nqe == 3 ? k_adj_knear<3> : k_adj_knear<0>;
+    for (int f = 0; f < F; ++f) hipLaunchKernelGGL(kern, dim3((unsigned)n_icells), dim3(256), 0, st, P, f, Ds, Dk);
     return hipGetLastError();
 }
 
