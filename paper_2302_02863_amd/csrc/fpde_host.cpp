@@ -302,18 +302,16 @@ H2Tree make_h2(const Tree& t, const TreeDev& d, int p) {
     return h;
 }
 
-// Chebyshev axes of every cluster and P1 values of s, sqrt(kappa) at the nodes
+// Chebyshev axes of every cluster and the P1 stencil of each of its nodes: up to 3
+// (mesh node, P1 weight) of the cell holding it, or (nearest node, 1) outside the
+// mesh; node -1 pads.  The values of s and sqrt(kappa) there come from the stencils
+// on the device (launch_node_fields).
 void cluster_nodes(const fpde_op& op, const Tree& t, const Locator& loc, std::vector<double>& axes,
-                   std::vector<double>& ns, std::vector<double>& nk, std::vector<int64_t>* st_node = nullptr,
-                   std::vector<double>* st_w = nullptr) {
+                   std::vector<int64_t>& st_node, std::vector<double>& st_w) {
     const int d = t.dim, p = op.opts.cheb_p, k = d == 2 ? p * p : p;
     axes.assign(t.ncl * d * p, 0.0);
-    ns.assign((int64_t)op.F * t.ncl * k, 0.0);
-    nk.assign((int64_t)op.F * t.ncl * k, 0.0);
-    // stencil of every node: up to 3 (mesh node, P1 weight); node -1 pads
-    if (st_node) st_node->assign(t.ncl * k * 3, -1);
-    if (st_w) st_w->assign(t.ncl * k * 3, 0.0);
-    const int64_t M = op.mesh.M;
+    st_node.assign(t.ncl * k * 3, -1);
+    st_w.assign(t.ncl * k * 3, 0.0);
     parallel_for(t.ncl, [&](int64_t c) {
         double* ax = &axes[c * d * p];
         cheb_axes(d, &t.lo[c * d], &t.hi[c * d], p, ax);
@@ -321,37 +319,16 @@ void cluster_nodes(const fpde_op& op, const Tree& t, const Locator& loc, std::ve
             double x[2] = {ax[al % p], d == 2 ? ax[p + al / p] : 0.0};
             double lam[3];
             int64_t node = -1;
-            int64_t cell = loc.locate(x, lam, &node);
-            if (st_node) {
-                const int64_t o = (c * k + al) * 3;
-                if (cell < 0) {
-                    (*st_node)[o] = node;
-                    (*st_w)[o] = 1.0;
-                } else {
-                    for (int a = 0; a <= d; ++a) {
-                        (*st_node)[o + a] = op.mesh.v(a, cell);
-                        (*st_w)[o + a] = lam[a];
-                    }
+            const int64_t cell = loc.locate(x, lam, &node);
+            const int64_t o = (c * k + al) * 3;
+            if (cell < 0) {
+                st_node[o] = node;
+                st_w[o] = 1.0;
+            } else {
+                for (int a = 0; a <= d; ++a) {
+                    st_node[o + a] = op.mesh.v(a, cell);
+                    st_w[o + a] = lam[a];
                 }
-            }
-            for (int f = 0; f < op.F; ++f) {
-                const double* sf = &op.s[(int64_t)f * M];
-                const double* kf = &op.kappa[(int64_t)f * M];
-                double sv, kv;
-                if (cell < 0) {
-                    sv = sf[node];
-                    kv = kf[node];
-                } else if (d == 1) {
-                    sv = sf[op.mesh.v(0, cell)] * lam[0] + sf[op.mesh.v(1, cell)] * lam[1];
-                    kv = kf[op.mesh.v(0, cell)] * lam[0] + kf[op.mesh.v(1, cell)] * lam[1];
-                } else {
-                    sv = (sf[op.mesh.v(0, cell)] * lam[0] + sf[op.mesh.v(1, cell)] * lam[1]) +
-                         sf[op.mesh.v(2, cell)] * lam[2];
-                    kv = (kf[op.mesh.v(0, cell)] * lam[0] + kf[op.mesh.v(1, cell)] * lam[1]) +
-                         kf[op.mesh.v(2, cell)] * lam[2];
-                }
-                ns[((int64_t)f * t.ncl + c) * k + al] = sv;
-                nk[((int64_t)f * t.ncl + c) * k + al] = std::sqrt(kv);
             }
         }
     });
@@ -614,6 +591,19 @@ void recompress(fpde_op& op, hipStream_t st) {
     op.stats.t_recompress_ms = ms_since(t0);
 }
 
+// s and sqrt(kappa) of every field at the nn cluster nodes, [F][nn], from the stencils
+void node_fields(Arena& A, int64_t nn, int F, int64_t M, const std::vector<int64_t>& stn,
+                 const std::vector<double>& stw, const double* d_s, const double* d_k, TreeDev& td, hipStream_t st) {
+    int64_t* d_stn = A.upload(stn, st);
+    double* d_stw = A.upload(stw, st);
+    td.node_s = A.alloc<double>((int64_t)F * nn);
+    td.node_k = A.alloc<double>((int64_t)F * nn);
+    hipck(launch_node_fields(nn, F, M, d_stn, d_stw, d_s, d_k, td.node_s, td.node_k, st), "node fields");
+    hipck(hipStreamSynchronize(st), "node fields sync");
+    A.release(d_stn);
+    A.release(d_stw);
+}
+
 void build_device(fpde_op& op) {
     const HostMesh& m = op.mesh;
     const int d = m.dim, F = op.F, p = op.opts.cheb_p, k = d == 2 ? p * p : p;
@@ -738,9 +728,9 @@ void build_device(fpde_op& op) {
         const Tree& rt = op.rt;
         Locator loc;
         loc.build(m);
-        std::vector<double> axes, ns, nk, stw;
+        std::vector<double> axes, stw;
         std::vector<int64_t> stn;
-        cluster_nodes(op, rt, loc, axes, ns, nk, &stn, &stw);
+        cluster_nodes(op, rt, loc, axes, stn, stw);
         {
             std::vector<int64_t> sp, si;
             std::vector<double> swt;
@@ -762,8 +752,7 @@ void build_device(fpde_op& op) {
         td.end = A.upload(rt.end, st);
         td.perm = A.upload(rt.perm, st);
         td.axes = A.upload(axes, st);
-        td.node_s = A.upload(ns, st);
-        td.node_k = A.upload(nk, st);
+        node_fields(A, rt.ncl * k, F, m.M, stn, stw, d_s, d_k, td, st);
         td.far_ptr = A.upload(fptr, st);
         td.far_src = A.upload(fsrc, st);
         td.E = A.alloc<double>(rt.ncl * d * p * p);
@@ -860,9 +849,9 @@ void build_device(fpde_op& op) {
         const Tree& kt = op.kt;
         Locator loc;
         loc.build(m);
-        std::vector<double> axes, ns, nk, stw;
+        std::vector<double> axes, stw;
         std::vector<int64_t> stn;
-        cluster_nodes(op, kt, loc, axes, ns, nk, &stn, &stw);
+        cluster_nodes(op, kt, loc, axes, stn, stw);
         {
             std::vector<int64_t> sp, si;
             std::vector<double> swt;
@@ -878,8 +867,7 @@ void build_device(fpde_op& op) {
         td.end = A.upload(kt.end, st);
         td.perm = A.upload(kt.perm, st);
         td.axes = A.upload(axes, st);
-        td.node_s = A.upload(ns, st);
-        td.node_k = A.upload(nk, st);
+        node_fields(A, kt.ncl * k, F, m.M, stn, stw, d_s, d_k, td, st);
         td.far_ptr = A.upload(fptr, st);
         td.far_src = A.upload(fsrc, st);
         td.E = A.alloc<double>(kt.ncl * d * p * p);

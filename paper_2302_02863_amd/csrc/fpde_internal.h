@@ -31,6 +31,10 @@ hipError_t launch_segsum(int64_t nslots, const int64_t* ptr, const int64_t* idx,
                          hipStream_t st);
 
 // s, sqrt(kappa) at the quadrature points: qs[f][q], qk[f][q]
+// ns[f][i], nk[f][i] = s_f and sqrt(kappa_f) at node i (< nn) from its stencil of 3
+// (mesh node, P1 weight) entries, node -1 padding
+hipError_t launch_node_fields(int64_t nn, int F, int64_t M, const int64_t* st_node, const double* st_w,
+                              const double* s, const double* kappa, double* ns, double* nk, hipStream_t st);
 hipError_t launch_quad_fields(int dim, int64_t nc, int nqe, const int32_t* cells,
                               const double* lam /*[dim+1][nqe]*/, int F, int64_t n_nodes,
                               const double* s, const double* kappa, double* qs, double* qk,

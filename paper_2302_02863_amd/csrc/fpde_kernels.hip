@@ -568,6 +568,36 @@ hipError_t launch_quad_fields(int dim, int64_t nc, int nqe, const int32_t* cells
     return hipGetLastError();
 }
 
+// P1 values of s and sqrt(kappa) at the Chebyshev nodes of the clusters: the stencil
+// entries summed in order, each product rounded on its own (no contraction)
+FPDE_KERNEL void k_node_fields(int64_t nn, int64_t M, const int64_t* st_node, const double* st_w,
+                               const double* s, const double* kappa, double* ns, double* nk, int f) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    const double* sf = s + (int64_t)f * M;
+    const double* kf = kappa + (int64_t)f * M;
+    double sv = 0.0, kv = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t v = st_node[i * 3 + a];
+        if (v < 0) continue;
+        const double w = st_w[i * 3 + a];
+        const double ps = sf[v] * w, pk = kf[v] * w;
+        sv = a == 0 ? ps : sv + ps;
+        kv = a == 0 ? pk : kv + pk;
+    }
+    ns[(int64_t)f * nn + i] = sv;
+    nk[(int64_t)f * nn + i] = sqrt(kv);
+}
+
+hipError_t launch_node_fields(int64_t nn, int F, int64_t M, const int64_t* st_node, const double* st_w,
+                              const double* s, const double* kappa, double* ns, double* nk, hipStream_t st) {
+    for (int f = 0; f < F; ++f)
+        hipLaunchKernelGGL(k_node_fields, dim3(grid1(nn)), dim3(256), 0, st, nn, M, st_node, st_w, s, kappa, ns, nk,
+                           f);
+    return hipGetLastError();
+}
+
 // ============================================================ Chebyshev helpers
 
 // 1D Lagrange basis value L_a(x) on the axis points t[0..p)
