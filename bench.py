@@ -365,6 +365,28 @@ def batched_solve_and_adjoint(P, x, ops):
     return out
 
 
+def build_and_adjoint():
+    """The headline workload's FP64 operator built once and its adjoint run once with one
+    vector pair per field (a short run for a kernel trace of the build and the adjoint)."""
+    import torch
+    import paper_2302_02863_amd as fp
+    from fpde_inputs import configs
+    P = configs.batched(256, n_fields=16, nrhs=2)
+    t0 = time.perf_counter()
+    op = fp.Operator(P.mesh, P.s, P.kappa, dict(P.opts))
+    torch.cuda.synchronize()
+    build = time.perf_counter() - t0
+    st = op.stats()
+    x = torch.tensor(P.x, device="cuda:0")
+    ms = time_adjoint(op, x[:, :, :1].contiguous(), x[:, :, 1:2].contiguous(), n=1)
+    op.close()
+    return {"workload": "square-256x256-P1, 16 order fields, FP64 operator; adjoint with 1 vector pair per field",
+            "build_s": build,
+            "build_phase_ms": {k: st[k] for k in ("t_plan_ms", "t_singular_ms", "t_rho_ms", "t_mass_ms",
+                                                  "t_bases_ms", "t_near_blocks_ms")},
+            "adjoint_ms": ms}
+
+
 def p1_l2_norm(mesh, u_dofs):
     """L2(Omega_i) norm of the P1 function with dof values u (zero on the other nodes):
     per cell, vol (sum u_a^2 + (sum u_a)^2) / ((d+1)(d+2)) is the exact integral of u^2."""
@@ -589,6 +611,8 @@ def main():
     ap.add_argument("--no-scaling", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 256 MiB (calibrates HBM byte counters)")
+    ap.add_argument("--build-adjoint", action="store_true",
+                    help="run only one build of the headline FP64 operator and one adjoint (kernel traces)")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -604,6 +628,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(1)
+    if args.build_adjoint:
+        print(json.dumps(build_and_adjoint()))
+        return
 
     P, x, ops, hl = headline(args.steps, args.warmup)
     ys_fp64 = hl.pop("_y_fp64")
