@@ -196,10 +196,111 @@ FPDE_KERNEL void k_adj_knear(AdjKnear P, int f, double* Ds, double* Dk) {
     }
 }
 
+// The same sums with the target point fixed per thread (rule sizes known at compile
+// time): thread tid owns point l = tid % NQE of the cell and takes the source items
+// of group tid / NQE, G = 256 / NQE groups in turn.  Each thread keeps its point's
+// data and two sums in registers; the groups' sums are added in group order.
+template <int NQE>
+FPDE_KERNEL void k_adj_knear_pt(AdjKnear P, int f, double* Ds, double* Dk) {
+    constexpr int G = 256 / NQE;
+    __shared__ double redS[256], redK[256];
+    const int64_t ci = blockIdx.x;
+    const int64_t cell = P.icells[ci];
+    const int nv = P.dim + 1;
+    const int tid = threadIdx.x, l = tid % NQE, g = tid / NQE;
+    const double* qs = P.qs + (int64_t)f * P.nq;
+    const double* qk = P.qk + (int64_t)f * P.nq;
+    int tv[3] = {-1, -1, -1}, tl[3] = {-1, -1, -1};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (a < nv) {
+            tv[a] = P.cells[a * P.nc + cell];
+            tl[a] = P.leaf_of_node[tv[a]];
+        }
+    const int64_t q = cell * NQE + l;
+    const double tx = P.qx[q], ty = P.dim == 2 ? P.qx[P.nq + q] : 0.0;
+    const double ts = qs[q], tk = qk[q];
+    const double dd = (double)P.dim;
+    double accS = 0.0, accK = 0.0;
+    if (g < G) {
+        for (int64_t e0 = P.cell_leaf_ptr[ci]; e0 < P.cell_leaf_ptr[ci + 1]; ++e0) {
+            const int S = P.cell_leaf[e0];
+            double tW = 0.0, tU = 0.0;   // W_S, U_S at the point
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (a < nv && tl[a] == S) {
+                    const double la = P.lam[a * NQE + l];
+                    tW += la * P.w[((int64_t)f * P.N + tv[a]) * P.R + P.r];
+                    tU += la * P.u[((int64_t)f * P.N + tv[a]) * P.R + P.r];
+                }
+            int64_t base = 0;   // items of the earlier source leaves
+            for (int64_t e = P.near_ptr[S]; e < P.near_ptr[S + 1]; ++e) {
+                const int64_t S2 = P.near_src[e];
+                const int64_t pb = P.patch_ptr[S2], pn = P.patch_ptr[S2 + 1] - pb;
+                const int64_t k0 = ((g - base) % G + G) % G;   // (base + k0) % G == g
+                base += pn;
+                for (int64_t k = k0; k < pn; k += G) {
+                    const int64_t c2 = P.patch_cell[pb + k];
+                    int sv[3] = {-2, -2, -2}, sl[3] = {-1, -1, -1};
+                    bool touch = false;
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        if (b < nv) {
+                            sv[b] = P.cells[b * P.nc + c2];
+                            sl[b] = P.leaf_of_node[sv[b]];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) touch |= (a < nv && tv[a] == sv[b]);
+                        }
+                    if (touch) continue;
+                    double wv[3] = {0, 0, 0}, uv[3] = {0, 0, 0};
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        if (b < nv && sl[b] == (int)S2) {
+                            wv[b] = P.w[((int64_t)f * P.N + sv[b]) * P.R + P.r];
+                            uv[b] = P.u[((int64_t)f * P.N + sv[b]) * P.R + P.r];
+                        }
+#pragma unroll 3
+                    for (int l2 = 0; l2 < NQE; ++l2) {
+                        const int64_t q2 = c2 * NQE + l2;
+                        double W2 = 0.0, U2 = 0.0;
+#pragma unroll
+                        for (int b = 0; b < 3; ++b)
+                            if (b < nv) {
+                                W2 += P.lam[b * NQE + l2] * wv[b];
+                                U2 += P.lam[b * NQE + l2] * uv[b];
+                            }
+                        const double x2 = P.qx[q2], y2 = P.dim == 2 ? P.qx[P.nq + q2] : 0.0;
+                        const double s2 = qs[q2], k2 = qk[q2], w2 = P.qw[q2];
+                        const double d0 = tx - x2, d1 = ty - y2;
+                        const double lr2 = log(d0 * d0 + d1 * d1);
+                        const double gm = tk * k2 * exp(-0.5 * (dd + ts + s2) * lr2);
+                        const double cf = w2 * gm * (tW * U2 + tU * W2);
+                        accS += -0.5 * lr2 * cf;
+                        accK += cf;
+                    }
+                }
+            }
+        }
+    }
+    redS[tid] = accS;
+    redK[tid] = accK;
+    __syncthreads();
+    if (tid < NQE) {   // point tid: the groups' sums in group order
+        double vs = 0.0, vk = 0.0;
+        for (int gg = 0; gg < G; ++gg) {
+            vs += redS[gg * NQE + tid];
+            vk += redK[gg * NQE + tid];
+        }
+        const double c = -2.0 * P.a_scale * P.qw[q];
+        Ds[(int64_t)f * P.nq + q] += c * vs;
+        Dk[(int64_t)f * P.nq + q] += c * vk / (2.0 * tk * tk);
+    }
+}
+
 hipError_t launch_adj_knear(const AdjKnear& P, int64_t n_icells, int F, double* Ds, double* Dk, hipStream_t st) {
     if (P.nqe > kMaxQE) return hipErrorInvalidValue;
     if (n_icells == 0) return hipSuccess;
-    auto kern = P.nqe == 9 ? k_adj_knear<9> : P.nqe == 3 ? k_adj_knear<3> : k_adj_knear<0>;
+    auto kern = P.nqe == 9 ? k_adj_knear_pt<9> : P.nqe == 3 ? k_adj_knear_pt<3> : k_adj_knear<0>;
     for (int f = 0; f < F; ++f) hipLaunchKernelGGL(kern, dim3((unsigned)n_icells), dim3(256), 0, st, P, f, Ds, Dk);
     return hipGetLastError();
 }
