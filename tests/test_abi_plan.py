@@ -100,9 +100,14 @@ def test_k_tree_and_partition_match_oracle(fp, case):
     assert gf == set(far) and gn == set(near)
 
 
-@pytest.mark.parametrize("case", list(CASES))
+# 73,728 quadrature points: the planner splits the tree levels and the partition's
+# subtrees on host threads (at least 65,536 points, a front of 1,024 pairs)
+RHO_CASES = dict(CASES, square_threads=lambda: configs.square(32, 16, leaf_size=16, leaf_size_rho=32))
+
+
+@pytest.mark.parametrize("case", list(RHO_CASES))
 def test_rho_tree_and_partition_match_oracle(fp, case):
-    P = CASES[case]()
+    P = RHO_CASES[case]()
     op = _plan(fp, P)
     m = P.mesh
     Q = quad_points(m, P.opts["nq_reg"])
