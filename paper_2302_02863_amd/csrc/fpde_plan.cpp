@@ -566,13 +566,4 @@ int64_t Locator::locate(const double* p, double* lam, int64_t* node) const {
     return -1;
 }
 
-double Locator::interp(const double* field, const double* p) const {
-    double lam[3];
-    int64_t node = -1;
-    int64_t c = locate(p, lam, &node);
-    if (c < 0) return field[node];
-    if (m->dim == 1) return field[m->v(0, c)] * lam[0] + field[m->v(1, c)] * lam[1];
-    return (field[m->v(0, c)] * lam[0] + field[m->v(1, c)] * lam[1]) + field[m->v(2, c)] * lam[2];
-}
-
 }  // namespace fpde

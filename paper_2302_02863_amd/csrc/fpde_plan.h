@@ -89,7 +89,7 @@ void partition(const Tree& t, double eta, const std::vector<double>* hc,
 // Chebyshev axes of a box: out[k*p + a]
 void cheb_axes(int dim, const double* lo, const double* hi, int p, double* out);
 
-// P1 interpolation at arbitrary points (nearest node outside the mesh)
+// Point location: the cell holding a point and its barycentrics (nearest node outside the mesh)
 struct Locator {
     const HostMesh* m = nullptr;
     double lo[2], inv[2];
@@ -99,7 +99,6 @@ struct Locator {
     void build(const HostMesh& mesh);
     // returns cell >= 0 and barycentrics, or -1 and nearest node in *node
     int64_t locate(const double* p, double* lam, int64_t* node) const;
-    double interp(const double* field, const double* p) const;
 };
 
 // largest edge length of every cell
