@@ -74,12 +74,12 @@ struct Arena {
     void release(void* p) {
         auto it = std::find(ptrs.begin(), ptrs.end(), p);
         if (it != ptrs.end()) {
-            hipFree(p);
+            (void)hipFree(p);   // a failure here surfaces at the next checked call
             ptrs.erase(it);
         }
     }
     ~Arena() {
-        for (void* p : ptrs) hipFree(p);
+        for (void* p : ptrs) (void)hipFree(p);
     }
 };
 
@@ -495,21 +495,27 @@ void contrib_csr(int64_t nslots, std::vector<std::pair<int64_t, int64_t>>& c, st
 
 // ------------------------------------------------------------------ device build
 
+// HIP events around a build phase on the build stream (released by the destructor, also
+// when the phase throws)
 struct Timer {
-    hipEvent_t a, b;
+    hipEvent_t a = nullptr, b = nullptr;
     hipStream_t st;
     explicit Timer(hipStream_t s) : st(s) {
-        hipEventCreate(&a);
-        hipEventCreate(&b);
-        hipEventRecord(a, st);
+        hipck(hipEventCreate(&a), "timer event");
+        hipck(hipEventCreate(&b), "timer event");
+        hipck(hipEventRecord(a, st), "timer record");
     }
+    ~Timer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    Timer(const Timer&) = delete;
+    Timer& operator=(const Timer&) = delete;
     double stop() {
-        hipEventRecord(b, st);
-        hipEventSynchronize(b);
+        hipck(hipEventRecord(b, st), "timer record");
+        hipck(hipEventSynchronize(b), "timer sync");
         float ms = 0;
-        hipEventElapsedTime(&ms, a, b);
-        hipEventDestroy(a);
-        hipEventDestroy(b);
+        hipck(hipEventElapsedTime(&ms, a, b), "timer elapsed");
         return ms;
     }
 };
@@ -1375,7 +1381,6 @@ hipError_t enqueue_apply(fpde_op& op, int parts, int dtype, const void* x, void*
     const int64_t nfar = (int64_t)op.kfar.size();
     const bool f32 = op.mixed && !(parts & FPDE_PART_FP64);
     const int pr = f32 ? 1 : 0;
-    const size_t esz = f32 ? sizeof(float) : sizeof(double);
     PanelPlan pp{op.d_poff, op.d_pstride, op.d_pcols, op.d_pcols_ptr, op.panel_max_stride, op.d_csr_col_dof};
     pp.pcols_pad = op.d_pcols_pad;
     pp.perm_pad = op.d_perm_pad;
@@ -2040,16 +2045,16 @@ fpde_status fpde_profile(fpde_op* op, int32_t enable, fpde_profile_t* out) {
             hipck(hipEventSynchronize(ev[4]), "event sync");
             // ev0 start, ev1 end of the far work before the near-field kernel, ev2/ev3 start/stop of that kernel, ev4 end
             float b = 0, c = 0, d = 0, e = 0;
-            hipEventElapsedTime(&b, ev[0], ev[1]);
-            hipEventElapsedTime(&c, ev[2], ev[3]);
-            hipEventElapsedTime(&d, ev[3], ev[4]);
-            hipEventElapsedTime(&e, ev[0], ev[4]);
+            hipck(hipEventElapsedTime(&b, ev[0], ev[1]), "event time");
+            hipck(hipEventElapsedTime(&c, ev[2], ev[3]), "event time");
+            hipck(hipEventElapsedTime(&d, ev[3], ev[4]), "event time");
+            hipck(hipEventElapsedTime(&e, ev[0], ev[4]), "event time");
             acc.ms_far += b;
             acc.ms_out += c;
             acc.ms_far_out += d;
             acc.ms_total += e;
             acc.n_applies++;
-            for (auto& e : ev) hipEventDestroy(e);
+            for (auto& e : ev) (void)hipEventDestroy(e);
         }
         op->prof_ev.clear();
         op->profiling = enable != 0;
@@ -2151,21 +2156,22 @@ fpde_status fpde_export(const fpde_op* op, int32_t what, int32_t field, void* ds
     });
 }
 
+// Releases everything; the HIP results are not reported (there is no status to return)
 void fpde_destroy(fpde_op* op) {
     if (!op) return;
-    if (op->h_nact) hipHostFree(op->h_nact);
+    if (op->h_nact) (void)hipHostFree(op->h_nact);
     for (auto& ev : op->prof_ev)
-        for (auto& e : ev) hipEventDestroy(e);
+        for (auto& e : ev) (void)hipEventDestroy(e);
     if (op->stream) {
-        hipStreamSynchronize(op->stream);
-        hipStreamDestroy(op->stream);
+        (void)hipStreamSynchronize(op->stream);
+        (void)hipStreamDestroy(op->stream);
     }
     if (op->stream2) {
-        hipStreamSynchronize(op->stream2);
-        hipStreamDestroy(op->stream2);
+        (void)hipStreamSynchronize(op->stream2);
+        (void)hipStreamDestroy(op->stream2);
     }
-    if (op->ev_fork) hipEventDestroy(op->ev_fork);
-    if (op->ev_join) hipEventDestroy(op->ev_join);
+    if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
+    if (op->ev_join) (void)hipEventDestroy(op->ev_join);
     delete op;
 }
 

@@ -810,8 +810,8 @@ hipError_t launch_rho_eval(const H2Tree& t, const int64_t* perm, const double* q
     hipLaunchKernelGGL(k_rho_eval, dim3(grid1(nq_all)), dim3(256), 0, st, t, perm, leaf_of, qx, q_int,
                        nq_all, F, yh, rho);
     e = hipGetLastError();
-    hipFreeAsync(leaf_of, st);
-    return e;
+    const hipError_t ef = hipFreeAsync(leaf_of, st);
+    return e != hipSuccess ? e : ef;
 }
 
 // near sums: one 64-thread block per target leaf; source leaves staged in LDS
@@ -985,8 +985,8 @@ hipError_t launch_basis_n(const H2Tree& t, int64_t N, const int64_t* perm, const
     hipLaunchKernelGGL(k_basis, dim3(grid1(N * t.k)), dim3(256), 0, st, t, perm, leaf_of, nc_ptr,
                        nc_cell, nc_slot, nqe, qx, qw, lam, nq_all, N, U);
     e = hipGetLastError();
-    hipFreeAsync(leaf_of, st);
-    return e;
+    const hipError_t ef = hipFreeAsync(leaf_of, st);
+    return e != hipSuccess ? e : ef;
 }
 
 // ============================================================ near leaf blocks of K~

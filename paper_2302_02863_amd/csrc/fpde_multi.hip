@@ -250,15 +250,16 @@ hipError_t launch_apply_multi(const ApplyPlan& a, const H2Tree& t, int ls, const
                               int64_t nfar, int dtype, const void* x, double* xh, double* tmp, void* y,
                               hipStream_t st, hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev) {
     const bool far = (parts & 8) != 0;
-    if (ev) hipEventRecord(ev[0], st);
+    if (ev) (void)hipEventRecord(ev[0], st);
     hipStream_t fs = st;
     if (far && side != st) {
-        hipEventRecord(fork, st);
-        hipStreamWaitEvent(side, fork, 0);
+        hipError_t e0 = hipEventRecord(fork, st);
+        if (e0 == hipSuccess) e0 = hipStreamWaitEvent(side, fork, 0);
+        if (e0 != hipSuccess) return e0;
         fs = side;
     }
     if (far) FPDE_DISPATCH_DP(t.dim, t.p, far_m_t, a, t, ls, F, R, St, nfar, dtype, x, xh, tmp, fs);
-    if (ev) hipEventRecord(ev[1], fs);
+    if (ev) (void)hipEventRecord(ev[1], fs);
     hipError_t e = panel_f32 ? launch_near_mm(a, pp, (const float*)panel, (parts & 4) != 0, csr_val, F, R, dtype, x, y,
                                               st, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr)
                              : launch_near_mm(a, pp, (const double*)panel, (parts & 4) != 0, csr_val, F, R, dtype, x,
@@ -266,12 +267,13 @@ hipError_t launch_apply_multi(const ApplyPlan& a, const H2Tree& t, int ls, const
     if (e != hipSuccess) return e;
     if (far) {
         if (fs != st) {
-            hipEventRecord(join, fs);
-            hipStreamWaitEvent(st, join, 0);
+            hipError_t e1 = hipEventRecord(join, fs);
+            if (e1 == hipSuccess) e1 = hipStreamWaitEvent(st, join, 0);
+            if (e1 != hipSuccess) return e1;
         }
         FPDE_DISPATCH_DP(t.dim, t.p, far_out_m_t, a, t, F, R, tmp, dtype, y, st);
     }
-    if (ev) hipEventRecord(ev[4], st);
+    if (ev) (void)hipEventRecord(ev[4], st);
     return hipGetLastError();
 }
 
@@ -282,11 +284,12 @@ hipError_t launch_apply_wide(const ApplyPlan& a, const H2Tree& t, const PanelPla
                              const void* x, double* xt, double* xh, double* yh, void* y, hipStream_t st,
                              hipStream_t side, hipEvent_t fork, hipEvent_t join, hipEvent_t* ev) {
     const bool far = (parts & 8) != 0;
-    if (ev) hipEventRecord(ev[0], st);
+    if (ev) (void)hipEventRecord(ev[0], st);
     hipStream_t fs = st;
     if (far && side != st) {
-        hipEventRecord(fork, st);
-        hipStreamWaitEvent(side, fork, 0);
+        hipError_t e0 = hipEventRecord(fork, st);
+        if (e0 == hipSuccess) e0 = hipStreamWaitEvent(side, fork, 0);
+        if (e0 != hipSuccess) return e0;
         fs = side;
     }
     hipError_t e = hipSuccess;
@@ -299,7 +302,7 @@ hipError_t launch_apply_wide(const ApplyPlan& a, const H2Tree& t, const PanelPla
         for (int lev = 0; lev < t.L; ++lev)
             if ((e = launch_down_level(t, lev, F, R, yh, fs)) != hipSuccess) return e;
     }
-    if (ev) hipEventRecord(ev[1], fs);
+    if (ev) (void)hipEventRecord(ev[1], fs);
     e = panel_f32 ? launch_near_mm(a, pp, (const float*)panel, (parts & 4) != 0, csr_val, F, R, dtype, x, y, st,
                                    ev ? ev[2] : nullptr, ev ? ev[3] : nullptr)
                   : launch_near_mm(a, pp, (const double*)panel, (parts & 4) != 0, csr_val, F, R, dtype, x, y, st,
@@ -307,12 +310,13 @@ hipError_t launch_apply_wide(const ApplyPlan& a, const H2Tree& t, const PanelPla
     if (e != hipSuccess) return e;
     if (far) {
         if (fs != st) {
-            hipEventRecord(join, fs);
-            hipStreamWaitEvent(st, join, 0);
+            hipError_t e1 = hipEventRecord(join, fs);
+            if (e1 == hipSuccess) e1 = hipStreamWaitEvent(st, join, 0);
+            if (e1 != hipSuccess) return e1;
         }
         if ((e = launch_leaf_out(a, t, 8, F, R, nullptr, xt, yh, dtype, y, st, 1)) != hipSuccess) return e;
     }
-    if (ev) hipEventRecord(ev[4], st);
+    if (ev) (void)hipEventRecord(ev[4], st);
     return hipGetLastError();
 }
 
