@@ -613,6 +613,8 @@ def main():
                     help="run only a plain device copy of 256 MiB (calibrates HBM byte counters)")
     ap.add_argument("--build-adjoint", action="store_true",
                     help="run only one build of the headline FP64 operator and one adjoint (kernel traces)")
+    ap.add_argument("--square128-only", action="store_true",
+                    help="run only the one-vector square-128 extra (kernel traces)")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -630,6 +632,9 @@ def main():
         sys.exit(1)
     if args.build_adjoint:
         print(json.dumps(build_and_adjoint()))
+        return
+    if args.square128_only:
+        print(json.dumps(square128(max(100, args.steps), 20)))
         return
 
     P, x, ops, hl = headline(args.steps, args.warmup)
