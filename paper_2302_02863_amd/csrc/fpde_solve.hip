@@ -125,6 +125,7 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
             // stride over the blocks, then a fixed-order tree (same value in every block)
             double pv = 0.0;
             if (col < R)
+#pragma unroll 8
                 for (int64_t b = rl; b < nb_in; b += nrl) pv += part_in[((int64_t)f * nb_in + b) * R + col];
             red[t] = pv;
             __syncthreads();
@@ -138,6 +139,7 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
                 __syncthreads();
                 double pw = 0.0;
                 if (col < R)
+#pragma unroll 8
                     for (int64_t b = rl; b < nb_in; b += nrl) pw += part_in2[((int64_t)f * nb_in + b) * R + col];
                 red[t] = pw;
                 __syncthreads();
@@ -187,6 +189,7 @@ __global__ __launch_bounds__(kBS) void k_rowblock(int64_t N, int R, int64_t rpb,
         double acc1 = 0.0, acc2 = 0.0;
         if (col < R) {
             const double cf = kCoef ? coef[cl] : 0.0;
+#pragma unroll 4   // four rows of loads in flight per thread
             for (int64_t row = r0 + rl; row < r1; row += nrl) {
                 const int64_t i = ((int64_t)f * N + row) * R + col;
                 if (OP == CG_DOT) {
