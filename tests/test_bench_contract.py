@@ -84,3 +84,21 @@ def test_bench_l2_norm_matches_oracle():
     for P in (configs.bump(3), configs.interval(n_int=16, n_ext=4)):
         u = np.random.default_rng(0).standard_normal(P.mesh.n_dofs)
         assert abs(bench.p1_l2_norm(P.mesh, u) - l2_norm(P.mesh, u)) < 1e-13 * l2_norm(P.mesh, u)
+
+
+def test_profile_commands_use_existing_bench_flags():
+    """Every bench.py command quoted in profiles/ (the rocprofv3 summaries and counter
+    records) names only flags bench.py accepts, so each record can be re-run as written."""
+    import re
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    known = set(re.findall(r'add_argument\("(--[a-z0-9-]+)"', src))
+    assert "--steps" in known and "--build-adjoint" in known
+    pdir = os.path.join(ROOT, "profiles")
+    seen = 0
+    for name in sorted(os.listdir(pdir)):
+        text = open(os.path.join(pdir, name)).read().replace("\\\n", " ")
+        for m in re.finditer(r"bench\.py((?:\s+--[a-z0-9-]+(?:\s+[0-9]+)?)*)", text):
+            flags = re.findall(r"--[a-z0-9-]+", m.group(1))
+            seen += 1
+            assert set(flags) <= known, (name, sorted(set(flags) - known))
+    assert seen >= 4
