@@ -459,16 +459,24 @@ void plan(fpde_op& op) {
                     if (dofs[b] < m.N) col[fill[row]++] = (int32_t)op.pos_of_dof[dofs[b]];
             }
         }
+        // rows sorted and made unique in place on host threads, then packed in row order
+        constexpr int64_t kRows = 1024;
+        const int64_t nblk = (m.N + kRows - 1) / kRows;
+        std::vector<int64_t> ulen(m.N);
+        parallel_for(nblk, [&](int64_t blk) {
+            for (int64_t i = blk * kRows; i < std::min(m.N, (blk + 1) * kRows); ++i) {
+                auto b = col.begin() + cnt[i], e = col.begin() + cnt[i + 1];
+                std::sort(b, e);
+                ulen[i] = std::unique(b, e) - b;
+            }
+        });
         op.csr_ptr.assign(m.N + 1, 0);
-        op.csr_col.clear();
-        op.csr_col.reserve(col.size() / 2);
-        for (int64_t i = 0; i < m.N; ++i) {
-            auto b = col.begin() + cnt[i], e = col.begin() + cnt[i + 1];
-            std::sort(b, e);
-            e = std::unique(b, e);
-            op.csr_col.insert(op.csr_col.end(), b, e);
-            op.csr_ptr[i + 1] = (int64_t)op.csr_col.size();
-        }
+        for (int64_t i = 0; i < m.N; ++i) op.csr_ptr[i + 1] = op.csr_ptr[i] + ulen[i];
+        op.csr_col.resize(op.csr_ptr[m.N]);
+        parallel_for(nblk, [&](int64_t blk) {
+            for (int64_t i = blk * kRows; i < std::min(m.N, (blk + 1) * kRows); ++i)
+                std::copy(col.begin() + cnt[i], col.begin() + cnt[i] + ulen[i], op.csr_col.begin() + op.csr_ptr[i]);
+        });
     }
     op.stats.t_plan_ms = ms_since(t0);
 }

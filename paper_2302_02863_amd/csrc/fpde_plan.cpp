@@ -92,36 +92,39 @@ QuadPoints quad_points(const HostMesh& m, const ElementRule& r) {
     Q.x.resize(m.dim * Q.nq);
     Q.w.resize(Q.nq);
     Q.q_int.resize(Q.nq);
-    for (int64_t c = 0; c < m.nc; ++c) {
-        if (m.dim == 1) {
-            double v0 = m.x(0, m.v(0, c));
-            double J = m.x(0, m.v(1, c)) - v0;
-            double det = std::fabs(J);
-            for (int l = 0; l < r.nqe; ++l) {
-                int64_t q = c * r.nqe + l;
-                Q.x[q] = v0 + J * r.xh[l];
-                Q.w[q] = det * r.wh[l];
-                Q.q_int[q] = m.interior[c];
-            }
-        } else {
-            double J[2][2], v0[2];
-            for (int d = 0; d < 2; ++d) {
-                v0[d] = m.x(d, m.v(0, c));
-                J[d][0] = m.x(d, m.v(1, c)) - m.x(d, m.v(0, c));
-                J[d][1] = m.x(d, m.v(2, c)) - m.x(d, m.v(1, c));
-            }
-            double det = std::fabs(J[0][0] * J[1][1] - J[0][1] * J[1][0]);
-            for (int l = 0; l < r.nqe; ++l) {
-                int64_t q = c * r.nqe + l;
-                for (int d = 0; d < 2; ++d) {
-                    double t = v0[d] + J[d][0] * r.xh[l];
-                    Q.x[d * Q.nq + q] = t + J[d][1] * r.xh[r.nqe + l];
+    constexpr int64_t kChunk = 4096;   // cells per task; each cell writes its own points
+    parallel_for((m.nc + kChunk - 1) / kChunk, [&](int64_t ch) {
+        for (int64_t c = ch * kChunk; c < std::min(m.nc, (ch + 1) * kChunk); ++c) {
+            if (m.dim == 1) {
+                double v0 = m.x(0, m.v(0, c));
+                double J = m.x(0, m.v(1, c)) - v0;
+                double det = std::fabs(J);
+                for (int l = 0; l < r.nqe; ++l) {
+                    int64_t q = c * r.nqe + l;
+                    Q.x[q] = v0 + J * r.xh[l];
+                    Q.w[q] = det * r.wh[l];
+                    Q.q_int[q] = m.interior[c];
                 }
-                Q.w[q] = det * r.wh[l];
-                Q.q_int[q] = m.interior[c];
+            } else {
+                double J[2][2], v0[2];
+                for (int d = 0; d < 2; ++d) {
+                    v0[d] = m.x(d, m.v(0, c));
+                    J[d][0] = m.x(d, m.v(1, c)) - m.x(d, m.v(0, c));
+                    J[d][1] = m.x(d, m.v(2, c)) - m.x(d, m.v(1, c));
+                }
+                double det = std::fabs(J[0][0] * J[1][1] - J[0][1] * J[1][0]);
+                for (int l = 0; l < r.nqe; ++l) {
+                    int64_t q = c * r.nqe + l;
+                    for (int d = 0; d < 2; ++d) {
+                        double t = v0[d] + J[d][0] * r.xh[l];
+                        Q.x[d * Q.nq + q] = t + J[d][1] * r.xh[r.nqe + l];
+                    }
+                    Q.w[q] = det * r.wh[l];
+                    Q.q_int[q] = m.interior[c];
+                }
             }
         }
-    }
+    }, 2);
     return Q;
 }
 
@@ -146,10 +149,26 @@ NodeCells node_cells(const HostMesh& m) {
 }
 
 std::vector<Pair> touching_pairs(const HostMesh& m, const NodeCells& ncs) {
+    // chunks of cells on host threads, each chunk's pairs in cell order, then the
+    // chunks concatenated in order: the same list as one pass over the cells
+    constexpr int64_t kChunk = 4096;
+    const int64_t nch = (m.nc + kChunk - 1) / kChunk;
+    std::vector<std::vector<Pair>> part(nch);
+    parallel_for(
+        nch, [&](int64_t ch) { touching_pairs_range(m, ncs, ch * kChunk, std::min(m.nc, (ch + 1) * kChunk), part[ch]); },
+        2);
     std::vector<Pair> out;
+    size_t n = 0;
+    for (auto& v : part) n += v.size();
+    out.reserve(n);
+    for (auto& v : part) out.insert(out.end(), v.begin(), v.end());
+    return out;
+}
+
+void touching_pairs_range(const HostMesh& m, const NodeCells& ncs, int64_t cbeg, int64_t cend, std::vector<Pair>& out) {
     const int k = m.dim + 1;
     std::vector<int64_t> nbr;
-    for (int64_t c = 0; c < m.nc; ++c) {
+    for (int64_t c = cbeg; c < cend; ++c) {
         int32_t vc[3];
         for (int a = 0; a < k; ++a) vc[a] = m.v(a, c);
         if (m.interior[c]) {
@@ -210,7 +229,6 @@ std::vector<Pair> touching_pairs(const HostMesh& m, const NodeCells& ncs) {
             out.push_back(p);
         }
     }
-    return out;
 }
 
 int pair_dofs(const HostMesh& m, const Pair& p, int32_t* o) {

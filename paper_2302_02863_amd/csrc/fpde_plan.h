@@ -57,6 +57,8 @@ struct Pair {
     int32_t v[6];   // canonical vertices: cell0 (3), cell1 (3); 1D: (2),(2)
 };
 std::vector<Pair> touching_pairs(const HostMesh& m, const NodeCells& nc);
+// the pairs whose first cell lies in [cbeg, cend), appended to out in cell order
+void touching_pairs_range(const HostMesh& m, const NodeCells& nc, int64_t cbeg, int64_t cend, std::vector<Pair>& out);
 // local dof list of a pair (global node ids), returns count
 int pair_dofs(const HostMesh& m, const Pair& p, int32_t* out);
 
