@@ -736,12 +736,14 @@ void build_device(fpde_op& op) {
         op.stats.t_singular_ms = tm.stop();
     }
 
+    // point location in the mesh, for the Chebyshev nodes of both trees
+    Locator loc;
+    loc.build(m);
+
     // ---- density rho at every interior quadrature point (Sec. 6.2) and M (Sec. 6.1)
     {
         Timer tm(st);
         const Tree& rt = op.rt;
-        Locator loc;
-        loc.build(m);
         std::vector<double> axes, stw;
         std::vector<int64_t> stn;
         cluster_nodes(op, rt, loc, axes, stn, stw);
@@ -861,8 +863,6 @@ void build_device(fpde_op& op) {
     {
         Timer tm(st);
         const Tree& kt = op.kt;
-        Locator loc;
-        loc.build(m);
         std::vector<double> axes, stw;
         std::vector<int64_t> stn;
         cluster_nodes(op, kt, loc, axes, stn, stw);
