@@ -627,7 +627,7 @@ def main():
                           "launches": args.steps}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+        print(json.dumps({"error": "this library runs on one GPU only; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(1)
     if args.build_adjoint:
