@@ -339,11 +339,29 @@ bool admissible(int dim, const double* lo_a, const double* hi_a, const double* l
 }
 
 void sort_pairs(std::vector<std::pair<int64_t, int64_t>>& v, int64_t ncl) {
-    std::vector<int64_t> ptr(ncl + 1, 0);
-    for (auto& x : v) ++ptr[x.first + 1];
-    for (int64_t c = 0; c < ncl; ++c) ptr[c + 1] += ptr[c];
-    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1), b(v.size());
-    for (auto& x : v) b[fill[x.first]++] = x.second;
+    const int64_t n = (int64_t)v.size();
+    std::vector<int64_t> ptr(ncl + 1, 0), b(n);
+    if (n < (int64_t(1) << 20)) {
+        for (auto& x : v) ++ptr[x.first + 1];
+        for (int64_t c = 0; c < ncl; ++c) ptr[c + 1] += ptr[c];
+        std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+        for (auto& x : v) b[fill[x.first]++] = x.second;
+    } else {
+        // counts and scatter on host threads with atomic counters: the order inside a
+        // bucket then depends on the schedule, and the bucket sort below fixes it again
+        constexpr int64_t kChunk = int64_t(1) << 16;
+        const int64_t nch = (n + kChunk - 1) / kChunk;
+        parallel_for(nch, [&](int64_t ch) {
+            for (int64_t e = ch * kChunk; e < std::min(n, (ch + 1) * kChunk); ++e)
+                __atomic_fetch_add(&ptr[v[e].first + 1], int64_t(1), __ATOMIC_RELAXED);
+        }, 2);
+        for (int64_t c = 0; c < ncl; ++c) ptr[c + 1] += ptr[c];
+        std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+        parallel_for(nch, [&](int64_t ch) {
+            for (int64_t e = ch * kChunk; e < std::min(n, (ch + 1) * kChunk); ++e)
+                b[__atomic_fetch_add(&fill[v[e].first], int64_t(1), __ATOMIC_RELAXED)] = v[e].second;
+        }, 2);
+    }
     parallel_for((ncl + 4095) / 4096, [&](int64_t blk) {
         const int64_t c1 = std::min(ncl, (blk + 1) * 4096);
         for (int64_t c = blk * 4096; c < c1; ++c) {

@@ -78,7 +78,7 @@ bool admissible(int dim, const double* lo_a, const double* hi_a, const double* l
                 const double* hi_b, double eta, double min_dist);
 
 // sorts (a, b) pairs with 0 <= a < ncl by a, then b (a counting sort on a, then
-// each bucket by b)
+// each bucket by b; the result does not depend on the host threads' schedule)
 void sort_pairs(std::vector<std::pair<int64_t, int64_t>>& v, int64_t ncl);
 
 // dual-tree partition; a pair is far only if admissible and its boxes are more than
