@@ -438,27 +438,39 @@ void plan(fpde_op& op) {
     // CSR pattern of B (and M) in tree order: the (row, column) entries of every pair,
     // bucketed by row, then each row's columns sorted and made unique
     {
-        int32_t dofs[5];
+        // counts and fill by chunks of pairs on host threads, each (pair, row) taking its
+        // run of slots with one atomic add; the order inside a row depends on the
+        // schedule until the rows are sorted below
+        constexpr int64_t kPairs = int64_t(1) << 14;
+        const int64_t npair = (int64_t)op.pairs.size(), npch = (npair + kPairs - 1) / kPairs;
         std::vector<int64_t> cnt(m.N + 1, 0);
-        for (const Pair& p : op.pairs) {
-            const int nd = pair_dofs(m, p, dofs);
-            int ni = 0;
-            for (int b = 0; b < nd; ++b) ni += dofs[b] < m.N;
-            for (int a = 0; a < nd; ++a)
-                if (dofs[a] < m.N) cnt[op.pos_of_dof[dofs[a]] + 1] += ni;
-        }
+        parallel_for(npch, [&](int64_t ch) {
+            int32_t dofs[5];
+            for (int64_t e = ch * kPairs; e < std::min(npair, (ch + 1) * kPairs); ++e) {
+                const int nd = pair_dofs(m, op.pairs[e], dofs);
+                int64_t ni = 0;
+                for (int b = 0; b < nd; ++b) ni += dofs[b] < m.N;
+                for (int a = 0; a < nd; ++a)
+                    if (dofs[a] < m.N) __atomic_fetch_add(&cnt[op.pos_of_dof[dofs[a]] + 1], ni, __ATOMIC_RELAXED);
+            }
+        }, 2);
         for (int64_t i = 0; i < m.N; ++i) cnt[i + 1] += cnt[i];
         std::vector<int32_t> col(cnt[m.N]);
         std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-        for (const Pair& p : op.pairs) {
-            const int nd = pair_dofs(m, p, dofs);
-            for (int a = 0; a < nd; ++a) {
-                if (dofs[a] >= m.N) continue;
-                const int64_t row = op.pos_of_dof[dofs[a]];
-                for (int b = 0; b < nd; ++b)
-                    if (dofs[b] < m.N) col[fill[row]++] = (int32_t)op.pos_of_dof[dofs[b]];
+        parallel_for(npch, [&](int64_t ch) {
+            int32_t dofs[5];
+            for (int64_t e = ch * kPairs; e < std::min(npair, (ch + 1) * kPairs); ++e) {
+                const int nd = pair_dofs(m, op.pairs[e], dofs);
+                int64_t ni = 0;
+                for (int b = 0; b < nd; ++b) ni += dofs[b] < m.N;
+                for (int a = 0; a < nd; ++a) {
+                    if (dofs[a] >= m.N) continue;
+                    int64_t at = __atomic_fetch_add(&fill[op.pos_of_dof[dofs[a]]], ni, __ATOMIC_RELAXED);
+                    for (int b = 0; b < nd; ++b)
+                        if (dofs[b] < m.N) col[at++] = (int32_t)op.pos_of_dof[dofs[b]];
+                }
             }
-        }
+        }, 2);
         // rows sorted and made unique in place on host threads, then packed in row order
         constexpr int64_t kRows = 1024;
         const int64_t nblk = (m.N + kRows - 1) / kRows;
