@@ -341,7 +341,7 @@ bool admissible(int dim, const double* lo_a, const double* hi_a, const double* l
 void sort_pairs(std::vector<std::pair<int64_t, int64_t>>& v, int64_t ncl) {
     const int64_t n = (int64_t)v.size();
     std::vector<int64_t> ptr(ncl + 1, 0), b(n);
-    if (n < (int64_t(1) << 20)) {
+    if (n < (int64_t(1) << 14)) {
         for (auto& x : v) ++ptr[x.first + 1];
         for (int64_t c = 0; c < ncl; ++c) ptr[c + 1] += ptr[c];
         std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);

@@ -100,8 +100,9 @@ def test_k_tree_and_partition_match_oracle(fp, case):
     assert gf == set(far) and gn == set(near)
 
 
-# 73,728 quadrature points: the planner splits the tree levels and the partition's
-# subtrees on host threads (at least 65,536 points, a front of 1,024 pairs)
+# 73,728 quadrature points: the planner splits the tree levels, the partition's
+# subtrees and the sort of its pair lists on host threads (at least 65,536 points, a
+# front of 1,024 pairs, 16,384 pairs)
 RHO_CASES = dict(CASES, square_threads=lambda: configs.square(32, 16, leaf_size=16, leaf_size_rho=32))
 
 
@@ -127,10 +128,15 @@ def test_rho_tree_and_partition_match_oracle(fp, case):
     far, near = partition(tree, lo, hi, P.opts["eta"], cluster_h(tree, cell_diameters(m)[Q["cell"]]))
     is_int = m.cell_interior[Q["cell"]] > 0
     has_int = [bool(is_int[tree.members[c]].any()) for c in range(tree.n_clusters)]
-    gf = {tuple(p) for p in op.export("RHO_FAR").reshape(-1, 2)}
-    gn = {tuple(p) for p in op.export("RHO_NEAR").reshape(-1, 2)}
+    ef = op.export("RHO_FAR").reshape(-1, 2)
+    en = op.export("RHO_NEAR").reshape(-1, 2)
+    gf = {tuple(p) for p in ef}
+    gn = {tuple(p) for p in en}
     assert gf == {p for p in far if has_int[p[0]]}
     assert gn == {p for p in near if has_int[p[0]]}
+    for e in (ef, en):   # ordered by target, then source, without repeats (the device lists' order)
+        key = e[:, 0].astype(np.int64) * tree.n_clusters + e[:, 1]
+        assert np.all(np.diff(key) > 0)
     # tree membership: leaves hold the same points
     sizes = np.diff([0] + [tree.members[c].size for c in tree.leaves()]).size
     assert sizes == tree.n_clusters - leaf0
