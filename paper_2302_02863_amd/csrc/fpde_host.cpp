@@ -334,24 +334,56 @@ void cluster_nodes(const fpde_op& op, const Tree& t, const Locator& loc, std::ve
     });
 }
 
-// node -> list of (index, weight), entries sorted by (node, index): a stable counting
-// sort on the node (entries i come in increasing index i / per, and no (node, index)
-// repeats: the nodes of one stencil are distinct)
+// node -> list of (index, weight), entries sorted by (node, index), no (node, index)
+// repeated (the nodes of one stencil are distinct): a counting sort on the node, on host
+// threads with atomic counters for long lists, then each node's entries by index
 void node_csr(int64_t M, const std::vector<int64_t>& st_node, const std::vector<double>& st_w, int per,
               std::vector<int64_t>& ptr, std::vector<int64_t>& idx, std::vector<double>& wts) {
+    const int64_t n = (int64_t)st_node.size();
     ptr.assign(M + 1, 0);
-    for (int64_t v : st_node)
-        if (v >= 0) ptr[v + 1]++;
+    if (n < (int64_t(1) << 20)) {   // entries come in increasing index: a stable pass suffices
+        for (int64_t v : st_node)
+            if (v >= 0) ptr[v + 1]++;
+        for (int64_t i = 0; i < M; ++i) ptr[i + 1] += ptr[i];
+        idx.resize(ptr[M]);
+        wts.resize(ptr[M]);
+        std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t v = st_node[i];
+            if (v < 0) continue;
+            idx[fill[v]] = i / per;
+            wts[fill[v]++] = st_w[i];
+        }
+        return;
+    }
+    constexpr int64_t kChunk = int64_t(1) << 16;
+    const int64_t nch = (n + kChunk - 1) / kChunk;
+    parallel_for(nch, [&](int64_t ch) {
+        for (int64_t i = ch * kChunk; i < std::min(n, (ch + 1) * kChunk); ++i)
+            if (st_node[i] >= 0) __atomic_fetch_add(&ptr[st_node[i] + 1], int64_t(1), __ATOMIC_RELAXED);
+    }, 2);
     for (int64_t i = 0; i < M; ++i) ptr[i + 1] += ptr[i];
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    std::vector<std::pair<int64_t, double>> e(ptr[M]);
+    parallel_for(nch, [&](int64_t ch) {
+        for (int64_t i = ch * kChunk; i < std::min(n, (ch + 1) * kChunk); ++i) {
+            const int64_t v = st_node[i];
+            if (v >= 0) e[__atomic_fetch_add(&fill[v], int64_t(1), __ATOMIC_RELAXED)] = {i / per, st_w[i]};
+        }
+    }, 2);
     idx.resize(ptr[M]);
     wts.resize(ptr[M]);
-    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
-    for (size_t i = 0; i < st_node.size(); ++i) {
-        const int64_t v = st_node[i];
-        if (v < 0) continue;
-        idx[fill[v]] = (int64_t)(i / per);
-        wts[fill[v]++] = st_w[i];
-    }
+    constexpr int64_t kNodes = 4096;
+    parallel_for((M + kNodes - 1) / kNodes, [&](int64_t blk) {
+        for (int64_t v = blk * kNodes; v < std::min(M, (blk + 1) * kNodes); ++v) {
+            std::sort(e.begin() + ptr[v], e.begin() + ptr[v + 1],
+                      [](const std::pair<int64_t, double>& a, const std::pair<int64_t, double>& b) { return a.first < b.first; });
+            for (int64_t q = ptr[v]; q < ptr[v + 1]; ++q) {
+                idx[q] = e[q].first;
+                wts[q] = e[q].second;
+            }
+        }
+    }, 2);
 }
 
 bool symmetric_pairs(std::vector<std::pair<int64_t, int64_t>> v) {
